@@ -1,0 +1,102 @@
+"""Pins for the oracle's semi-Lagrangian transport (Sec. 3)."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import transport
+from oracle.spectral import Grid
+
+
+def _const_velocity(n, vec):
+    return np.stack([np.full((n, n, n), c) for c in vec])
+
+
+def test_zero_velocity_is_the_identity():
+    n = 16
+    g = Grid(n)
+    fields = {k: synthetic.random_field(n, s) for s, k in enumerate("pingwf")}
+    out = transport.advect(g, fields, np.zeros((3, n, n, n)), 0.01)
+    for k in "pingwf":
+        assert np.array_equal(out[k], fields[k])
+
+
+@pytest.mark.parametrize("shift", [(1, 0, 0), (2, -3, 1), (-5, 4, 7)])
+def test_integer_cell_shift_is_exact(shift):
+    n, dt = 16, 0.01
+    g = Grid(n)
+    v = _const_velocity(n, [s * g.h / dt for s in shift])
+    q = synthetic.random_field(n, 3)
+    out = transport.advect(g, {k: q for k in "pingwf"}, v, dt)
+    ref = np.roll(q, shift=(shift[2], shift[1], shift[0]), axis=(0, 1, 2))
+    for k in "pingwf":
+        assert np.max(np.abs(out[k] - ref)) < 1e-13
+
+
+def test_rk2_is_exact_for_constant_velocity():
+    n, dt = 16, 0.01
+    g = Grid(n)
+    vec = (0.37, -1.9, 2.6)
+    X = transport.departure_points(g, _const_velocity(n, vec), dt)
+    base = transport.grid_indices(n)
+    for a in range(3):
+        assert np.max(np.abs(X[a] - (base[a] - dt * vec[a] / g.h))) < 1e-12
+
+
+def test_fractional_shift_error_bound_and_fourth_order():
+    # Cubic Lagrange on nodes -1..2: |err| <= max|f''''| h^4 max|prod(t - t_j)| / 4!
+    # with max over t in [0, 1] of |(t+1) t (t-1) (t-2)| = 9/16.
+    errs = []
+    for n in (16, 32, 64):
+        g = Grid(n)
+        dt = 0.01
+        frac = 0.37
+        v = _const_velocity(n, [frac * g.h / dt, 0.0, 0.0])
+        x3, y3, z3 = g.coords()
+        q = np.sin(x3)
+        out = transport.advect(g, {k: q for k in "pingwf"}, v, dt)["f"]
+        exact = np.sin(x3 - frac * g.h)
+        err = np.max(np.abs(out - exact))
+        bound = g.h ** 4 * (9.0 / 16.0) / 24.0
+        assert err <= bound
+        errs.append(err)
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 3.8)
+
+
+def test_cubic_polynomials_are_reproduced_on_interior_stencils():
+    n = 16
+    q = np.zeros((n, n, n))
+    jz, jy, jx = np.meshgrid(*(np.arange(n, dtype=float),) * 3, indexing="ij")
+    poly = lambda x, y, z: 0.3 * x ** 3 - x * y * z + 2 * y ** 2 - z ** 3 / 7 + 1.5
+    q[...] = poly(jx, jy, jz)
+    rng = np.random.default_rng(5)
+    pts = rng.uniform(2.0, n - 4.0, size=(3, 200))      # stencils stay inside [1, n-2]
+    out = transport.interp(q, pts[0], pts[1], pts[2])
+    assert np.max(np.abs(out - poly(pts[0], pts[1], pts[2]))) < 1e-10
+
+
+def test_interp_hits_nodes_exactly_and_wraps():
+    n = 8
+    q = synthetic.random_field(n, 6)
+    idx = np.array([0.0, 3.0, 7.0, 8.0, -1.0, 15.0])
+    out = transport.interp(q, idx, idx, idx)
+    j = np.mod(idx.astype(int), n)
+    assert np.array_equal(out, q[j, j, j])
+
+
+def test_advection_is_linear_and_conservative_source_vanishes_for_solenoidal_flow():
+    n, dt = 16, 0.02
+    g = Grid(n)
+    v = synthetic.random_field(n, 11, 2.0, ncomp=3) * 3.0
+    a = synthetic.random_field(n, 12, 1.0)
+    b = synthetic.random_field(n, 13, 1.0)
+    oa = transport.advect(g, {k: a for k in "pingwf"}, v, dt)
+    ob = transport.advect(g, {k: b for k in "pingwf"}, v, dt)
+    oab = transport.advect(g, {k: a + 2 * b for k in "pingwf"}, v, dt)
+    assert np.max(np.abs(oab["p"] - oa["p"] - 2 * ob["p"])) < 1e-12
+    # Divergence-free velocity (a curl): conservative and plain transport agree
+    # up to the (round-off) spectral divergence.
+    x3, y3, z3 = g.coords()
+    vs = np.stack([np.sin(y3), np.cos(z3), np.sin(x3)]) * 5.0
+    o = transport.advect(g, {k: a for k in "pingwf"}, vs, dt)
+    assert np.max(np.abs(o["p"] - o["f"])) < 1e-13
