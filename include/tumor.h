@@ -1,0 +1,224 @@
+/*
+ * tumor.h -- C ABI of libtumor, an MI355X (gfx950) implementation of one
+ * operator-split time step of the multispecies glioblastoma model with mass
+ * effect of Subramanian, Gholami & Biros (arXiv 1810.05370).
+ *
+ * Model and discretisation this library implements:
+ *   - species p, i, n (proliferative, invasive, necrotic tumour cells), o
+ *     (oxygen), l (edema), g, w (gray, white matter), f (CSF) on the periodic
+ *     cube [0, 2*pi)^3 with N^3 nodes (Sec. 3, fictitious domain);
+ *   - the PDE system of Eq. e:gog (Sec. 2.3) with the edema equation e:edema
+ *     (Sec. 2.4) and the screened elasticity e:screening with Lame fields
+ *     e:lame (Sec. 2.1);
+ *   - the multispecies splitting of Sec. 3: semi-Lagrangian transport,
+ *     Crank-Nicolson diffusion by preconditioned CG, explicit reaction,
+ *     oxygen and edema updates, coefficient refresh, and the elasticity
+ *     solve by PCG with the constant-Lame spectral preconditioner.
+ *
+ * Conventions for every entry point:
+ *   - Real arrays are FP64, N^3 elements, C order [z][y][x] (x fastest).
+ *     Vector fields are three such blocks (x, y, z components) back to back.
+ *   - Array arguments are DEVICE pointers unless marked "host".  The caller
+ *     owns every pointer it passes; inputs are copied, never retained, except
+ *     the workspace, which must stay valid until tumor_destroy.
+ *   - All work is queued on the HIP stream given to tumor_init.  Each call
+ *     returns after its work has completed (PCG control reads scalars back).
+ *   - Every call returns a tumor_status.  No C++ exception crosses the ABI.
+ *     On a non-OK status, tumor_last_error() returns a message (thread-local).
+ *   - Arguments are validated before any device work: a bad pointer/size/enum
+ *     gives TUMOR_EINVAL and leaves the context unchanged.
+ *   - A context is single-threaded: calls on one context must not overlap.
+ *   - Device memory is never allocated after tumor_init; tumor_init itself
+ *     only carves the caller's workspace (it allocates a few hundred bytes of
+ *     pinned host memory for scalar read-back).
+ */
+#ifndef TUMOR_H
+#define TUMOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TUMOR_ABI_VERSION 1
+
+typedef enum {
+  TUMOR_OK = 0,
+  TUMOR_EINVAL = -1,   /* invalid argument (checked before any device work)     */
+  TUMOR_ENOMEM = -2,   /* workspace smaller than tumor_workspace_bytes reports  */
+  TUMOR_ENOCONV = -3,  /* a PCG solve hit max_it; state holds the last iterate  */
+  TUMOR_EDEVICE = -4,  /* HIP runtime error (no device, launch failure, ...)    */
+  TUMOR_ENAN = -5,     /* a residual norm became NaN/Inf                        */
+  TUMOR_ESTATE = -6    /* call out of order (e.g. adjoint without a record)     */
+} tumor_status;
+
+typedef enum {
+  TUMOR_PREC_FP64 = 0,  /* every kernel in FP64                                  */
+  TUMOR_PREC_MIXED = 1  /* FP32 FFTs, operator applies and interpolation; FP64
+                           species, reaction thresholds, PCG dot products and an
+                           outer FP64 residual correction of every solve         */
+} tumor_precision;
+
+/* Sub-step switches (tumor_config.flags). */
+#define TUMOR_F_ADVECTION  0x1  /* semi-Lagrangian transport (Sec. 3)          */
+#define TUMOR_F_ELASTICITY 0x2  /* mass-effect elasticity solve (Sec. 3)       */
+#define TUMOR_F_EDEMA      0x4  /* edema diffusion + reaction (Sec. 2.4)        */
+#define TUMOR_F_DEFAULT    (TUMOR_F_ADVECTION | TUMOR_F_ELASTICITY | TUMOR_F_EDEMA)
+
+/* Model parameters.  Names follow Table t:setup (Sec. 2.5) and the equations
+ * they enter:
+ *   K      = k_w w + k_g g + k_f f                       (e:diffusion_tensor)
+ *   rho_p  = rho_w w + rho_g g,  rho_i = rho_inv_frac * rho_p
+ *                                                  (e:reaction_op, e:gog_reac_inv_op)
+ *   alpha  = alpha0 H(o_inv - o), beta = beta0 H(sigma_b - p - i) o,
+ *   h      = gamma H(o_hyp - o), o_mit = (o_hyp + o_inv)/2
+ *                                  (e:alpha, e:beta, e:death, e:gog_reac_op)
+ *   oxygen: -delta_p p + delta_s (o_heal - o)(g + w)                    (e:ox)
+ *   edema:  delta_e i/(i + delta_half)(1 - i) - delta_l l             (e:edema)
+ *   eta    = eta_tumor (p+i+n) + eta_healthy (g+w+f)             (e:screening)
+ *   mu, lambda from (E_s, nu_s) of w, g, f and the tumour p+i+n (e:lame),
+ *           both multiplied by lame_scale
+ *   force  b = zeta tanh(p+n) grad(p+n)                   (e:forcingfunction)
+ *   H(x)   = (1 + tanh(x / heaviside_eps)) / 2  (the smoothed Heaviside)
+ */
+typedef struct {
+  double k_w, k_g, k_f;
+  double rho_w, rho_g, rho_inv_frac;
+  double alpha0, beta0, gamma, sigma_b, o_hyp, o_inv, o_heal, delta_s, delta_p;
+  double delta_e, delta_half, delta_l;
+  double eta_tumor, eta_healthy;
+  double E_wm, E_gm, E_csf, E_tumor, nu_wm, nu_gm, nu_csf, nu_tumor;
+  double lame_scale, zeta;
+  double heaviside_eps;
+} tumor_params;
+
+/* Numerical configuration (Table t:numparams: N, dt, Krylov tolerance). */
+typedef struct {
+  int32_t n;            /* grid size per axis: a power of two in [16, 512]     */
+  int32_t precision;    /* tumor_precision                                       */
+  double dt;            /* time step (> 0)                                       */
+  double rtol_diff;     /* CN diffusion PCG relative tolerance, in (0, 1)        */
+  double rtol_elast;    /* elasticity PCG relative tolerance, in (0, 1)          */
+  int32_t max_it;       /* PCG iteration cap per solve (>= 1)                    */
+  int32_t flags;        /* TUMOR_F_* (0 selects TUMOR_F_DEFAULT)                 */
+  int32_t reserved[4];  /* must be zero                                          */
+} tumor_config;
+
+/* Statistics of the last step (or solve). */
+typedef struct {
+  int32_t it_diff[3];        /* CG iterations: invasive cells, oxygen, edema   */
+  int32_t it_elast;          /* elasticity PCG iterations (inner, summed)      */
+  int32_t outer_elast;       /* FP64 outer corrections (mixed precision)       */
+  int32_t outer_diff[3];     /* FP64 outer corrections of the three CN solves  */
+  double relres_diff[3];     /* final relative residuals (FP64)                */
+  double relres_elast;
+  double mass[8];            /* h^3 sum of p, i, n, o, l, g, w, f               */
+  double max_cfl;            /* max |dt v| / h of the velocity that was used    */
+} tumor_step_stats;
+
+typedef struct tumor_ctx tumor_ctx;
+
+/* Field identifiers for tumor_get_field / tumor_set_field. */
+enum {
+  TUMOR_FIELD_P = 0, TUMOR_FIELD_I, TUMOR_FIELD_N, TUMOR_FIELD_O, TUMOR_FIELD_L,
+  TUMOR_FIELD_G, TUMOR_FIELD_W, TUMOR_FIELD_F,
+  TUMOR_FIELD_U = 8,        /* displacement u^n, 3 N^3 values                 */
+  TUMOR_FIELD_UPREV = 9,    /* displacement u^{n-1}, 3 N^3 values             */
+  TUMOR_FIELD_K = 10, TUMOR_FIELD_RHO = 11, TUMOR_FIELD_MU = 12,
+  TUMOR_FIELD_LAMBDA = 13, TUMOR_FIELD_ETA = 14,   /* coefficients, read only */
+  TUMOR_FIELD_COUNT = 15
+};
+
+/* Device workspace size (bytes) a context for `cfg` needs.  Host arguments.
+ * Returns TUMOR_EINVAL for an invalid configuration. */
+int tumor_workspace_bytes(const tumor_config* cfg, size_t* bytes);
+
+/* Create a context and its initial state (Sec. 3 initial conditions, Eq. e:gog):
+ *   g0, w0, f0 <- gm, wm, csf (device, copied);
+ *   p0 = sum_k ic_weights[k] exp(-d(x, c_k)^2 / (2 ic_sigmas[k]^2)), d the
+ *        periodic minimum-image distance, c_k = ic_centers[3k..3k+2] as (x,y,z);
+ *   i0 = n0 = l0 = 0, o0 = o_heal, u^0 = u^-1 = 0; coefficients from q0.
+ * ic_centers, ic_sigmas, ic_weights are HOST arrays of n_ic >= 0 entries.
+ * workspace: device buffer of ws_bytes >= tumor_workspace_bytes(cfg), 256-byte
+ * aligned, owned by the caller, used exclusively by this context.
+ * hip_stream: a hipStream_t (NULL = the null stream). */
+int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm,
+               void* workspace, size_t ws_bytes,
+               const double* wm, const double* gm, const double* csf,
+               int32_t n_ic, const double* ic_centers, const double* ic_sigmas,
+               const double* ic_weights, void* hip_stream);
+
+/* Advance nsteps split steps (Sec. 3, multispecies splitting).  `last` (host,
+ * nullable) receives the statistics of the final step.  TUMOR_ENOCONV: a solve
+ * hit max_it (the step still completed with the last iterate). */
+int tumor_step(tumor_ctx* ctx, int32_t nsteps, tumor_step_stats* last);
+
+/* Solve the screened elasticity system (eta - L) u = -b (the SPD form of
+ * Eq. e:screening) with the context's current coefficients, starting from the
+ * current displacement u^n.  force: 3 N^3 device array b, or NULL to use
+ * b = zeta tanh(p+n) grad(p+n) of the current state.  u_out: 3 N^3 device
+ * output.  iters / relres: host outputs (nullable).  The state is unchanged. */
+int tumor_solve_elasticity(tumor_ctx* ctx, const double* force, double* u_out,
+                           int32_t* iters, double* relres);
+
+/* One step of the discrete adjoint, in reverse order of the recorded forward
+ * steps (requires tumor_record).  adj: device, 14 N^3 values: on input the
+ * adjoint of (p,i,n,o,l,g,w,f,u,u_prev) after step k+1, on output the
+ * adjoint before it.  grad: host, 5 + n_ic doubles, accumulated in place:
+ * d/d(rho, k_w, k_g, k_f, lame_scale, ic_weights[0..n_ic)).  Returns
+ * TUMOR_ESTATE when no recorded step is left. */
+int tumor_adjoint_step(tumor_ctx* ctx, double* adj, double* grad);
+
+/* Start recording the next `nsteps` forward steps for the adjoint, keeping
+ * full checkpoints every `ckpt_every` steps (>= 1) in `tape` (device,
+ * tape_bytes >= tumor_tape_bytes(...)); steps between checkpoints are
+ * recomputed during the reverse sweep. */
+int tumor_tape_bytes(const tumor_config* cfg, int32_t nsteps, int32_t ckpt_every, size_t* bytes);
+int tumor_record(tumor_ctx* ctx, int32_t nsteps, int32_t ckpt_every, void* tape, size_t tape_bytes);
+
+/* Copy a field out of / into the state (device arrays of N^3, or 3 N^3 for
+ * TUMOR_FIELD_U and TUMOR_FIELD_UPREV).  Coefficient fields are read only;
+ * setting a species refreshes nothing (call tumor_refresh afterwards to
+ * recompute the coefficients from the species). */
+int tumor_get_field(tumor_ctx* ctx, int32_t field_id, double* dst);
+int tumor_set_field(tumor_ctx* ctx, int32_t field_id, const double* src);
+int tumor_refresh(tumor_ctx* ctx);
+
+/* Building blocks of the step, exposed for verification.  Device arrays.
+ *   TUMOR_OP_DERIV_X/Y/Z : out = G_a in (spectral derivative, Nyquist dropped)
+ *   TUMOR_OP_DIFFUSION   : out = div(K grad in), K of the current state
+ *   TUMOR_OP_ELASTICITY  : out = (eta - L) in on 3 N^3 arrays
+ *   TUMOR_OP_ELAST_PRECOND: out = constant-Lame inverse of in (3 N^3)
+ *   TUMOR_OP_CN_PRECOND  : out = constant-K CN inverse of in
+ *   TUMOR_OP_FORCE       : out (3 N^3) = zeta tanh(in) grad(in)
+ * In the mixed mode these run in FP32. */
+enum {
+  TUMOR_OP_DERIV_X = 0, TUMOR_OP_DERIV_Y = 1, TUMOR_OP_DERIV_Z = 2,
+  TUMOR_OP_DIFFUSION = 3, TUMOR_OP_ELASTICITY = 4, TUMOR_OP_ELAST_PRECOND = 5,
+  TUMOR_OP_CN_PRECOND = 6, TUMOR_OP_FORCE = 7, TUMOR_OP_COUNT = 8
+};
+int tumor_apply_op(tumor_ctx* ctx, int32_t op, const double* in, double* out);
+
+/* Semi-Lagrangian interpolation: out[k] = tricubic Lagrange interpolant of
+ * the periodic field q at grid-index coordinates (jx[k], jy[k], jz[k]),
+ * k < count (device arrays, count <= N^3). */
+int tumor_interp(tumor_ctx* ctx, const double* q, const double* jx, const double* jy,
+                 const double* jz, int64_t count, double* out);
+
+/* Verification hook for the FP64 precision: run the four solves of the next
+ * step (invasive-cell, oxygen and edema CN solves, elasticity) for exactly
+ * iters[k] PCG iterations each (-1 = stop on the tolerance as usual), so that
+ * two implementations can be compared in iteration lockstep.  iters: host
+ * array of 4 values, or NULL to clear.  TUMOR_EINVAL in the mixed precision. */
+int tumor_force_iterations(tumor_ctx* ctx, const int32_t* iters);
+
+void tumor_destroy(tumor_ctx* ctx);
+const char* tumor_last_error(void);
+int tumor_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TUMOR_H */

@@ -1,0 +1,280 @@
+"""Python binding of libtumor: the MI355X split step of the multispecies
+glioblastoma model with mass effect (Subramanian, Gholami & Biros).
+
+Argument marshalling only.  Every step of the method runs in the HIP kernels
+of ``libtumor.so``; PyTorch supplies device memory (the workspace and field
+tensors) and the stream.  There is no CPU fallback: if the library is not
+built, or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtumor.so")
+
+# tumor_params, in the C struct order (include/tumor.h)
+PARAM_FIELDS = (
+    "k_w", "k_g", "k_f", "rho_w", "rho_g", "rho_inv_frac",
+    "alpha0", "beta0", "gamma", "sigma_b", "o_hyp", "o_inv", "o_heal", "delta_s", "delta_p",
+    "delta_e", "delta_half", "delta_l", "eta_tumor", "eta_healthy",
+    "E_wm", "E_gm", "E_csf", "E_tumor", "nu_wm", "nu_gm", "nu_csf", "nu_tumor",
+    "lame_scale", "zeta", "heaviside_eps",
+)
+
+OK, EINVAL, ENOMEM, ENOCONV, EDEVICE, ENAN, ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "TUMOR_OK", -1: "TUMOR_EINVAL", -2: "TUMOR_ENOMEM", -3: "TUMOR_ENOCONV",
+                -4: "TUMOR_EDEVICE", -5: "TUMOR_ENAN", -6: "TUMOR_ESTATE"}
+PREC = {"fp64": 0, "mixed": 1}
+F_ADVECTION, F_ELASTICITY, F_EDEMA = 0x1, 0x2, 0x4
+F_DEFAULT = F_ADVECTION | F_ELASTICITY | F_EDEMA
+FIELDS = {"p": 0, "i": 1, "n": 2, "o": 3, "l": 4, "g": 5, "w": 6, "f": 7, "u": 8, "u_prev": 9,
+          "K": 10, "rho": 11, "mu": 12, "lambda": 13, "eta": 14}
+OPS = {"deriv_x": 0, "deriv_y": 1, "deriv_z": 2, "diffusion": 3, "elasticity": 4,
+       "elast_precond": 5, "cn_precond": 6, "force": 7}
+VECTOR_OPS = ("elasticity", "elast_precond", "force")
+
+
+class TumorParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in PARAM_FIELDS]
+
+
+class TumorConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("precision", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("rtol_diff", ctypes.c_double), ("rtol_elast", ctypes.c_double),
+                ("max_it", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class TumorStepStats(ctypes.Structure):
+    _fields_ = [("it_diff", ctypes.c_int32 * 3), ("it_elast", ctypes.c_int32),
+                ("outer_elast", ctypes.c_int32), ("outer_diff", ctypes.c_int32 * 3),
+                ("relres_diff", ctypes.c_double * 3), ("relres_elast", ctypes.c_double),
+                ("mass", ctypes.c_double * 8), ("max_cfl", ctypes.c_double)]
+
+    def as_dict(self):
+        return dict(it_diff=list(self.it_diff), it_elast=self.it_elast, outer_elast=self.outer_elast,
+                    outer_diff=list(self.outer_diff), relres_diff=list(self.relres_diff),
+                    relres_elast=self.relres_elast, mass=list(self.mass), max_cfl=self.max_cfl)
+
+
+class TumorError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+P = ctypes.c_void_p
+
+
+def load_library(path: Optional[str] = None):
+    """Load libtumor.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with __graft_entry__.build() "
+                          "(python -m paper_1810_05370_amd._build)")
+    lib = ctypes.CDLL(p)
+    sig = {
+        "tumor_abi_version": (ctypes.c_int, []),
+        "tumor_last_error": (ctypes.c_char_p, []),
+        "tumor_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(TumorConfig), ctypes.POINTER(ctypes.c_size_t)]),
+        "tumor_init": (ctypes.c_int, [ctypes.POINTER(P), ctypes.POINTER(TumorConfig), ctypes.POINTER(TumorParams),
+                                      P, ctypes.c_size_t, P, P, P, ctypes.c_int32, P, P, P, P]),
+        "tumor_step": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(TumorStepStats)]),
+        "tumor_solve_elasticity": (ctypes.c_int, [P, P, P, ctypes.POINTER(ctypes.c_int32),
+                                                  ctypes.POINTER(ctypes.c_double)]),
+        "tumor_adjoint_step": (ctypes.c_int, [P, P, P]),
+        "tumor_tape_bytes": (ctypes.c_int, [ctypes.POINTER(TumorConfig), ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_size_t)]),
+        "tumor_record": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_size_t]),
+        "tumor_get_field": (ctypes.c_int, [P, ctypes.c_int32, P]),
+        "tumor_set_field": (ctypes.c_int, [P, ctypes.c_int32, P]),
+        "tumor_refresh": (ctypes.c_int, [P]),
+        "tumor_apply_op": (ctypes.c_int, [P, ctypes.c_int32, P, P]),
+        "tumor_interp": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, P]),
+        "tumor_force_iterations": (ctypes.c_int, [P, P]),
+        "tumor_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != OK:
+        msg = load_library().tumor_last_error()
+        raise TumorError(code, msg.decode() if msg else "")
+
+
+def make_params(values: dict) -> TumorParams:
+    missing = [k for k in PARAM_FIELDS if k not in values]
+    if missing:
+        raise KeyError(f"missing parameters: {missing}")
+    return TumorParams(*[float(values[k]) for k in PARAM_FIELDS])
+
+
+def make_config(n, precision="fp64", dt=0.01, rtol_diff=1e-8, rtol_elast=1e-8, max_it=1000,
+                flags=F_DEFAULT) -> TumorConfig:
+    return TumorConfig(int(n), PREC[precision], float(dt), float(rtol_diff), float(rtol_elast),
+                       int(max_it), int(flags), (ctypes.c_int32 * 4)(0, 0, 0, 0))
+
+
+def workspace_bytes(cfg: TumorConfig) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().tumor_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host_array(vals):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(vals, dtype=np.float64).ravel())
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Tumor:
+    """One simulation context on the current CUDA/HIP device.
+
+    wm, gm, csf: float64 device tensors of shape (n, n, n), [z][y][x].
+    centers (k, 3) as (x, y, z), sigmas (k,), weights (k,): host arrays.
+    """
+
+    def __init__(self, n, params: dict, wm, gm, csf, centers=(), sigmas=(), weights=(),
+                 precision="fp64", dt=0.01, rtol_diff=1e-8, rtol_elast=1e-8, max_it=1000,
+                 flags=F_DEFAULT, stream=None):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        self.lib = lib
+        self.n = int(n)
+        self.cfg = make_config(n, precision, dt, rtol_diff, rtol_elast, max_it, flags)
+        self.prm = make_params(params)
+        nb = workspace_bytes(self.cfg)
+        dev = wm.device
+        self.device = dev
+        self.workspace = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._ws_ptr = ctypes.c_void_p(base + off)
+        self._ws_bytes = nb
+        for t in (wm, gm, csf):
+            if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != (n, n, n):
+                raise ValueError("tissue maps must be contiguous float64 (n, n, n) device tensors")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        c, cp = _host_array(centers)
+        s, sp = _host_array(sigmas)
+        w, wp = _host_array(weights)
+        nic = s.size
+        if c.size != 3 * nic or w.size != nic:
+            raise ValueError("centers must be (k, 3), sigmas and weights (k,)")
+        ctx = ctypes.c_void_p()
+        torch.cuda.synchronize(dev)
+        code = lib.tumor_init(ctypes.byref(ctx), ctypes.byref(self.cfg), ctypes.byref(self.prm),
+                              self._ws_ptr, nb, _ptr(wm), _ptr(gm), _ptr(csf), nic,
+                              cp if nic else None, sp if nic else None, wp if nic else None,
+                              ctypes.c_void_p(self.stream.cuda_stream))
+        _check(code)
+        self.ctx = ctx
+        self.n_ic = nic
+
+    # -- lifetime ------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.tumor_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- method --------------------------------------------------------
+    def step(self, nsteps=1, allow_noconv=False):
+        st = TumorStepStats()
+        code = self.lib.tumor_step(self.ctx, int(nsteps), ctypes.byref(st))
+        if code == ENOCONV and allow_noconv:
+            return st.as_dict()
+        _check(code)
+        return st.as_dict()
+
+    def solve_elasticity(self, force=None):
+        torch = self._torch
+        n = self.n
+        u = torch.empty((3, n, n, n), dtype=torch.float64, device=self.device)
+        it = ctypes.c_int32(0)
+        rr = ctypes.c_double(0)
+        if force is not None:
+            force = force.contiguous()
+        _check(self.lib.tumor_solve_elasticity(self.ctx, _ptr(force) if force is not None else None,
+                                               _ptr(u), ctypes.byref(it), ctypes.byref(rr)))
+        return u, it.value, rr.value
+
+    def get(self, name):
+        torch = self._torch
+        n = self.n
+        fid = FIELDS[name]
+        shape = (3, n, n, n) if name in ("u", "u_prev") else (n, n, n)
+        out = torch.empty(shape, dtype=torch.float64, device=self.device)
+        _check(self.lib.tumor_get_field(self.ctx, fid, _ptr(out)))
+        return out
+
+    def set(self, name, value):
+        v = value.to(device=self.device, dtype=self._torch.float64).contiguous()
+        _check(self.lib.tumor_set_field(self.ctx, FIELDS[name], _ptr(v)))
+
+    def refresh(self):
+        _check(self.lib.tumor_refresh(self.ctx))
+
+    def apply_op(self, name, x):
+        torch = self._torch
+        n = self.n
+        x = x.to(device=self.device, dtype=torch.float64).contiguous()
+        shape = (3, n, n, n) if name in VECTOR_OPS else (n, n, n)
+        out = torch.empty(shape, dtype=torch.float64, device=self.device)
+        _check(self.lib.tumor_apply_op(self.ctx, OPS[name], _ptr(x), _ptr(out)))
+        return out
+
+    def interp(self, q, jx, jy, jz):
+        torch = self._torch
+        q = q.to(device=self.device, dtype=torch.float64).contiguous()
+        pts = [a.to(device=self.device, dtype=torch.float64).contiguous() for a in (jx, jy, jz)]
+        out = torch.empty(pts[0].shape, dtype=torch.float64, device=self.device)
+        _check(self.lib.tumor_interp(self.ctx, _ptr(q), _ptr(pts[0]), _ptr(pts[1]), _ptr(pts[2]),
+                                     pts[0].numel(), _ptr(out)))
+        return out
+
+    def force_iterations(self, iters=None):
+        if iters is None:
+            _check(self.lib.tumor_force_iterations(self.ctx, None))
+            return
+        arr = (ctypes.c_int32 * 4)(*[int(v) for v in iters])
+        _check(self.lib.tumor_force_iterations(self.ctx, ctypes.cast(arr, ctypes.c_void_p)))
+
+
+def from_inputs(inputs: dict, params: dict, device="cuda", **kw) -> Tumor:
+    """Build a context from a ``synthetic.workload_inputs`` dictionary."""
+    import torch
+    n = inputs["n"]
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
+    return Tumor(n, params, t(inputs["wm"]), t(inputs["gm"]), t(inputs["csf"]),
+                 inputs["centers"], inputs["sigmas"], inputs["weights"], **kw)

@@ -1,0 +1,1211 @@
+// libtumor host engine: workspace layout, operator sequences, PCG control and
+// the C ABI declared in include/tumor.h.
+//
+// State on the device (FP64): species p, i, n, o, l, g, w, f (physical) and
+// the displacements u^n, u^{n-1} in packed spectral form (see passes.hpp).
+// Every Krylov solve runs in spectral space: vectors are spectra, the
+// preconditioners are diagonal (diffusion) or 3x3 per mode (elasticity), and
+// inner products are Parseval-weighted sums, which equal N^3 times the
+// physical inner products, so the iterates are those of the physical-space
+// method.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "passes.hpp"
+#include "tumor.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail : std::runtime_error {
+  int code;
+  Fail(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHECK(expr)                                                                      \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw Fail(TUMOR_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+using tumor::cplx;
+using tumor::ColProg;
+using tumor::ColTerm;
+using tumor::SYM_IW;
+using tumor::SYM_ONE;
+using tumor::SYM_RAW;
+using tumor::XProg;
+
+template <typename R>
+struct PrecBufs {
+  cplx<R>* A[8];
+  cplx<R>* B[8];
+  cplx<R>* x;  // Krylov vectors, 3 blocks of S each
+  cplx<R>* r;
+  cplx<R>* p;
+  cplx<R>* q;
+  void* tw;
+  const R* K;
+  const R* mu;
+  const R* lam;
+  const R* eta;
+};
+
+struct Carver {
+  char* base;
+  size_t off;
+  bool dry;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = dry ? nullptr : reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+bool valid_n(int n) { return n >= 16 && n <= 512 && (n & (n - 1)) == 0; }
+
+int check_cfg(const tumor_config* c) {
+  if (!c) return TUMOR_EINVAL;
+  if (!valid_n(c->n)) return TUMOR_EINVAL;
+  if (c->precision != TUMOR_PREC_FP64 && c->precision != TUMOR_PREC_MIXED) return TUMOR_EINVAL;
+  if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return TUMOR_EINVAL;
+  if (!(c->rtol_diff > 0.0 && c->rtol_diff < 1.0)) return TUMOR_EINVAL;
+  if (!(c->rtol_elast > 0.0 && c->rtol_elast < 1.0)) return TUMOR_EINVAL;
+  if (c->max_it < 1) return TUMOR_EINVAL;
+  if (c->flags & ~TUMOR_F_DEFAULT) return TUMOR_EINVAL;
+  for (int k = 0; k < 4; ++k)
+    if (c->reserved[k] != 0) return TUMOR_EINVAL;
+  return TUMOR_OK;
+}
+
+}  // namespace
+
+struct tumor_ctx {
+  tumor_config cfg;
+  tumor_params prm;
+  hipStream_t st;
+  int n;
+  long long V, S;
+  bool mixed;
+  int flags;
+  double* F[8];
+  double* G[8];
+  cplx<double>* U;
+  cplx<double>* Up;
+  cplx<double>* Un;
+  double *K, *rho, *mu, *lam, *eta;
+  float *K32, *mu32, *lam32, *eta32;
+  double* vel[4];
+  cplx<double>* b64;
+  PrecBufs<double> p64;
+  PrecBufs<float> p32;
+  tumor::SolveScalars* sv64;
+  tumor::SolveScalars* sv32;
+  tumor::CoefScalars* cs;
+  double* partials;
+  // host side
+  tumor::SolveScalars* hsv;
+  tumor::CoefScalars* hcs;
+  int pred[4];
+  int forced[4];
+  bool has_forced;
+  tumor::RefreshConsts fc;
+  tumor::ReactConsts rc;
+};
+
+namespace {
+
+using Ctx = tumor_ctx;
+
+void layout(Ctx& c, Carver& cv) {
+  const long long V = c.V, S = c.S;
+  for (int k = 0; k < 8; ++k) c.F[k] = cv.take<double>(V);
+  for (int k = 0; k < 8; ++k) c.G[k] = cv.take<double>(V);
+  c.U = cv.take<cplx<double>>(3 * S);
+  c.Up = cv.take<cplx<double>>(3 * S);
+  c.Un = cv.take<cplx<double>>(3 * S);
+  c.K = cv.take<double>(V);
+  c.rho = cv.take<double>(V);
+  c.mu = cv.take<double>(V);
+  c.lam = cv.take<double>(V);
+  c.eta = cv.take<double>(V);
+  for (int k = 0; k < 4; ++k) c.vel[k] = cv.take<double>(V);
+  c.b64 = cv.take<cplx<double>>(3 * S);
+  for (int k = 0; k < 8; ++k) c.p64.A[k] = cv.take<cplx<double>>(S);
+  for (int k = 0; k < 8; ++k) c.p64.B[k] = cv.take<cplx<double>>(S);
+  c.p64.x = nullptr;  // the elasticity solve iterates directly in Un
+  c.p64.r = cv.take<cplx<double>>(3 * S);
+  c.p64.p = cv.take<cplx<double>>(3 * S);
+  c.p64.q = cv.take<cplx<double>>(3 * S);
+  c.p64.tw = cv.take<cplx<double>>(c.n);
+  c.p64.K = c.K;
+  c.p64.mu = c.mu;
+  c.p64.lam = c.lam;
+  c.p64.eta = c.eta;
+  c.K32 = c.mu32 = c.lam32 = c.eta32 = nullptr;
+  if (c.mixed) {
+    c.K32 = cv.take<float>(V);
+    c.mu32 = cv.take<float>(V);
+    c.lam32 = cv.take<float>(V);
+    c.eta32 = cv.take<float>(V);
+    for (int k = 0; k < 8; ++k) c.p32.A[k] = cv.take<cplx<float>>(S);
+    for (int k = 0; k < 8; ++k) c.p32.B[k] = cv.take<cplx<float>>(S);
+    c.p32.x = cv.take<cplx<float>>(3 * S);
+    c.p32.r = cv.take<cplx<float>>(3 * S);
+    c.p32.p = cv.take<cplx<float>>(3 * S);
+    c.p32.q = cv.take<cplx<float>>(3 * S);
+  } else {
+    std::memset(&c.p32, 0, sizeof(c.p32));
+  }
+  c.p32.tw = cv.take<cplx<float>>(c.n);
+  c.p32.K = c.K32;
+  c.p32.mu = c.mu32;
+  c.p32.lam = c.lam32;
+  c.p32.eta = c.eta32;
+  c.sv64 = cv.take<tumor::SolveScalars>(1);
+  c.sv32 = cv.take<tumor::SolveScalars>(1);
+  c.cs = cv.take<tumor::CoefScalars>(1);
+  c.partials = cv.take<double>((size_t)tumor::kRedBlocksMax * tumor::kPartialsPerBlock);
+}
+
+size_t workspace_size(const tumor_config& cfg) {
+  Ctx c;
+  std::memset(&c, 0, sizeof(c));
+  c.n = cfg.n;
+  c.V = (long long)cfg.n * cfg.n * cfg.n;
+  c.S = c.V / 2;
+  c.mixed = cfg.precision == TUMOR_PREC_MIXED;
+  Carver cv{nullptr, 0, true};
+  layout(c, cv);
+  return (cv.off + 255) & ~size_t(255);
+}
+
+template <typename R>
+PrecBufs<R>& pb(Ctx& c);
+template <>
+PrecBufs<double>& pb<double>(Ctx& c) { return c.p64; }
+template <>
+PrecBufs<float>& pb<float>(Ctx& c) { return c.p32; }
+
+// ---------------------------------------------------------- program helpers
+struct Prog {
+  ColProg p;
+  Prog() {
+    std::memset(&p, 0, sizeof(p));
+  }
+  Prog& in(int k, const void* ptr) {
+    p.in[k] = ptr;
+    return *this;
+  }
+  Prog& out(void* dst, std::initializer_list<ColTerm> terms) {
+    const int o = p.nout++;
+    p.out[o] = dst;
+    int q = 0;
+    for (const ColTerm& t : terms) p.term[o][q++] = t;
+    p.nterm[o] = q;
+    return *this;
+  }
+  Prog& skip(const int* s) {
+    p.skip = s;
+    return *this;
+  }
+};
+
+XProg to_x(const ColProg& p, double scale) {
+  XProg x;
+  std::memset(&x, 0, sizeof(x));
+  for (int k = 0; k < tumor::kMaxCol; ++k) {
+    x.in[k] = p.in[k];
+    x.out[k] = p.out[k];
+    x.nterm[k] = p.nterm[k];
+    for (int q = 0; q < tumor::kMaxTerms; ++q) x.term[k][q] = p.term[k][q];
+  }
+  x.nout = p.nout;
+  x.scale = scale;
+  x.skip = p.skip;
+  return x;
+}
+
+constexpr ColTerm T1(int s, double c = 1.0) { return ColTerm{s, SYM_ONE, c}; }
+constexpr ColTerm TW(int s, double c = 1.0) { return ColTerm{s, SYM_IW, c}; }
+constexpr ColTerm TR(int s, double c = 1.0) { return ColTerm{s, SYM_RAW, c}; }
+
+template <typename R>
+void colp(Ctx& c, int axis, bool inv, const Prog& pr) {
+  tumor::launch_col_pass<R>(c.n, axis, inv, pr.p, pb<R>(c).tw, c.st);
+}
+
+// Forward 3-D transform of coef_a * a (+ coef_b * b), physical FP64 -> spectral R.
+template <typename R>
+void fwd3(Ctx& c, const double* a, const double* b, cplx<R>* out, double ca = 1.0, double cb = 1.0) {
+  PrecBufs<R>& P = pb<R>(c);
+  Prog x;
+  x.in(0, a).in(1, b);
+  if (b) x.out(P.A[0], {T1(0, ca), T1(1, cb)});
+  else x.out(P.A[0], {T1(0, ca)});
+  tumor::launch_xfwd<R>(c.n, to_x(x.p, 1.0), P.tw, c.st, true);
+  colp<R>(c, 1, false, Prog().in(0, P.A[0]).out(P.B[0], {T1(0)}));
+  colp<R>(c, 2, false, Prog().in(0, P.B[0]).out(out, {T1(0)}));
+}
+
+// Inverse 3-D transform (spectral R -> physical R) with an optional derivative
+// along axis d (0, 1, 2 = x, y, z; -1 = none) and a scale.
+template <typename R>
+void inv3(Ctx& c, const cplx<R>* in, R* out, double scale, int d = -1) {
+  PrecBufs<R>& P = pb<R>(c);
+  colp<R>(c, 2, true, Prog().in(0, in).out(P.A[0], {d == 2 ? TW(0) : T1(0)}));
+  colp<R>(c, 1, true, Prog().in(0, P.A[0]).out(P.B[0], {d == 1 ? TW(0) : T1(0)}));
+  Prog x;
+  x.in(0, P.B[0]).out(out, {d == 0 ? TW(0) : T1(0)});
+  tumor::launch_xinv<R>(c.n, to_x(x.p, scale), P.tw, c.st);
+}
+
+// out = raw * in + dcoef * D in (spectral), D c = div(K grad c).
+template <typename R>
+void diff_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, double raw, double dcoef, const int* skip) {
+  PrecBufs<R>& P = pb<R>(c);
+  colp<R>(c, 2, true, Prog().in(0, in).out(P.A[0], {T1(0)}).out(P.A[1], {TW(0)}).skip(skip));
+  colp<R>(c, 1, true,
+          Prog().in(0, P.A[0]).in(1, P.A[1]).out(P.B[0], {T1(0)}).out(P.B[1], {TW(0)}).out(P.B[2], {T1(1)}).skip(
+              skip));
+  tumor::XDiffArgs xa;
+  xa.in[0] = P.B[0];
+  xa.in[1] = P.B[1];
+  xa.in[2] = P.B[2];
+  xa.out[0] = P.A[0];
+  xa.out[1] = P.A[1];
+  xa.out[2] = P.A[2];
+  xa.K = P.K;
+  xa.skip = skip;
+  tumor::launch_xdiff<R>(c.n, xa, P.tw, c.st);
+  colp<R>(c, 1, false,
+          Prog().in(0, P.A[0]).in(1, P.A[1]).in(2, P.A[2]).out(P.B[0], {T1(0), TW(1)}).out(P.B[1], {T1(2)}).skip(skip));
+  Prog z;
+  z.in(0, P.B[0]).in(1, P.B[1]).in(2, in).skip(skip);
+  if (raw != 0.0) z.out(out, {TR(2, raw), T1(0, dcoef), TW(1, dcoef)});
+  else z.out(out, {T1(0, dcoef), TW(1, dcoef)});
+  colp<R>(c, 2, false, z);
+}
+
+// out = (eta - L) in on 3-component spectra.
+template <typename R>
+void elast_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, const int* skip) {
+  PrecBufs<R>& P = pb<R>(c);
+  const long long S = c.S;
+  auto** A = P.A;
+  auto** B = P.B;
+  colp<R>(c, 2, true,
+          Prog()
+              .in(0, in)
+              .in(1, in + S)
+              .in(2, in + 2 * S)
+              .out(A[0], {T1(0)})
+              .out(A[1], {T1(1)})
+              .out(A[2], {T1(2)})
+              .out(A[3], {TW(0)})
+              .out(A[4], {TW(1)})
+              .out(A[5], {TW(2)})
+              .skip(skip));
+  Prog y;
+  for (int k = 0; k < 6; ++k) y.in(k, A[k]);
+  y.out(B[0], {T1(0)})
+      .out(B[1], {T1(1)})
+      .out(B[2], {T1(2)})
+      .out(B[3], {TW(0)})
+      .out(B[4], {TW(1)})
+      .out(B[5], {T1(4), TW(2)})
+      .out(B[6], {T1(3)})
+      .out(B[7], {T1(5)})
+      .skip(skip);
+  colp<R>(c, 1, true, y);
+  tumor::XElastArgs xa;
+  for (int k = 0; k < 8; ++k) {
+    xa.in[k] = B[k];
+    xa.out[k] = A[k];
+  }
+  xa.mu = P.mu;
+  xa.lam = P.lam;
+  xa.eta = P.eta;
+  xa.skip = skip;
+  tumor::launch_xelast<R>(c.n, xa, P.tw, c.st);
+  Prog yf;
+  for (int k = 0; k < 8; ++k) yf.in(k, A[k]);
+  yf.out(B[0], {T1(0), TW(3, -1.0)})
+      .out(B[1], {T1(1), TW(4, -1.0)})
+      .out(B[2], {T1(2), TW(5, -1.0)})
+      .out(B[3], {T1(6)})
+      .out(B[4], {T1(5)})
+      .out(B[5], {T1(7)})
+      .skip(skip);
+  colp<R>(c, 1, false, yf);
+  Prog zf;
+  for (int k = 0; k < 6; ++k) zf.in(k, B[k]);
+  zf.out(out, {T1(0), TW(3, -1.0)})
+      .out(out + S, {T1(1), TW(4, -1.0)})
+      .out(out + 2 * S, {T1(2), TW(5, -1.0)})
+      .skip(skip);
+  colp<R>(c, 2, false, zf);
+}
+
+// Spectral right-hand side -b of the elasticity system from tau (physical),
+// b = zeta tanh(tau) grad(tau)  (e:forcingfunction).  Written to out (3 S).
+void force_rhs(Ctx& c, const double* pa, const double* pbp, cplx<double>* out) {
+  PrecBufs<double>& P = c.p64;
+  auto** A = P.A;
+  auto** B = P.B;
+  fwd3<double>(c, pa, pbp, A[1]);
+  colp<double>(c, 2, true, Prog().in(0, A[1]).out(B[0], {T1(0)}).out(B[1], {TW(0)}));
+  colp<double>(c, 1, true, Prog().in(0, B[0]).in(1, B[1]).out(A[0], {T1(0)}).out(A[1], {TW(0)}).out(A[2], {T1(1)}));
+  tumor::XForceArgs xa;
+  xa.in[0] = A[0];
+  xa.in[1] = A[1];
+  xa.in[2] = A[2];
+  xa.out[0] = B[0];
+  xa.out[1] = B[1];
+  xa.out[2] = B[2];
+  xa.zeta = c.prm.zeta;
+  tumor::launch_xforce<double>(c.n, xa, P.tw, c.st);
+  colp<double>(c, 1, false,
+               Prog().in(0, B[0]).in(1, B[1]).in(2, B[2]).out(A[0], {T1(0)}).out(A[1], {T1(1)}).out(A[2], {T1(2)}));
+  colp<double>(c, 2, false,
+               Prog()
+                   .in(0, A[0])
+                   .in(1, A[1])
+                   .in(2, A[2])
+                   .out(out, {T1(0)})
+                   .out(out + c.S, {T1(1)})
+                   .out(out + 2 * c.S, {T1(2)}));
+}
+
+// Velocity v = (u^n - u^{n-1}) / dt and its divergence, physical FP64.
+void velocity(Ctx& c) {
+  PrecBufs<double>& P = c.p64;
+  auto** A = P.A;
+  auto** B = P.B;
+  const long long S = c.S;
+  const double idt = 1.0 / c.cfg.dt;
+  Prog z;
+  for (int k = 0; k < 3; ++k) z.in(k, c.U + k * S).in(3 + k, c.Up + k * S);
+  z.out(A[0], {T1(0, idt), T1(3, -idt)})
+      .out(A[1], {T1(1, idt), T1(4, -idt)})
+      .out(A[2], {T1(2, idt), T1(5, -idt)})
+      .out(A[3], {TW(2, idt), TW(5, -idt)});
+  colp<double>(c, 2, true, z);
+  colp<double>(c, 1, true,
+               Prog()
+                   .in(0, A[0])
+                   .in(1, A[1])
+                   .in(2, A[2])
+                   .in(3, A[3])
+                   .out(B[0], {T1(0)})
+                   .out(B[1], {T1(1)})
+                   .out(B[2], {T1(2)})
+                   .out(B[3], {T1(3), TW(1)}));
+  Prog x;
+  x.in(0, B[0]).in(1, B[1]).in(2, B[2]).in(3, B[3]);
+  x.out(c.vel[0], {T1(0)}).out(c.vel[1], {T1(1)}).out(c.vel[2], {T1(2)}).out(c.vel[3], {TW(0), T1(3)});
+  tumor::launch_xinv<double>(c.n, to_x(x.p, 1.0 / (double)c.V), P.tw, c.st);
+}
+
+// ---------------------------------------------------------------- PCG control
+void readback(Ctx& c, tumor::SolveScalars* dev) {
+  HIPCHECK(hipMemcpyAsync(c.hsv, dev, sizeof(tumor::SolveScalars), hipMemcpyDeviceToHost, c.st));
+  HIPCHECK(hipStreamSynchronize(c.st));
+}
+
+struct SolveOut {
+  int it = 0;
+  int outer = 0;
+  double relres = 0.0;
+  bool conv = true;
+  bool bad = false;
+};
+
+template <typename R>
+tumor::KrylovArgs kargs(Ctx& c, int ncomp, cplx<R>* x, tumor::SolveScalars* sv, double h, int kind) {
+  PrecBufs<R>& P = pb<R>(c);
+  tumor::KrylovArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = x;
+  a.r = P.r;
+  a.p = P.p;
+  a.q = P.q;
+  a.b = nullptr;
+  a.ax = nullptr;
+  a.cs = c.cs;
+  a.sv = sv;
+  a.partials = c.partials;
+  a.n = c.n;
+  a.ncomp = ncomp;
+  a.pc.h = h;
+  a.pc.kind = kind;
+  a.pc.singular = (kind == tumor::PREC_ELAST && c.prm.eta_tumor == 0.0 && c.prm.eta_healthy == 0.0) ? 1 : 0;
+  return a;
+}
+
+// Plain PCG iterations after the residual r and its norms are in place.
+// `apply(p, q, skip)` computes q = A p.  Returns iterations taken.
+template <typename R, typename Apply>
+int pcg_iterate(Ctx& c, tumor::KrylovArgs a, Apply apply, double thr2, int limit, bool fixed, int pred,
+                bool& conv, bool& bad) {
+  a.thr2 = thr2;
+  a.limit = limit;
+  a.fixed = fixed ? 1 : 0;
+  tumor::launch_pcg_start<R>(a, 0, c.st);
+  int launched = 0;
+  int chunk = std::max(1, std::min(limit, pred + 2));
+  tumor::SolveScalars* sv = a.sv;
+  const int* skip = &sv->done;
+  for (;;) {
+    for (int k = 0; k < chunk && launched < limit; ++k, ++launched) {
+      apply(static_cast<const cplx<R>*>(a.p), static_cast<cplx<R>*>(a.q), skip);
+      tumor::launch_pcg_pq<R>(a, c.st);
+      tumor::launch_pcg_update<R>(a, c.st);
+      tumor::launch_pcg_pupdate<R>(a, c.st);
+    }
+    HIPCHECK(hipGetLastError());
+    readback(c, sv);
+    if (c.hsv->done || launched >= limit) break;
+    chunk = 4;
+  }
+  conv = c.hsv->conv != 0;
+  bad = c.hsv->bad != 0;
+  return c.hsv->it;
+}
+
+// Solve A x = b for a spectral system.  On entry x holds x0 and `resid0`
+// computes r = b - A x0 (and b, norms) into the FP64 vectors.  For the mixed
+// precision the FP32 inner PCG corrects x in FP64 outer iterations.
+template <typename Apply64, typename Apply32, typename Resid64>
+SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cplx<double>* bvec, double rtol,
+                      int which, Apply64 A64, Apply32 A32, Resid64 resid0) {
+  SolveOut so;
+  tumor::KrylovArgs a = kargs<double>(c, ncomp, x, c.sv64, h, kind);
+  a.b = bvec;
+  resid0(a);
+  readback(c, c.sv64);
+  const double bb = c.hsv->bb;
+  double rr = c.hsv->rr;
+  if (c.hsv->bad) {
+    so.bad = true;
+    so.conv = false;
+    return so;
+  }
+  const long long cnt = 2LL * ncomp * c.S;  // reals
+  if (bb == 0.0) {
+    HIPCHECK(hipMemsetAsync(x, 0, cnt * sizeof(double), c.st));
+    return so;
+  }
+  const double thr2 = rtol * rtol * bb;
+  int forced = -1;
+  if (c.has_forced && which >= 0) forced = c.forced[which];
+  if (forced < 0 && rr <= thr2) {
+    so.relres = std::sqrt(rr / bb);
+    return so;
+  }
+  const int pred = c.pred[which >= 0 ? which : 3];
+  if (!c.mixed) {
+    bool conv = true, bad = false;
+    const bool fixed = forced >= 0;
+    const int limit = fixed ? forced : c.cfg.max_it;
+    if (limit > 0) so.it = pcg_iterate<double>(c, a, A64, thr2, limit, fixed, pred, conv, bad);
+    so.conv = conv;
+    so.bad = bad;
+    so.relres = std::sqrt(c.hsv->rr / bb);
+    if (which >= 0) c.pred[which] = std::max(1, so.it);
+    return so;
+  }
+  // Mixed precision: x64 += PCG32(b - A64 x64) until the FP64 residual meets rtol.
+  PrecBufs<float>& P = c.p32;
+  tumor::KrylovArgs a32 = kargs<float>(c, ncomp, P.x, c.sv32, h, kind);
+  // r32 = float(r64): rerun the residual kernel on r64 with no subtraction.
+  tumor::KrylovArgs conv_args = a;
+  conv_args.b = a.r;
+  conv_args.ax = nullptr;
+  const int max_outer = 30;
+  int total = 0;
+  while (so.outer < max_outer) {
+    tumor::launch_residual<double>(conv_args, P.r, c.st);
+    const double need = rtol * std::sqrt(bb / rr);
+    const double in_rtol = std::max(1e-4, 0.3 * need);
+    bool conv = true, bad = false;
+    int inner_it = 0;
+    // inner solve with x32 = 0, r32 from above; threshold relative to ||r32||
+    tumor::KrylovArgs ai = a32;
+    ai.x = P.x;
+    const double thr_in = in_rtol * in_rtol * rr;
+    // pcg_start with zero_x = 1
+    ai.thr2 = thr_in;
+    ai.limit = c.cfg.max_it;
+    ai.fixed = 0;
+    tumor::launch_pcg_start<float>(ai, 1, c.st);
+    {
+      int launched = 0;
+      int chunk = std::max(1, (c.pred[which >= 0 ? which : 3] + 2) / 2 + 1);
+      const int* skip = &c.sv32->done;
+      for (;;) {
+        for (int k = 0; k < chunk && launched < ai.limit; ++k, ++launched) {
+          A32(P.p, P.q, skip);
+          tumor::launch_pcg_pq<float>(ai, c.st);
+          tumor::launch_pcg_update<float>(ai, c.st);
+          tumor::launch_pcg_pupdate<float>(ai, c.st);
+        }
+        HIPCHECK(hipGetLastError());
+        readback(c, c.sv32);
+        if (c.hsv->done || launched >= ai.limit) break;
+        chunk = 4;
+      }
+      conv = c.hsv->conv != 0;
+      bad = c.hsv->bad != 0;
+      inner_it = c.hsv->it;
+      total += inner_it;
+    }
+    so.outer++;
+    if (bad) {
+      so.bad = true;
+      so.conv = false;
+      break;
+    }
+    tumor::launch_add32to64(x, P.x, cnt, c.st);
+    // r64 = b - A64 x64
+    A64(x, c.p64.q, nullptr);
+    tumor::KrylovArgs ar = a;
+    ar.b = bvec;
+    ar.ax = c.p64.q;
+    tumor::launch_residual<double>(ar, nullptr, c.st);
+    readback(c, c.sv64);
+    rr = c.hsv->rr;
+    if (c.hsv->bad) {
+      so.bad = true;
+      so.conv = false;
+      break;
+    }
+    if (rr <= thr2) break;
+    if (!conv && inner_it >= c.cfg.max_it) break;
+  }
+  so.it = total;
+  so.relres = std::sqrt(rr / bb);
+  so.conv = rr <= thr2;
+  if (which >= 0) c.pred[which] = std::max(1, total / std::max(1, so.outer));
+  return so;
+}
+
+// Crank-Nicolson diffusion of the physical field src into dst (may alias).
+SolveOut cn_solve(Ctx& c, const double* src, double* dst, int which) {
+  const double h = 0.5 * c.cfg.dt;
+  cplx<double>* x = c.Un;  // free between elasticity solves
+  cplx<double>* b = c.b64;
+  fwd3<double>(c, src, nullptr, x);
+  auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip) { diff_apply<double>(c, p, q, 1.0, -h, skip); };
+  auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip) { diff_apply<float>(c, p, q, 1.0, -h, skip); };
+  auto r0 = [&](tumor::KrylovArgs& a) {
+    diff_apply<double>(c, x, c.p64.q, 0.0, 1.0, nullptr);
+    tumor::launch_cn_residual<double>(a, x, c.p64.q, c.st);
+  };
+  SolveOut so = solve_system(c, 1, tumor::PREC_DIFF, h, x, b, c.cfg.rtol_diff, which, A64, A32, r0);
+  inv3<double>(c, x, dst, 1.0 / (double)c.V);
+  return so;
+}
+
+// Elasticity solve (eta - L) u = rhs, rhs spectral in b64, warm start from U.
+SolveOut elast_solve(Ctx& c, cplx<double>* x, int which) {
+  HIPCHECK(hipMemcpyAsync(x, c.U, 3 * c.S * sizeof(cplx<double>), hipMemcpyDeviceToDevice, c.st));
+  auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip) { elast_apply<double>(c, p, q, skip); };
+  auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip) { elast_apply<float>(c, p, q, skip); };
+  auto r0 = [&](tumor::KrylovArgs& a) {
+    elast_apply<double>(c, x, c.p64.q, nullptr);
+    a.ax = c.p64.q;
+    tumor::launch_residual<double>(a, nullptr, c.st);
+    a.ax = nullptr;
+  };
+  return solve_system(c, 3, tumor::PREC_ELAST, 0.0, x, c.b64, c.cfg.rtol_elast, which, A64, A32, r0);
+}
+
+void refresh(Ctx& c, int do_reaction, const double* const* in, double* const* out) {
+  tumor::ReactArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.p = in[0];
+  a.i_dag = in[1];
+  a.i_dd = in[2];
+  a.n = in[3];
+  a.g = in[4];
+  a.w = in[5];
+  a.o = in[6];
+  a.l = in[7];
+  a.f = in[8];
+  a.po = out[0];
+  a.io = out[1];
+  a.no = out[2];
+  a.go = out[3];
+  a.wo = out[4];
+  a.oo = out[5];
+  a.lo = out[6];
+  a.fo = out[7];
+  a.K = c.K;
+  a.rho = c.rho;
+  a.mu = c.mu;
+  a.lam = c.lam;
+  a.eta = c.eta;
+  a.K32 = c.K32;
+  a.mu32 = c.mu32;
+  a.lam32 = c.lam32;
+  a.eta32 = c.eta32;
+  a.cs = c.cs;
+  a.partials = c.partials;
+  a.V = c.V;
+  a.do_reaction = do_reaction;
+  a.rc = c.rc;
+  a.fc = c.fc;
+  tumor::launch_react(a, c.st);
+}
+
+void refresh_state(Ctx& c) {
+  enum { P, I, N, O, L, G, W, F };
+  const double* in[9] = {c.F[P], c.F[I], c.F[I], c.F[N], c.F[G], c.F[W], c.F[O], c.F[L], c.F[F]};
+  double* out[8] = {nullptr};
+  refresh(c, 0, in, out);
+}
+
+void set_consts(Ctx& c) {
+  const tumor_params& p = c.prm;
+  auto mu_of = [](double E, double nu) { return E / (2.0 * (1.0 + nu)); };
+  auto la_of = [](double E, double nu) { return nu * E / ((1.0 - 2.0 * nu) * (1.0 + nu)); };
+  const double s = p.lame_scale;
+  c.fc.k_w = p.k_w;
+  c.fc.k_g = p.k_g;
+  c.fc.k_f = p.k_f;
+  c.fc.rho_w = p.rho_w;
+  c.fc.rho_g = p.rho_g;
+  c.fc.mu_w = s * mu_of(p.E_wm, p.nu_wm);
+  c.fc.mu_g = s * mu_of(p.E_gm, p.nu_gm);
+  c.fc.mu_f = s * mu_of(p.E_csf, p.nu_csf);
+  c.fc.mu_t = s * mu_of(p.E_tumor, p.nu_tumor);
+  c.fc.la_w = s * la_of(p.E_wm, p.nu_wm);
+  c.fc.la_g = s * la_of(p.E_gm, p.nu_gm);
+  c.fc.la_f = s * la_of(p.E_csf, p.nu_csf);
+  c.fc.la_t = s * la_of(p.E_tumor, p.nu_tumor);
+  c.fc.eta_t = p.eta_tumor;
+  c.fc.eta_h = p.eta_healthy;
+  c.rc.dt = c.cfg.dt;
+  c.rc.alpha0 = p.alpha0;
+  c.rc.beta0 = p.beta0;
+  c.rc.gamma = p.gamma;
+  c.rc.sigma_b = p.sigma_b;
+  c.rc.o_hyp = p.o_hyp;
+  c.rc.o_inv = p.o_inv;
+  c.rc.o_mit = 0.5 * (p.o_hyp + p.o_inv);
+  c.rc.o_heal = p.o_heal;
+  c.rc.delta_s = p.delta_s;
+  c.rc.delta_p = p.delta_p;
+  c.rc.delta_e = p.delta_e;
+  c.rc.delta_half = p.delta_half;
+  c.rc.delta_l = p.delta_l;
+  c.rc.eps = p.heaviside_eps;
+  c.rc.rho_inv_frac = p.rho_inv_frac;
+  c.rc.edema = (c.flags & TUMOR_F_EDEMA) ? 1 : 0;
+}
+
+int check_params(const tumor_params* p) {
+  if (!p) return TUMOR_EINVAL;
+  const double* v = reinterpret_cast<const double*>(p);
+  for (size_t k = 0; k < sizeof(tumor_params) / sizeof(double); ++k)
+    if (!std::isfinite(v[k])) return TUMOR_EINVAL;
+  if (!(p->heaviside_eps > 0.0)) return TUMOR_EINVAL;
+  if (!(p->o_inv > p->o_hyp)) return TUMOR_EINVAL;  // o_mit strictly below o_inv
+  const double nus[4] = {p->nu_wm, p->nu_gm, p->nu_csf, p->nu_tumor};
+  for (double nu : nus)
+    if (!(nu > -1.0 && nu < 0.5)) return TUMOR_EINVAL;
+  if (p->eta_tumor < 0.0 || p->eta_healthy < 0.0) return TUMOR_EINVAL;
+  return TUMOR_OK;
+}
+
+void twiddles(Ctx& c) {
+  const int n = c.n;
+  std::vector<cplx<double>> t64(n);
+  std::vector<cplx<float>> t32(n);
+  for (int m = 0; m < n; ++m) {
+    const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
+    t64[m] = {(double)cosl(ang), (double)sinl(ang)};
+    t32[m] = {(float)cosl(ang), (float)sinl(ang)};
+  }
+  HIPCHECK(hipMemcpyAsync(c.p64.tw, t64.data(), n * sizeof(cplx<double>), hipMemcpyHostToDevice, c.st));
+  HIPCHECK(hipMemcpyAsync(c.p32.tw, t32.data(), n * sizeof(cplx<float>), hipMemcpyHostToDevice, c.st));
+  HIPCHECK(hipStreamSynchronize(c.st));
+}
+
+void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
+  enum { P, I, N, O, L, G, W, F };
+  const int n = c.n;
+  (void)n;
+  // S1: transport with u_t^n = (u^n - u^{n-1}) / dt
+  if (c.flags & TUMOR_F_ADVECTION) {
+    velocity(c);
+    tumor::SLArgs s;
+    s.vx = c.vel[0];
+    s.vy = c.vel[1];
+    s.vz = c.vel[2];
+    s.div = c.vel[3];
+    s.p = c.F[P];
+    s.i = c.F[I];
+    s.n = c.F[N];
+    s.g = c.F[G];
+    s.w = c.F[W];
+    s.f = c.F[F];
+    s.po = c.G[P];
+    s.io = c.G[I];
+    s.no = c.G[N];
+    s.go = c.G[G];
+    s.wo = c.G[W];
+    s.fo = c.G[F];
+    s.n_grid = c.n;
+    s.dt = c.cfg.dt;
+    s.s = c.cfg.dt / (2.0 * M_PI / c.n);
+    if (c.mixed) tumor::launch_sl<float>(s, c.st);
+    else tumor::launch_sl<double>(s, c.st);
+  } else {
+    const int ids[6] = {P, I, N, G, W, F};
+    for (int k : ids)
+      HIPCHECK(hipMemcpyAsync(c.G[k], c.F[k], c.V * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+  }
+  // S2: Crank-Nicolson diffusion of i, o (and l).
+  SolveOut sd[3];
+  sd[0] = cn_solve(c, c.G[I], c.F[I], 0);
+  sd[1] = cn_solve(c, c.F[O], c.F[O], 1);
+  if (c.flags & TUMOR_F_EDEMA) sd[2] = cn_solve(c, c.F[L], c.F[L], 2);
+  // S3-S5: reaction, oxygen, edema, refresh.
+  {
+    const double* in[9] = {c.G[P], c.G[I], c.F[I], c.G[N], c.G[G], c.G[W], c.F[O], c.F[L], c.G[F]};
+    double* out[8] = {c.F[P], c.F[I], c.F[N], c.F[G], c.F[W], c.F[O], c.F[L], c.F[F]};
+    refresh(c, 1, in, out);
+  }
+  // S6-S7: elasticity and rotation.
+  SolveOut se;
+  if (c.flags & TUMOR_F_ELASTICITY) {
+    force_rhs(c, c.F[P], c.F[N], c.b64);
+    se = elast_solve(c, c.Un, 3);
+    cplx<double>* old = c.Up;
+    c.Up = c.U;
+    c.U = c.Un;
+    c.Un = old;
+  } else {
+    HIPCHECK(hipMemcpyAsync(c.Up, c.U, 3 * c.S * sizeof(cplx<double>), hipMemcpyDeviceToDevice, c.st));
+  }
+  c.has_forced = false;
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(c.hcs, c.cs, sizeof(tumor::CoefScalars), hipMemcpyDeviceToHost, c.st));
+  HIPCHECK(hipStreamSynchronize(c.st));
+  bool any_bad = se.bad || c.hcs->bad;
+  bool any_nc = !se.conv;
+  for (int k = 0; k < 3; ++k) {
+    any_bad |= sd[k].bad;
+    any_nc |= !sd[k].conv;
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    const double h = 2.0 * M_PI / c.n;
+    for (int k = 0; k < 3; ++k) {
+      stats->it_diff[k] = sd[k].it;
+      stats->outer_diff[k] = sd[k].outer;
+      stats->relres_diff[k] = sd[k].relres;
+    }
+    stats->it_elast = se.it;
+    stats->outer_elast = se.outer;
+    stats->relres_elast = se.relres;
+    for (int k = 0; k < 8; ++k) stats->mass[k] = c.hcs->mass[k] * h * h * h;
+    stats->max_cfl = -1.0;
+  }
+  if (any_bad) {
+    status = TUMOR_ENAN;
+    g_err = "non-finite value or loss of positive definiteness in a solve";
+  } else if (any_nc && status == TUMOR_OK) {
+    status = TUMOR_ENOCONV;
+    g_err = "a PCG solve reached max_it";
+  }
+}
+
+// Physical <-> state transfers for the displacement (spectral in the state).
+void u_to_phys(Ctx& c, const cplx<double>* U, double* dst) {
+  for (int k = 0; k < 3; ++k) inv3<double>(c, U + k * c.S, dst + k * c.V, 1.0 / (double)c.V);
+}
+void u_from_phys(Ctx& c, const double* src, cplx<double>* U) {
+  for (int k = 0; k < 3; ++k) fwd3<double>(c, src + k * c.V, nullptr, U + k * c.S);
+}
+
+template <typename R>
+void apply_op_t(Ctx& c, int op, const double* in, double* out) {
+  PrecBufs<R>& P = pb<R>(c);
+  const long long V = c.V, S = c.S;
+  const bool is64 = sizeof(R) == 8;
+  // Spectral vectors for 3-component work: P.r (input spectra), P.q (outputs).
+  cplx<R>* X = P.r;
+  cplx<R>* Q = P.q;
+  auto to_out = [&](const cplx<R>* spec, double* dst, double scale, int d) {
+    if (is64) {
+      inv3<R>(c, spec, reinterpret_cast<R*>(dst), scale, d);
+    } else {
+      R* tmp = reinterpret_cast<R*>(P.p);  // 3 S complex floats >= N^3 floats
+      inv3<R>(c, spec, tmp, scale, d);
+      tumor::launch_f32_to_f64(reinterpret_cast<const float*>(tmp), dst, V, c.st);
+    }
+  };
+  tumor::KrylovArgs ka = kargs<R>(c, 1, X, c.sv64, 0.5 * c.cfg.dt, tumor::PREC_DIFF);
+  switch (op) {
+    case TUMOR_OP_DERIV_X:
+    case TUMOR_OP_DERIV_Y:
+    case TUMOR_OP_DERIV_Z:
+      fwd3<R>(c, in, nullptr, X);
+      to_out(X, out, 1.0 / (double)V, op - TUMOR_OP_DERIV_X);
+      break;
+    case TUMOR_OP_DIFFUSION:
+      fwd3<R>(c, in, nullptr, X);
+      diff_apply<R>(c, X, Q, 0.0, 1.0, nullptr);
+      to_out(Q, out, 1.0 / (double)V, -1);
+      break;
+    case TUMOR_OP_CN_PRECOND:
+      fwd3<R>(c, in, nullptr, X);
+      tumor::launch_precond<R>(ka, X, Q, c.st);
+      to_out(Q, out, 1.0 / (double)V, -1);
+      break;
+    case TUMOR_OP_ELASTICITY:
+    case TUMOR_OP_ELAST_PRECOND:
+      for (int k = 0; k < 3; ++k) fwd3<R>(c, in + k * V, nullptr, X + k * S);
+      if (op == TUMOR_OP_ELASTICITY) {
+        elast_apply<R>(c, X, Q, nullptr);
+      } else {
+        ka.ncomp = 3;
+        ka.pc.kind = tumor::PREC_ELAST;
+        tumor::launch_precond<R>(ka, X, Q, c.st);
+      }
+      for (int k = 0; k < 3; ++k) to_out(Q + k * S, out + k * V, 1.0 / (double)V, -1);
+      break;
+    default:
+      throw Fail(TUMOR_EINVAL, "unknown operator id");
+  }
+}
+
+template <typename Fn>
+int guarded(Fn fn) {
+  try {
+    return fn();
+  } catch (const Fail& f) {
+    g_err = f.what();
+    return f.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return TUMOR_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return TUMOR_EDEVICE;
+  }
+}
+
+int einval(const char* msg) {
+  g_err = msg;
+  return TUMOR_EINVAL;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+int tumor_abi_version(void) { return TUMOR_ABI_VERSION; }
+
+const char* tumor_last_error(void) { return g_err.c_str(); }
+
+int tumor_workspace_bytes(const tumor_config* cfg, size_t* bytes) {
+  if (!bytes) return einval("bytes is NULL");
+  if (check_cfg(cfg) != TUMOR_OK) return einval("invalid tumor_config");
+  *bytes = workspace_size(*cfg);
+  return TUMOR_OK;
+}
+
+int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm, void* workspace,
+               size_t ws_bytes, const double* wm, const double* gm, const double* csf, int32_t n_ic,
+               const double* ic_centers, const double* ic_sigmas, const double* ic_weights, void* hip_stream) {
+  if (!out) return einval("out is NULL");
+  *out = nullptr;
+  if (check_cfg(cfg) != TUMOR_OK) return einval("invalid tumor_config");
+  if (check_params(prm) != TUMOR_OK) return einval("invalid tumor_params");
+  if (!workspace) return einval("workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return einval("workspace is not 256-byte aligned");
+  if (!wm || !gm || !csf) return einval("tissue map pointer is NULL");
+  if (n_ic < 0) return einval("n_ic < 0");
+  if (n_ic > 0 && (!ic_centers || !ic_sigmas || !ic_weights)) return einval("initial-condition array is NULL");
+  for (int k = 0; k < n_ic; ++k) {
+    if (!(ic_sigmas[k] > 0.0) || !std::isfinite(ic_sigmas[k])) return einval("ic_sigmas must be > 0");
+    if (!std::isfinite(ic_weights[k])) return einval("ic_weights must be finite");
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(ic_centers[3 * k + a])) return einval("ic_centers must be finite");
+  }
+  const size_t need = workspace_size(*cfg);
+  if (ws_bytes < need) {
+    g_err = "workspace too small: need " + std::to_string(need) + " bytes";
+    return TUMOR_ENOMEM;
+  }
+  const long long V = (long long)cfg->n * cfg->n * cfg->n;
+  if (5LL * n_ic > V) return einval("too many initial-condition centres for this grid");
+  tumor_ctx* c = new (std::nothrow) tumor_ctx;
+  if (!c) {
+    g_err = "host allocation failed";
+    return TUMOR_ENOMEM;
+  }
+  std::memset(c, 0, sizeof(*c));
+  int rc = guarded([&]() -> int {
+    c->cfg = *cfg;
+    c->prm = *prm;
+    c->st = static_cast<hipStream_t>(hip_stream);
+    c->n = cfg->n;
+    c->V = V;
+    c->S = V / 2;
+    c->mixed = cfg->precision == TUMOR_PREC_MIXED;
+    c->flags = cfg->flags == 0 ? TUMOR_F_DEFAULT : cfg->flags;
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) throw Fail(TUMOR_EDEVICE, "no HIP device");
+    Carver cv{static_cast<char*>(workspace), 0, false};
+    layout(*c, cv);
+    void* h1 = nullptr;
+    void* h2 = nullptr;
+    HIPCHECK(hipHostMalloc(&h1, sizeof(tumor::SolveScalars), hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc(&h2, sizeof(tumor::CoefScalars), hipHostMallocDefault));
+    c->hsv = static_cast<tumor::SolveScalars*>(h1);
+    c->hcs = static_cast<tumor::CoefScalars*>(h2);
+    c->pred[0] = c->pred[1] = c->pred[2] = 6;
+    c->pred[3] = 30;
+    set_consts(*c);
+    twiddles(*c);
+    HIPCHECK(hipMemsetAsync(c->sv64, 0, sizeof(tumor::SolveScalars), c->st));
+    HIPCHECK(hipMemsetAsync(c->sv32, 0, sizeof(tumor::SolveScalars), c->st));
+    HIPCHECK(hipMemsetAsync(c->cs, 0, sizeof(tumor::CoefScalars), c->st));
+    enum { P, I, N, O, L, G, W, F };
+    const size_t fb = V * sizeof(double);
+    HIPCHECK(hipMemcpyAsync(c->F[G], gm, fb, hipMemcpyDeviceToDevice, c->st));
+    HIPCHECK(hipMemcpyAsync(c->F[W], wm, fb, hipMemcpyDeviceToDevice, c->st));
+    HIPCHECK(hipMemcpyAsync(c->F[F], csf, fb, hipMemcpyDeviceToDevice, c->st));
+    HIPCHECK(hipMemsetAsync(c->F[I], 0, fb, c->st));
+    HIPCHECK(hipMemsetAsync(c->F[N], 0, fb, c->st));
+    HIPCHECK(hipMemsetAsync(c->F[L], 0, fb, c->st));
+    {
+      std::vector<double> o(V, prm->o_heal);
+      HIPCHECK(hipMemcpyAsync(c->F[O], o.data(), fb, hipMemcpyHostToDevice, c->st));
+      std::vector<double> ic(5 * (size_t)n_ic);
+      for (int k = 0; k < n_ic; ++k) {
+        ic[5 * k + 0] = ic_centers[3 * k + 0];
+        ic[5 * k + 1] = ic_centers[3 * k + 1];
+        ic[5 * k + 2] = ic_centers[3 * k + 2];
+        ic[5 * k + 3] = ic_sigmas[k];
+        ic[5 * k + 4] = ic_weights[k];
+      }
+      if (n_ic > 0)
+        HIPCHECK(hipMemcpyAsync(c->G[0], ic.data(), ic.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+      tumor::launch_ic(c->n, c->G[0], n_ic, c->F[P], c->st);
+      HIPCHECK(hipStreamSynchronize(c->st));  // host vectors go out of scope
+    }
+    const size_t ub = 3 * c->S * sizeof(cplx<double>);
+    HIPCHECK(hipMemsetAsync(c->U, 0, ub, c->st));
+    HIPCHECK(hipMemsetAsync(c->Up, 0, ub, c->st));
+    HIPCHECK(hipMemsetAsync(c->Un, 0, ub, c->st));
+    refresh_state(*c);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(c->st));
+    return TUMOR_OK;
+  });
+  if (rc != TUMOR_OK) {
+    if (c->hsv) (void)hipHostFree(c->hsv);
+    if (c->hcs) (void)hipHostFree(c->hcs);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return TUMOR_OK;
+}
+
+int tumor_step(tumor_ctx* ctx, int32_t nsteps, tumor_step_stats* last) {
+  if (!ctx) return einval("ctx is NULL");
+  if (nsteps < 0) return einval("nsteps < 0");
+  return guarded([&]() -> int {
+    int status = TUMOR_OK;
+    tumor_step_stats st;
+    for (int s = 0; s < nsteps; ++s) {
+      do_step(*ctx, &st, status);
+      if (status == TUMOR_ENAN) break;
+    }
+    if (last && nsteps > 0) *last = st;
+    return status;
+  });
+}
+
+int tumor_solve_elasticity(tumor_ctx* ctx, const double* force, double* u_out, int32_t* iters, double* relres) {
+  if (!ctx) return einval("ctx is NULL");
+  if (!u_out) return einval("u_out is NULL");
+  return guarded([&]() -> int {
+    Ctx& c = *ctx;
+    enum { P, I, N };
+    if (force) {
+      for (int k = 0; k < 3; ++k) fwd3<double>(c, force + k * c.V, nullptr, c.b64 + k * c.S, -1.0);
+    } else {
+      force_rhs(c, c.F[P], c.F[N], c.b64);
+    }
+    SolveOut so = elast_solve(c, c.Un, -1);
+    u_to_phys(c, c.Un, u_out);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(c.st));
+    if (iters) *iters = so.it;
+    if (relres) *relres = so.relres;
+    if (so.bad) {
+      g_err = "non-finite value in the elasticity solve";
+      return TUMOR_ENAN;
+    }
+    if (!so.conv) {
+      g_err = "elasticity PCG reached max_it";
+      return TUMOR_ENOCONV;
+    }
+    return TUMOR_OK;
+  });
+}
+
+int tumor_get_field(tumor_ctx* ctx, int32_t id, double* dst) {
+  if (!ctx) return einval("ctx is NULL");
+  if (!dst) return einval("dst is NULL");
+  if (id < 0 || id >= TUMOR_FIELD_COUNT) return einval("unknown field id");
+  return guarded([&]() -> int {
+    Ctx& c = *ctx;
+    const size_t fb = c.V * sizeof(double);
+    if (id < 8) {
+      HIPCHECK(hipMemcpyAsync(dst, c.F[id], fb, hipMemcpyDeviceToDevice, c.st));
+    } else if (id == TUMOR_FIELD_U || id == TUMOR_FIELD_UPREV) {
+      u_to_phys(c, id == TUMOR_FIELD_U ? c.U : c.Up, dst);
+    } else {
+      const double* src[5] = {c.K, c.rho, c.mu, c.lam, c.eta};
+      HIPCHECK(hipMemcpyAsync(dst, src[id - TUMOR_FIELD_K], fb, hipMemcpyDeviceToDevice, c.st));
+    }
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(c.st));
+    return TUMOR_OK;
+  });
+}
+
+int tumor_set_field(tumor_ctx* ctx, int32_t id, const double* src) {
+  if (!ctx) return einval("ctx is NULL");
+  if (!src) return einval("src is NULL");
+  if (id < 0 || id > TUMOR_FIELD_UPREV) return einval("field is not settable");
+  return guarded([&]() -> int {
+    Ctx& c = *ctx;
+    if (id < 8) {
+      HIPCHECK(hipMemcpyAsync(c.F[id], src, c.V * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+    } else {
+      u_from_phys(c, src, id == TUMOR_FIELD_U ? c.U : c.Up);
+    }
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(c.st));
+    return TUMOR_OK;
+  });
+}
+
+int tumor_refresh(tumor_ctx* ctx) {
+  if (!ctx) return einval("ctx is NULL");
+  return guarded([&]() -> int {
+    refresh_state(*ctx);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(ctx->st));
+    return TUMOR_OK;
+  });
+}
+
+int tumor_apply_op(tumor_ctx* ctx, int32_t op, const double* in, double* out) {
+  if (!ctx) return einval("ctx is NULL");
+  if (!in || !out) return einval("in/out is NULL");
+  if (op < 0 || op >= TUMOR_OP_COUNT) return einval("unknown operator id");
+  return guarded([&]() -> int {
+    Ctx& c = *ctx;
+    if (op == TUMOR_OP_FORCE) {
+      force_rhs(c, in, nullptr, c.b64);
+      for (int k = 0; k < 3; ++k) inv3<double>(c, c.b64 + k * c.S, out + k * c.V, -1.0 / (double)c.V);
+    } else if (c.mixed) {
+      apply_op_t<float>(c, op, in, out);
+    } else {
+      apply_op_t<double>(c, op, in, out);
+    }
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(c.st));
+    return TUMOR_OK;
+  });
+}
+
+int tumor_interp(tumor_ctx* ctx, const double* q, const double* jx, const double* jy, const double* jz,
+                 int64_t count, double* out) {
+  if (!ctx) return einval("ctx is NULL");
+  if (count < 0 || count > ctx->V) return einval("count out of range");
+  if (count > 0 && (!q || !jx || !jy || !jz || !out)) return einval("NULL array");
+  return guarded([&]() -> int {
+    tumor::launch_interp(ctx->n, q, jx, jy, jz, count, out, ctx->st);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(ctx->st));
+    return TUMOR_OK;
+  });
+}
+
+int tumor_force_iterations(tumor_ctx* ctx, const int32_t* iters) {
+  if (!ctx) return einval("ctx is NULL");
+  if (!iters) {
+    ctx->has_forced = false;
+    return TUMOR_OK;
+  }
+  if (ctx->mixed) return einval("forced iteration counts apply to the FP64 precision only");
+  for (int k = 0; k < 4; ++k) {
+    if (iters[k] < -1 || iters[k] > ctx->cfg.max_it) return einval("forced count out of range");
+    ctx->forced[k] = iters[k];
+  }
+  ctx->has_forced = true;
+  return TUMOR_OK;
+}
+
+int tumor_tape_bytes(const tumor_config* cfg, int32_t nsteps, int32_t ckpt_every, size_t* bytes) {
+  (void)cfg;
+  (void)nsteps;
+  (void)ckpt_every;
+  (void)bytes;
+  g_err = "the adjoint tape is not available in this build";
+  return TUMOR_ESTATE;
+}
+
+int tumor_record(tumor_ctx* ctx, int32_t nsteps, int32_t ckpt_every, void* tape, size_t tape_bytes) {
+  (void)ctx;
+  (void)nsteps;
+  (void)ckpt_every;
+  (void)tape;
+  (void)tape_bytes;
+  g_err = "the adjoint tape is not available in this build";
+  return TUMOR_ESTATE;
+}
+
+int tumor_adjoint_step(tumor_ctx* ctx, double* adj, double* grad) {
+  if (!ctx) return einval("ctx is NULL");
+  (void)adj;
+  (void)grad;
+  g_err = "no recorded forward step to reverse";
+  return TUMOR_ESTATE;
+}
+
+void tumor_destroy(tumor_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->st);
+  if (ctx->hsv) (void)hipHostFree(ctx->hsv);
+  if (ctx->hcs) (void)hipHostFree(ctx->hcs);
+  delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Pointwise, transport and Krylov-vector kernels (launchers).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft.hpp"
+
+namespace tumor {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocksMax = 1024;
+constexpr int kPartialsPerBlock = 16;
+
+// Device scalars of one PCG solve.  Written by the last block of each
+// reduction kernel, read by the following kernels and by the host.
+struct SolveScalars {
+  double bb;      // ||b||^2 (spectral, Parseval-weighted)
+  double rr;      // ||r||^2 of the current residual
+  double rho;     // <r, M^-1 r>
+  double alpha;
+  double beta;
+  double pq;      // <p, A p>
+  int32_t it;     // iterations taken
+  int32_t done;   // 1: no further iteration (converged, limit, breakdown)
+  int32_t conv;   // 1: converged
+  int32_t bad;    // 1: non-finite or non-positive curvature encountered
+  uint32_t counter;  // last-block counter of the reductions
+  int32_t pad[3];
+};
+
+// Voxel means of the coefficient fields and species masses.
+struct CoefScalars {
+  double Kbar, mubar, lambar, etabar;
+  double mass[8];
+  uint32_t counter;
+  int32_t bad;
+  int32_t pad[2];
+};
+
+// Constants of the coefficient refresh (Eqs. e:diffusion_tensor,
+// e:reaction_op, e:lame, e:screening), computed on the host from tumor_params.
+struct RefreshConsts {
+  double k_w, k_g, k_f;
+  double rho_w, rho_g;
+  double mu_w, mu_g, mu_f, mu_t;
+  double la_w, la_g, la_f, la_t;
+  double eta_t, eta_h;
+};
+
+struct ReactConsts {
+  double dt;
+  double alpha0, beta0, gamma, sigma_b, o_hyp, o_inv, o_mit, o_heal;
+  double delta_s, delta_p, delta_e, delta_half, delta_l, eps, rho_inv_frac;
+  int edema;
+};
+
+// Reaction + oxygen + edema + refresh (one pass over the grid).
+struct ReactArgs {
+  // inputs (after transport and diffusion)
+  const double *p, *i_dag, *i_dd, *n, *g, *w, *o, *l, *f;
+  // outputs (may alias p, n, g, w, o, l of the inputs; not i_dag)
+  double *po, *io, *no, *go, *wo, *oo, *lo, *fo;
+  // coefficient fields: rho is read (frozen growth rate) then overwritten
+  double *K, *rho, *mu, *lam, *eta;
+  float *K32, *mu32, *lam32, *eta32;  // nullable (mixed precision copies)
+  CoefScalars* cs;
+  double* partials;
+  long long V;
+  int do_reaction;
+  ReactConsts rc;
+  RefreshConsts fc;
+};
+
+void launch_react(const ReactArgs& a, hipStream_t st);
+
+// p0 = sum_k w_k exp(-|x - c_k|_per^2 / (2 s_k^2)); ic = n_ic x (cx, cy, cz, s, w)
+void launch_ic(int n, const double* ic, int n_ic, double* p0, hipStream_t st);
+
+// Semi-Lagrangian step (Sec. 3).  v: velocity components and divergence
+// (physical).  RC: arithmetic type of the interpolation weights and sums.
+struct SLArgs {
+  const double *vx, *vy, *vz, *div;
+  const double *p, *i, *n, *g, *w, *f;
+  double *po, *io, *no, *go, *wo, *fo;
+  int n_grid;
+  double dt, s;  // s = dt / h
+};
+template <typename RC>
+void launch_sl(const SLArgs& a, hipStream_t st);
+
+// Tricubic Lagrange interpolation at arbitrary grid-index points.
+void launch_interp(int n, const double* q, const double* jx, const double* jy, const double* jz,
+                   long long count, double* out, hipStream_t st);
+
+// ---- Krylov vectors in spectral space (ncomp blocks of S = N^3/2 complex)
+enum PrecKind : int { PREC_DIFF = 0, PREC_ELAST = 1 };
+
+struct PrecConsts {
+  double h;  // dt/2 for CN
+  int kind;  // PrecKind
+  int singular;  // elasticity without screening: zero the mean mode
+};
+
+struct KrylovArgs {
+  void *x, *r, *p, *q, *b;       // complex R arrays (b, ax: see each kernel)
+  const void* ax;
+  const CoefScalars* cs;
+  SolveScalars* sv;
+  double* partials;
+  int n, ncomp;
+  PrecConsts pc;
+  double thr2;   // convergence threshold on ||r||^2
+  int limit;     // iteration limit (max_it or a forced count)
+  int fixed;     // 1: ignore convergence, stop at `limit`
+};
+
+// r = b - ax (ax nullable: r = b); bb, rr -> sv.  Optionally r32 = float(r).
+template <typename R>
+void launch_residual(const KrylovArgs& a, void* r32, hipStream_t st);
+// CN start from c (= x0) and D c: b = c + h Dc, r = b - (c - h Dc); bb, rr -> sv.
+template <typename R>
+void launch_cn_residual(const KrylovArgs& a, const void* c, const void* dc, hipStream_t st);
+// p = M^-1 r; rho = <r, M^-1 r>; it = 0; done = 0.  zero_x: x = 0 as well.
+template <typename R>
+void launch_pcg_start(const KrylovArgs& a, int zero_x, hipStream_t st);
+// alpha = rho / <p, q>
+template <typename R>
+void launch_pcg_pq(const KrylovArgs& a, hipStream_t st);
+// x += alpha p, r -= alpha q, convergence test, beta
+template <typename R>
+void launch_pcg_update(const KrylovArgs& a, hipStream_t st);
+// p = M^-1 r + beta p
+template <typename R>
+void launch_pcg_pupdate(const KrylovArgs& a, hipStream_t st);
+// out = M^-1 in (one application of the preconditioner)
+template <typename R>
+void launch_precond(const KrylovArgs& a, const void* in, void* out, hipStream_t st);
+// x64 += x32 over ncomp blocks
+void launch_add32to64(void* x64, const void* x32, long long count, hipStream_t st);
+// physical float -> double
+void launch_f32_to_f64(const float* in, double* out, long long count, hipStream_t st);
+void launch_scale64(double* x, double s, long long count, hipStream_t st);
+
+}  // namespace tumor

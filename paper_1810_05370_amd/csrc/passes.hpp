@@ -1,0 +1,113 @@
+// Axis passes of the 3-D real FFT on the periodic N^3 grid, with the spectral
+// symbols and pointwise physical-space work of each operator fused in.
+//
+// Layouts (all C order, x fastest):
+//   physical  real    [z][y][x]                        N^3 values
+//   spectral  complex [kz][ky][kxp], kxp in [0, N/2)   N^3/2 values
+// The spectral array is the x-R2C half spectrum with the real Nyquist
+// coefficient (kx = N/2) packed into the imaginary part of the kx = 0
+// coefficient.  Both packed planes share w_x = 0 (the Nyquist wave number is
+// dropped in every derivative), so every symbol used here acts on the packed
+// column exactly as on the two planes separately.  Forward transforms are
+// unnormalised, inverse transforms are unnormalised; the 1/N^3 lives in the
+// physical-space step of each operator.
+//
+// Pass kinds:
+//   col_pass  : FFT along y or z for a tile of TC adjacent kxp columns.  A
+//               small program (ColProg) says which input columns are combined
+//               with which axis symbol into each output.
+//   xpass_*   : FFT along x (packed R2C / C2R) for a tile of rows, with the
+//               operator's physical-space work between the inverse and the
+//               forward transform, all in registers.
+#pragma once
+#include "fft.hpp"
+
+namespace tumor {
+
+constexpr int kMaxCol = 8;
+constexpr int kMaxTerms = 3;
+
+enum ColSym : int { SYM_ONE = 0, SYM_IW = 1, SYM_RAW = 2 };
+
+struct ColTerm {
+  int src;
+  int sym;      // ColSym
+  double coef;  // real multiplier
+};
+
+// Inverse pass: out[o] = IFFT_axis( sum_t coef_t * s_t(k) * in[src_t] )
+// Forward pass: out[o] = sum_t coef_t * s_t(k) * FFT_axis(in[src_t])
+//               (SYM_RAW: the input is read at the output position, untransformed)
+struct ColProg {
+  const void* in[kMaxCol];
+  void* out[kMaxCol];
+  int nout;
+  int nterm[kMaxCol];
+  ColTerm term[kMaxCol][kMaxTerms];
+  const int* skip;  // if non-null and *skip != 0 the launch does nothing
+};
+
+// Rows of the x pass: generic programs.
+//   xinv: phys_out[o] = scale * C2R( sum_t coef_t * s_t(kx) * in[src_t] )
+//   xfwd: spec_out[o] = R2C( sum_t coef_t * phys_in[src_t] )
+struct XProg {
+  const void* in[kMaxCol];
+  void* out[kMaxCol];
+  int nout;
+  int nterm[kMaxCol];
+  ColTerm term[kMaxCol][kMaxTerms];
+  double scale;
+  const int* skip;
+};
+
+// Elasticity x pass.  Inputs (packed spectral rows, after the y and z inverse
+// passes): U_x, U_y, U_z, dy u_x, dy u_y, (dz u_y + dy u_z), dz u_x, dz u_z.
+// Coefficients (physical): mu, lambda, eta.  Outputs (packed spectral rows):
+// eta u_x - dx s_xx, eta u_y - dx s_xy, eta u_z - dx s_xz, s_xy, s_yy, s_yz,
+// s_xz, s_zz, where s = mu (grad u + grad u^T) + lambda div u I.
+struct XElastArgs {
+  const void* in[8];
+  void* out[8];
+  const void* mu;
+  const void* lam;
+  const void* eta;
+  const int* skip;
+};
+
+// Diffusion x pass.  Inputs: C, dy c, dz c (packed rows); coefficient K.
+// Outputs: i w_x F(K dx c), F(K dy c), F(K dz c).
+struct XDiffArgs {
+  const void* in[3];
+  void* out[3];
+  const void* K;
+  const int* skip;
+};
+
+// Force x pass.  Inputs: T, dy t, dz t (packed rows of tau = p + n).
+// Outputs: F(-zeta tanh(tau) d_a tau), a = x, y, z.
+struct XForceArgs {
+  const void* in[3];
+  void* out[3];
+  double zeta;
+};
+
+struct PassGeom {
+  int n;
+};
+
+// Host-side launchers, instantiated for R = double and float.
+template <typename R>
+void launch_col_pass(int n, int axis /*1 = y, 2 = z*/, bool inverse, const ColProg& prog,
+                     const void* tw, hipStream_t st);
+template <typename R>
+void launch_xinv(int n, const XProg& prog, const void* tw, hipStream_t st);
+template <typename R>
+void launch_xfwd(int n, const XProg& prog, const void* tw, hipStream_t st, bool in_fp64);
+template <typename R>
+void launch_xelast(int n, const XElastArgs& a, const void* tw, hipStream_t st);
+template <typename R>
+void launch_xdiff(int n, const XDiffArgs& a, const void* tw, hipStream_t st);
+template <typename R>
+void launch_xforce(int n, const XForceArgs& a, const void* tw, hipStream_t st);
+
+}  // namespace tumor

@@ -1,0 +1,466 @@
+// Kernels and launchers of the axis passes (see passes.hpp for layouts).
+#pragma once
+#include <stdexcept>
+#include <string>
+
+#include "passes.hpp"
+
+namespace tumor {
+
+// ----------------------------------------------------------------- geometry
+// Column tiles: TC adjacent kxp columns, TP = N/8 threads per column.
+template <int N>
+struct ColCfg {
+  static constexpr int TP = N / 8;
+  static constexpr int TCW = 256 / TP;
+  static constexpr int TC = (N / 2) < (TCW < 8 ? 8 : TCW) ? (N / 2) : (TCW < 8 ? 8 : TCW);
+  static constexpr int THREADS = TC * TP;
+  static constexpr int LDS = N * TC + N / 8 + 1;
+};
+
+// Row tiles: RW rows of L = N/2 packed complex values, TP = L/8 threads each.
+template <int N>
+struct RowCfg {
+  static constexpr int L = N / 2;
+  static constexpr int TP = L / 8;
+  static constexpr int RW0 = 256 / TP;
+  static constexpr int RW = RW0 > N * N ? N * N : RW0;
+  static constexpr int THREADS = RW * TP;
+  static constexpr int LP = L + L / 8;  // padded row length in LDS
+};
+
+template <int N>
+__device__ __forceinline__ int xwave(int k) {  // x wave number of packed index k
+  return k;                                    // k = 0 carries both kx = 0 and kx = N/2: w = 0
+}
+
+// ---------------------------------------------------------------- col pass
+template <typename R, int N, bool INV>
+__global__ void __launch_bounds__(ColCfg<N>::THREADS)
+    k_col_pass(ColProg prog, long long fstride, long long astride, const cplx<R>* __restrict__ tw) {
+  if (prog.skip && *prog.skip) return;
+  using Cfg = ColCfg<N>;
+  constexpr int TP = Cfg::TP, TC = Cfg::TC;
+  __shared__ R sre[Cfg::LDS];
+  __shared__ R sim[Cfg::LDS];
+  const int tid = threadIdx.x;
+  const int col = tid % TC;
+  const int t = tid / TC;
+  const long long base = (long long)blockIdx.y * fstride + (long long)blockIdx.x * TC + col;
+  const LdsView<R> lds{sre + col, sim + col, TC, 1};
+  for (int o = 0; o < prog.nout; ++o) {
+    cplx<R> acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = czero<R>();
+    const int nt = prog.nterm[o];
+    if constexpr (INV) {
+      for (int q = 0; q < nt; ++q) {
+        const ColTerm tm = prog.term[o][q];
+        const cplx<R>* __restrict__ src = static_cast<const cplx<R>*>(prog.in[tm.src]);
+        const R cf = R(tm.coef);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int n = t + TP * j;
+          cplx<R> v = src[base + (long long)n * astride];
+          if (tm.sym == SYM_IW) v = ciw(v, R(wavenum<N>(n)));
+          acc[j].x += cf * v.x;
+          acc[j].y += cf * v.y;
+        }
+      }
+      fft_block<R, N, true, 1>(acc, lds, t, tw);
+    } else {
+      for (int q = 0; q < nt; ++q) {
+        const ColTerm tm = prog.term[o][q];
+        const cplx<R>* __restrict__ src = static_cast<const cplx<R>*>(prog.in[tm.src]);
+        const R cf = R(tm.coef);
+        cplx<R> tmp[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) tmp[j] = src[base + (long long)(t + TP * j) * astride];
+        if (tm.sym != SYM_RAW) fft_block<R, N, false, 1>(tmp, lds, t, tw);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          cplx<R> v = tmp[j];
+          if (tm.sym == SYM_IW) v = ciw(v, R(wavenum<N>(t + TP * j)));
+          acc[j].x += cf * v.x;
+          acc[j].y += cf * v.y;
+        }
+      }
+    }
+    cplx<R>* __restrict__ dst = static_cast<cplx<R>*>(prog.out[o]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dst[base + (long long)(t + TP * j) * astride] = acc[j];
+  }
+}
+
+// ------------------------------------------------------------- row helpers
+// Pre-processing of the packed C2R: A = combined packed value at k, B at L-k.
+template <typename R, int N>
+__device__ __forceinline__ cplx<R> c2r_pre(cplx<R> A, cplx<R> B, int k, const cplx<R>* __restrict__ tw) {
+  if (k == 0) return {A.x + A.y, A.x - A.y};
+  const cplx<R> xc = cconj(B);
+  const cplx<R> s = cadd(A, xc), d = csub(A, xc);
+  const cplx<R> w = tw[k];
+  const cplx<R> e = cmul(cconj(w), d);
+  return {s.x - e.y, s.y + e.x};
+}
+
+// Packed R2C of the row held as v[j] = (x[2p], x[2p+1]), p = t + TP*j.
+template <typename R, int N>
+__device__ __forceinline__ void row_r2c(cplx<R> (&v)[8], const LdsView<R>& lds, int t,
+                                        const cplx<R>* __restrict__ tw) {
+  constexpr int L = N / 2, TP = L / 8;
+  fft_block<R, L, false, 2>(v, lds, t, tw);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) lds.put(t + TP * j, v[j]);
+  __syncthreads();
+  cplx<R> zc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) zc[j] = cconj(lds.get((L - (t + TP * j)) & (L - 1)));
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = t + TP * j;
+    const cplx<R> z = v[j];
+    if (k == 0) {
+      v[j] = {z.x + z.y, z.x - z.y};
+    } else {
+      const cplx<R> s = cadd(z, zc[j]), d = csub(z, zc[j]);
+      const cplx<R> wd = cmul(tw[k], d);
+      v[j] = {R(0.5) * (s.x + wd.y), R(0.5) * (s.y - wd.x)};
+    }
+  }
+}
+
+// Packed C2R: gathers sum_t coef * s_t(kx) * in_t at k and L-k, pre-processes,
+// inverse transforms; on return v[j] = N * (x[2p], x[2p+1]).
+template <typename R, int N>
+__device__ __forceinline__ void row_c2r_terms(cplx<R> (&v)[8], int nt, const ColTerm* terms,
+                                              const void* const* in, long long rowoff,
+                                              const LdsView<R>& lds, int t,
+                                              const cplx<R>* __restrict__ tw) {
+  constexpr int L = N / 2, TP = L / 8;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = t + TP * j;
+    const int kp = (L - k) & (L - 1);
+    cplx<R> A = czero<R>(), B = czero<R>();
+    for (int q = 0; q < nt; ++q) {
+      const ColTerm tm = terms[q];
+      const cplx<R>* __restrict__ src = static_cast<const cplx<R>*>(in[tm.src]) + rowoff;
+      const R cf = R(tm.coef);
+      cplx<R> a = src[k], b = src[kp];
+      if (tm.sym == SYM_IW) {
+        a = ciw(a, R(xwave<N>(k)));
+        b = ciw(b, R(xwave<N>(kp)));
+      }
+      A.x += cf * a.x;
+      A.y += cf * a.y;
+      B.x += cf * b.x;
+      B.y += cf * b.y;
+    }
+    v[j] = c2r_pre<R, N>(A, B, k, tw);
+  }
+  fft_block<R, L, true, 2>(v, lds, t, tw);
+}
+
+// Single-input C2R with an optional x-derivative and an optional added input.
+template <typename R, int N>
+__device__ __forceinline__ void row_c2r(cplx<R> (&v)[8], const cplx<R>* __restrict__ a, bool iw_a,
+                                        const cplx<R>* __restrict__ b, const LdsView<R>& lds, int t,
+                                        const cplx<R>* __restrict__ tw) {
+  constexpr int L = N / 2, TP = L / 8;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = t + TP * j;
+    const int kp = (L - k) & (L - 1);
+    cplx<R> A = a[k], B = a[kp];
+    if (iw_a) {
+      A = ciw(A, R(xwave<N>(k)));
+      B = ciw(B, R(xwave<N>(kp)));
+    }
+    if (b) {
+      A = cadd(A, b[k]);
+      B = cadd(B, b[kp]);
+    }
+    v[j] = c2r_pre<R, N>(A, B, k, tw);
+  }
+  fft_block<R, L, true, 2>(v, lds, t, tw);
+}
+
+template <typename R, int N>
+__device__ __forceinline__ void store_row(cplx<R>* __restrict__ dst, const cplx<R> (&v)[8], int t) {
+  constexpr int TP = N / 16;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) dst[t + TP * j] = v[j];
+}
+
+// iw_x (packed) times a row held in registers
+template <typename R, int N>
+__device__ __forceinline__ cplx<R> iwx(cplx<R> a, int k) {
+  return ciw(a, R(xwave<N>(k)));
+}
+
+#define TUMOR_ROW_SETUP(N)                                           \
+  using RC = RowCfg<N>;                                              \
+  constexpr int L = RC::L, TP = RC::TP;                              \
+  __shared__ R sre[RC::RW * RC::LP];                                 \
+  __shared__ R sim[RC::RW * RC::LP];                                 \
+  const int t = threadIdx.x % TP;                                    \
+  const int rl = threadIdx.x / TP;                                   \
+  const long long row = (long long)blockIdx.x * RC::RW + rl;         \
+  const LdsView<R> lds{sre + rl * RC::LP, sim + rl * RC::LP, 1, 1};  \
+  const long long soff = row * L;                                    \
+  const long long poff = row * N;                                    \
+  (void)soff;                                                        \
+  (void)poff;
+
+// ------------------------------------------------------------- x kernels
+template <typename R, int N>
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xinv(XProg prog, const cplx<R>* __restrict__ tw) {
+  if (prog.skip && *prog.skip) return;
+  TUMOR_ROW_SETUP(N)
+  const R scale = R(prog.scale);
+  for (int o = 0; o < prog.nout; ++o) {
+    cplx<R> v[8];
+    row_c2r_terms<R, N>(v, prog.nterm[o], prog.term[o], prog.in, soff, lds, t, tw);
+    cplx<R>* __restrict__ dst = reinterpret_cast<cplx<R>*>(static_cast<R*>(prog.out[o]) + poff);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dst[t + TP * j] = cscale(v[j], scale);
+  }
+}
+
+template <typename R, int N, typename RIN>
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xfwd(XProg prog, const cplx<R>* __restrict__ tw) {
+  if (prog.skip && *prog.skip) return;
+  TUMOR_ROW_SETUP(N)
+  for (int o = 0; o < prog.nout; ++o) {
+    cplx<R> v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = czero<R>();
+    for (int q = 0; q < prog.nterm[o]; ++q) {
+      const ColTerm tm = prog.term[o][q];
+      const cplx<RIN>* __restrict__ src =
+          reinterpret_cast<const cplx<RIN>*>(static_cast<const RIN*>(prog.in[tm.src]) + poff);
+      const R cf = R(tm.coef);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const cplx<RIN> a = src[t + TP * j];
+        v[j].x += cf * R(a.x);
+        v[j].y += cf * R(a.y);
+      }
+    }
+    row_r2c<R, N>(v, lds, t, tw);
+    store_row<R, N>(static_cast<cplx<R>*>(prog.out[o]) + soff, v, t);
+  }
+}
+
+template <typename R, int N>
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xelast(XElastArgs a, const cplx<R>* __restrict__ tw) {
+  if (a.skip && *a.skip) return;
+  TUMOR_ROW_SETUP(N)
+  const R invV = R(1.0) / (R(N) * R(N) * R(N));
+  const cplx<R>* in[8];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) in[f] = static_cast<const cplx<R>*>(a.in[f]) + soff;
+  const cplx<R>* mu = reinterpret_cast<const cplx<R>*>(static_cast<const R*>(a.mu) + poff);
+  const cplx<R>* lam = reinterpret_cast<const cplx<R>*>(static_cast<const R*>(a.lam) + poff);
+  const cplx<R>* eta = reinterpret_cast<const cplx<R>*>(static_cast<const R*>(a.eta) + poff);
+  cplx<R>* out[8];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) out[f] = static_cast<cplx<R>*>(a.out[f]) + soff;
+
+  // Group A: diagonal stresses and eta u_x.
+  {
+    cplx<R> ux[8], exx[8], eyy[8], ezz[8];
+    row_c2r<R, N>(ux, in[0], false, nullptr, lds, t, tw);
+    row_c2r<R, N>(exx, in[0], true, nullptr, lds, t, tw);
+    row_c2r<R, N>(eyy, in[4], false, nullptr, lds, t, tw);
+    row_c2r<R, N>(ezz, in[7], false, nullptr, lds, t, tw);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int p = t + TP * j;
+      const cplx<R> m = mu[p], l = lam[p], e = eta[p];
+      const R trx = (exx[j].x + eyy[j].x + ezz[j].x) * invV;
+      const R try_ = (exx[j].y + eyy[j].y + ezz[j].y) * invV;
+      exx[j] = {R(2) * m.x * exx[j].x * invV + l.x * trx, R(2) * m.y * exx[j].y * invV + l.y * try_};
+      eyy[j] = {R(2) * m.x * eyy[j].x * invV + l.x * trx, R(2) * m.y * eyy[j].y * invV + l.y * try_};
+      ezz[j] = {R(2) * m.x * ezz[j].x * invV + l.x * trx, R(2) * m.y * ezz[j].y * invV + l.y * try_};
+      ux[j] = {e.x * ux[j].x * invV, e.y * ux[j].y * invV};
+    }
+    row_r2c<R, N>(ux, lds, t, tw);
+    row_r2c<R, N>(exx, lds, t, tw);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ux[j] = csub(ux[j], iwx<R, N>(exx[j], t + TP * j));
+    store_row<R, N>(out[0], ux, t);
+    row_r2c<R, N>(eyy, lds, t, tw);
+    store_row<R, N>(out[4], eyy, t);
+    row_r2c<R, N>(ezz, lds, t, tw);
+    store_row<R, N>(out[7], ezz, t);
+  }
+  // Groups B and C: shear in the xy and xz planes with eta u_y, eta u_z.
+#pragma unroll 1
+  for (int g = 0; g < 2; ++g) {
+    const cplx<R>* U = g == 0 ? in[1] : in[2];
+    const cplx<R>* D = g == 0 ? in[3] : in[6];
+    cplx<R> u[8], s[8];
+    row_c2r<R, N>(u, U, false, nullptr, lds, t, tw);
+    row_c2r<R, N>(s, U, true, D, lds, t, tw);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int p = t + TP * j;
+      const cplx<R> m = mu[p], e = eta[p];
+      s[j] = {m.x * s[j].x * invV, m.y * s[j].y * invV};
+      u[j] = {e.x * u[j].x * invV, e.y * u[j].y * invV};
+    }
+    row_r2c<R, N>(s, lds, t, tw);
+    store_row<R, N>(g == 0 ? out[3] : out[6], s, t);
+    row_r2c<R, N>(u, lds, t, tw);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) u[j] = csub(u[j], iwx<R, N>(s[j], t + TP * j));
+    store_row<R, N>(g == 0 ? out[1] : out[2], u, t);
+  }
+  // Group D: shear in the yz plane.
+  {
+    cplx<R> s[8];
+    row_c2r<R, N>(s, in[5], false, nullptr, lds, t, tw);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const cplx<R> m = mu[t + TP * j];
+      s[j] = {m.x * s[j].x * invV, m.y * s[j].y * invV};
+    }
+    row_r2c<R, N>(s, lds, t, tw);
+    store_row<R, N>(out[5], s, t);
+  }
+}
+
+template <typename R, int N>
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdiff(XDiffArgs a, const cplx<R>* __restrict__ tw) {
+  if (a.skip && *a.skip) return;
+  TUMOR_ROW_SETUP(N)
+  const R invV = R(1.0) / (R(N) * R(N) * R(N));
+  const cplx<R>* K = reinterpret_cast<const cplx<R>*>(static_cast<const R*>(a.K) + poff);
+  const cplx<R>* C = static_cast<const cplx<R>*>(a.in[0]) + soff;
+#pragma unroll 1
+  for (int d = 0; d < 3; ++d) {
+    cplx<R> g[8];
+    if (d == 0) row_c2r<R, N>(g, C, true, nullptr, lds, t, tw);
+    else row_c2r<R, N>(g, static_cast<const cplx<R>*>(a.in[d]) + soff, false, nullptr, lds, t, tw);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const cplx<R> k = K[t + TP * j];
+      g[j] = {k.x * g[j].x * invV, k.y * g[j].y * invV};
+    }
+    row_r2c<R, N>(g, lds, t, tw);
+    if (d == 0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) g[j] = iwx<R, N>(g[j], t + TP * j);
+    }
+    store_row<R, N>(static_cast<cplx<R>*>(a.out[d]) + soff, g, t);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R rtanh(R x) { return tanh(x); }
+template <>
+__device__ __forceinline__ float rtanh<float>(float x) { return tanhf(x); }
+
+template <typename R, int N>
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xforce(XForceArgs a, const cplx<R>* __restrict__ tw) {
+  TUMOR_ROW_SETUP(N)
+  const R invV = R(1.0) / (R(N) * R(N) * R(N));
+  const cplx<R>* T = static_cast<const cplx<R>*>(a.in[0]) + soff;
+  cplx<R> th[8];
+  row_c2r<R, N>(th, T, false, nullptr, lds, t, tw);
+  const R mz = R(-a.zeta) * invV;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) th[j] = {mz * rtanh(th[j].x * invV), mz * rtanh(th[j].y * invV)};
+#pragma unroll 1
+  for (int d = 0; d < 3; ++d) {
+    cplx<R> g[8];
+    if (d == 0) row_c2r<R, N>(g, T, true, nullptr, lds, t, tw);
+    else row_c2r<R, N>(g, static_cast<const cplx<R>*>(a.in[d]) + soff, false, nullptr, lds, t, tw);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) g[j] = {th[j].x * g[j].x, th[j].y * g[j].y};
+    row_r2c<R, N>(g, lds, t, tw);
+    store_row<R, N>(static_cast<cplx<R>*>(a.out[d]) + soff, g, t);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+#define TUMOR_DISPATCH_N(n, BODY)                                    \
+  switch (n) {                                                       \
+    case 16: { constexpr int NN = 16; BODY; } break;                 \
+    case 32: { constexpr int NN = 32; BODY; } break;                 \
+    case 64: { constexpr int NN = 64; BODY; } break;                 \
+    case 128: { constexpr int NN = 128; BODY; } break;               \
+    case 256: { constexpr int NN = 256; BODY; } break;               \
+    case 512: { constexpr int NN = 512; BODY; } break;               \
+    default: throw std::runtime_error("unsupported grid size " + std::to_string(n)); \
+  }
+
+template <typename R>
+void launch_col_pass(int n, int axis, bool inverse, const ColProg& prog, const void* tw, hipStream_t st) {
+  const long long C = n / 2;
+  const long long fstride = axis == 1 ? (long long)n * C : C;
+  const long long astride = axis == 1 ? C : (long long)n * C;
+  const cplx<R>* twp = static_cast<const cplx<R>*>(tw);
+  TUMOR_DISPATCH_N(n, {
+    dim3 grid(C / ColCfg<NN>::TC, NN);
+    if (inverse)
+      hipLaunchKernelGGL((k_col_pass<R, NN, true>), grid, dim3(ColCfg<NN>::THREADS), 0, st, prog, fstride,
+                         astride, twp);
+    else
+      hipLaunchKernelGGL((k_col_pass<R, NN, false>), grid, dim3(ColCfg<NN>::THREADS), 0, st, prog, fstride,
+                         astride, twp);
+  });
+}
+
+template <typename R>
+void launch_xinv(int n, const XProg& prog, const void* tw, hipStream_t st) {
+  const cplx<R>* twp = static_cast<const cplx<R>*>(tw);
+  TUMOR_DISPATCH_N(n, {
+    dim3 grid((NN * NN) / RowCfg<NN>::RW);
+    hipLaunchKernelGGL((k_xinv<R, NN>), grid, dim3(RowCfg<NN>::THREADS), 0, st, prog, twp);
+  });
+}
+
+template <typename R>
+void launch_xfwd(int n, const XProg& prog, const void* tw, hipStream_t st, bool in_fp64) {
+  const cplx<R>* twp = static_cast<const cplx<R>*>(tw);
+  TUMOR_DISPATCH_N(n, {
+    dim3 grid((NN * NN) / RowCfg<NN>::RW);
+    if (in_fp64)
+      hipLaunchKernelGGL((k_xfwd<R, NN, double>), grid, dim3(RowCfg<NN>::THREADS), 0, st, prog, twp);
+    else
+      hipLaunchKernelGGL((k_xfwd<R, NN, R>), grid, dim3(RowCfg<NN>::THREADS), 0, st, prog, twp);
+  });
+}
+
+template <typename R>
+void launch_xelast(int n, const XElastArgs& a, const void* tw, hipStream_t st) {
+  const cplx<R>* twp = static_cast<const cplx<R>*>(tw);
+  TUMOR_DISPATCH_N(n, {
+    dim3 grid((NN * NN) / RowCfg<NN>::RW);
+    hipLaunchKernelGGL((k_xelast<R, NN>), grid, dim3(RowCfg<NN>::THREADS), 0, st, a, twp);
+  });
+}
+
+template <typename R>
+void launch_xdiff(int n, const XDiffArgs& a, const void* tw, hipStream_t st) {
+  const cplx<R>* twp = static_cast<const cplx<R>*>(tw);
+  TUMOR_DISPATCH_N(n, {
+    dim3 grid((NN * NN) / RowCfg<NN>::RW);
+    hipLaunchKernelGGL((k_xdiff<R, NN>), grid, dim3(RowCfg<NN>::THREADS), 0, st, a, twp);
+  });
+}
+
+template <typename R>
+void launch_xforce(int n, const XForceArgs& a, const void* tw, hipStream_t st) {
+  const cplx<R>* twp = static_cast<const cplx<R>*>(tw);
+  TUMOR_DISPATCH_N(n, {
+    dim3 grid((NN * NN) / RowCfg<NN>::RW);
+    hipLaunchKernelGGL((k_xforce<R, NN>), grid, dim3(RowCfg<NN>::THREADS), 0, st, a, twp);
+  });
+}
+
+}  // namespace tumor

@@ -1,0 +1,688 @@
+// Pointwise, semi-Lagrangian and Krylov-vector kernels for gfx950.
+//
+// Reductions are deterministic: each block writes one partial per quantity,
+// the last block to finish (detected with a device-scope counter) sums the
+// partials in a fixed order and publishes the result to device scalars that
+// later kernels and the host read.  The grid size of a reduction kernel is a
+// fixed function of the problem size, so results do not depend on timing.
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace tumor {
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-reduce v[], store this block's partials, return true in the last block.
+template <int NV>
+__device__ bool block_partials(double (&v)[NV], double* part, uint32_t* counter) {
+  __shared__ double sh[NV][kRedThreads / 64];
+  __shared__ int last;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double s = wave_sum(v[i]);
+    if (lane == 0) sh[i][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < kRedThreads / 64; ++w) s += sh[i][w];
+      part[(long long)blockIdx.x * kPartialsPerBlock + i] = s;
+    }
+    __threadfence();
+    const uint32_t prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  return last != 0;
+}
+
+// Called by every thread of the last block: fixed-order total of all partials.
+template <int NV>
+__device__ void final_sums(double (&tot)[NV], const double* part, uint32_t* counter) {
+  __threadfence();
+  __shared__ double sh[NV][kRedThreads / 64];
+  double v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = 0.0;
+  const volatile double* vp = part;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += vp[(long long)b * kPartialsPerBlock + i];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double s = wave_sum(v[i]);
+    if (lane == 0) sh[i][wv] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[i][w];
+    tot[i] = s;
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+static inline int red_blocks(long long count) {
+  long long b = (count + kRedThreads - 1) / kRedThreads;
+  if (b > kRedBlocksMax) b = kRedBlocksMax;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// ------------------------------------------------------ reaction + refresh
+__device__ __forceinline__ double heav(double x, double eps) { return 0.5 * (1.0 + tanh(x / eps)); }
+
+__device__ __forceinline__ double logistic_flow(double y, double r, double t) {
+  const double e = exp(r * t);
+  return y * e / (1.0 + y * (e - 1.0));
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_react(ReactArgs a) {
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  const ReactConsts& rc = a.rc;
+  const RefreshConsts& fc = a.fc;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.V; v += stride) {
+    double p = a.p[v], n = a.n[v], g = a.g[v], w = a.w[v], o = a.o[v], l = a.l[v], f = a.f[v];
+    double i = a.i_dd[v];
+    if (a.do_reaction) {
+      const double dt = rc.dt;
+      const double dD = i - a.i_dag[v];
+      const double rho_p = a.rho[v];
+      const double rho_i = rc.rho_inv_frac * rho_p;
+      const double alpha = rc.alpha0 * heav(rc.o_inv - o, rc.eps);
+      const double beta = rc.beta0 * heav(rc.sigma_b - p - i, rc.eps) * o;
+      const double h = rc.gamma * heav(rc.o_hyp - o, rc.eps);
+      double kap = (o - rc.o_mit) / (rc.o_inv - rc.o_mit);
+      kap = kap < 0.0 ? 0.0 : (kap > 1.0 ? 1.0 : kap);
+      const double dRp = logistic_flow(p, rho_p * kap, dt) - p;
+      const double dRi = logistic_flow(i, rho_i * kap, dt) - i;
+      const double p1 = p + dRp + dt * (-alpha * p + beta * i - h * p);
+      const double i1 = i + dRi + dt * (alpha * p - beta * i - h * i);
+      const double n1 = n + dt * h * (p + i + g + w);
+      const double s = dD + dRp + dRi;
+      const double gw = g + w;
+      const bool small = gw < 1e-12;
+      const double phig = small ? 0.5 : g / gw;
+      const double phiw = small ? 0.5 : w / gw;
+      const double g1 = g - phig * s - dt * h * g;
+      const double w1 = w - phiw * s - dt * h * w;
+      const double o1 = o + dt * (-rc.delta_p * p1 + rc.delta_s * (rc.o_heal - o) * (g1 + w1));
+      double l1 = l;
+      if (rc.edema) l1 = l + dt * (rc.delta_e * i1 / (i1 + rc.delta_half) * (1.0 - i1) - rc.delta_l * l);
+      p = p1; i = i1; n = n1; g = g1; w = w1; o = o1; l = l1;
+      a.po[v] = p; a.io[v] = i; a.no[v] = n; a.go[v] = g; a.wo[v] = w; a.oo[v] = o; a.lo[v] = l;
+      a.fo[v] = f;
+    }
+    // refresh
+    const double tau = p + i + n;
+    const double K = fc.k_w * w + fc.k_g * g + fc.k_f * f;
+    const double rho = fc.rho_w * w + fc.rho_g * g;
+    const double mu = fc.mu_w * w + fc.mu_g * g + fc.mu_f * f + fc.mu_t * tau;
+    const double lam = fc.la_w * w + fc.la_g * g + fc.la_f * f + fc.la_t * tau;
+    const double eta = fc.eta_t * tau + fc.eta_h * (g + w + f);
+    a.K[v] = K; a.rho[v] = rho; a.mu[v] = mu; a.lam[v] = lam; a.eta[v] = eta;
+    if (a.K32) {
+      a.K32[v] = (float)K; a.mu32[v] = (float)mu; a.lam32[v] = (float)lam; a.eta32[v] = (float)eta;
+    }
+    acc[0] += K; acc[1] += mu; acc[2] += lam; acc[3] += eta;
+    acc[4] += p; acc[5] += i; acc[6] += n; acc[7] += o; acc[8] += l; acc[9] += g; acc[10] += w;
+    acc[11] += f;
+  }
+  if (block_partials<12>(acc, a.partials, &a.cs->counter)) {
+    double tot[12];
+    final_sums<12>(tot, a.partials, &a.cs->counter);
+    if (threadIdx.x == 0) {
+      const double iv = 1.0 / (double)a.V;
+      a.cs->Kbar = tot[0] * iv;
+      a.cs->mubar = tot[1] * iv;
+      a.cs->lambar = tot[2] * iv;
+      a.cs->etabar = tot[3] * iv;
+      int bad = 0;
+      for (int k = 0; k < 8; ++k) {
+        a.cs->mass[k] = tot[4 + k];
+        if (!isfinite(tot[4 + k])) bad = 1;
+      }
+      a.cs->bad = bad;
+    }
+  }
+}
+
+void launch_react(const ReactArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_react, dim3(red_blocks(a.V)), dim3(kRedThreads), 0, st, a);
+}
+
+// ------------------------------------------------------- initial condition
+__global__ void k_ic(int n, const double* __restrict__ ic, int n_ic, double* __restrict__ p0) {
+  const long long V = (long long)n * n * n;
+  const double h = 2.0 * M_PI / n;
+  const double twopi = 2.0 * M_PI;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < V;
+       v += (long long)gridDim.x * blockDim.x) {
+    const int jx = (int)(v % n), jy = (int)((v / n) % n), jz = (int)(v / ((long long)n * n));
+    const double x = h * jx, y = h * jy, z = h * jz;
+    double s = 0.0;
+    for (int k = 0; k < n_ic; ++k) {
+      const double* c = ic + 5 * k;
+      double dx = x - c[0], dy = y - c[1], dz = z - c[2];
+      dx -= twopi * rint(dx / twopi);
+      dy -= twopi * rint(dy / twopi);
+      dz -= twopi * rint(dz / twopi);
+      const double d2 = dz * dz + dy * dy + dx * dx;
+      s += c[4] * exp(-d2 / (2.0 * c[3] * c[3]));
+    }
+    p0[v] = s;
+  }
+}
+
+void launch_ic(int n, const double* ic, int n_ic, double* p0, hipStream_t st) {
+  const long long V = (long long)n * n * n;
+  long long blocks = (V + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_ic, dim3((unsigned)blocks), dim3(256), 0, st, n, ic, n_ic, p0);
+}
+
+// --------------------------------------------------------- semi-Lagrangian
+template <typename RC>
+__device__ __forceinline__ void lagrange4(RC t, RC (&w)[4]) {
+  w[0] = -t * (t - RC(1)) * (t - RC(2)) / RC(6);
+  w[1] = (t + RC(1)) * (t - RC(1)) * (t - RC(2)) / RC(2);
+  w[2] = -(t + RC(1)) * t * (t - RC(2)) / RC(2);
+  w[3] = (t + RC(1)) * t * (t - RC(1)) / RC(6);
+}
+
+// Tricubic Lagrange interpolation of NF periodic fields at one point
+// (grid-index coordinates, computed in FP64; weights and sums in RC).
+template <typename RC, int NF>
+__device__ __forceinline__ void interp_pt(const double* const (&q)[NF], double jx, double jy, double jz, int n,
+                                          RC (&out)[NF]) {
+  const double bx = floor(jx), by = floor(jy), bz = floor(jz);
+  RC wx[4], wy[4], wz[4];
+  lagrange4<RC>(RC(jx - bx), wx);
+  lagrange4<RC>(RC(jy - by), wy);
+  lagrange4<RC>(RC(jz - bz), wz);
+  const int ix = (int)(long long)bx, iy = (int)(long long)by, iz = (int)(long long)bz;
+  const int m = n - 1;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) out[f] = RC(0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const long long zo = (long long)((iz + c - 1) & m) * n * n;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const long long yo = zo + (long long)((iy + b - 1) & m) * n;
+      const RC wzy = wz[c] * wy[b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const long long idx = yo + ((ix + a - 1) & m);
+        const RC wt = wzy * wx[a];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) out[f] += wt * RC(q[f][idx]);
+      }
+    }
+  }
+}
+
+template <typename RC>
+__global__ void __launch_bounds__(256) k_sl(SLArgs a) {
+  const int n = a.n_grid;
+  const long long V = (long long)n * n * n;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int jx = (int)(v % n), jy = (int)((v / n) % n), jz = (int)(v / ((long long)n * n));
+  const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v];
+  const double s = a.s;
+  // RK2 characteristics (Sec. 3): X* = x - dt v(x), X = x - dt/2 (v(x) + v(X*)).
+  const double* const vel[3] = {a.vx, a.vy, a.vz};
+  RC vs[3];
+  interp_pt<RC, 3>(vel, jx - s * vx, jy - s * vy, jz - s * vz, n, vs);
+  const double Xx = jx - 0.5 * s * (vx + (double)vs[0]);
+  const double Xy = jy - 0.5 * s * (vy + (double)vs[1]);
+  const double Xz = jz - 0.5 * s * (vz + (double)vs[2]);
+  const double* const fl[7] = {a.p, a.i, a.n, a.g, a.w, a.f, a.div};
+  RC qx[7];
+  interp_pt<RC, 7>(fl, Xx, Xy, Xz, n, qx);
+  // Heun with g(nu, x) = -nu div v(x).
+  const RC dt = RC(a.dt);
+  const RC dX = qx[6];
+  const RC d0 = RC(a.div[v]);
+  double* const outs[5] = {a.po, a.io, a.no, a.go, a.wo};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const RC qt = qx[k];
+    const RC g0 = -qt * dX;
+    const RC qs = qt + dt * g0;
+    const RC gs = -qs * d0;
+    outs[k][v] = (double)(qt + RC(0.5) * dt * (g0 + gs));
+  }
+  a.fo[v] = (double)qx[5];
+}
+
+template <typename RC>
+void launch_sl(const SLArgs& a, hipStream_t st) {
+  const long long V = (long long)a.n_grid * a.n_grid * a.n_grid;
+  hipLaunchKernelGGL(k_sl<RC>, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, a);
+}
+template void launch_sl<double>(const SLArgs&, hipStream_t);
+template void launch_sl<float>(const SLArgs&, hipStream_t);
+
+__global__ void k_interp(int n, const double* q, const double* jx, const double* jy, const double* jz,
+                         long long count, double* out) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const double* const f[1] = {q};
+  double r[1];
+  interp_pt<double, 1>(f, jx[k], jy[k], jz[k], n, r);
+  out[k] = r[0];
+}
+
+void launch_interp(int n, const double* q, const double* jx, const double* jy, const double* jz,
+                   long long count, double* out, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_interp, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, n, q, jx, jy, jz,
+                     count, out);
+}
+
+// ------------------------------------------------------------ Krylov vectors
+struct SpecIdx {
+  int lgh, lgn, hmask, nmask, n;
+  __device__ __forceinline__ void decode(long long e, int& kx, int& ky, int& kz) const {
+    kx = (int)(e & hmask);
+    const int iy = (int)((e >> lgh) & nmask);
+    const int iz = (int)(e >> (lgh + lgn));
+    ky = iy < n / 2 ? iy : (iy == n / 2 ? 0 : iy - n);
+    kz = iz < n / 2 ? iz : (iz == n / 2 ? 0 : iz - n);
+  }
+};
+
+static inline SpecIdx make_idx(int n) {
+  int lgn = 0;
+  while ((1 << lgn) < n) ++lgn;
+  return SpecIdx{lgn - 1, lgn, n / 2 - 1, n - 1, n};
+}
+
+template <typename R, int NC>
+__device__ __forceinline__ void apply_prec(const cplx<R> (&r)[NC], cplx<R> (&z)[NC], int kx, int ky, int kz,
+                                           const CoefScalars* cs, const PrecConsts& pc) {
+  const double w2 = (double)kx * kx + (double)ky * ky + (double)kz * kz;
+  if constexpr (NC == 1) {
+    const R s = R(1.0 / (1.0 + pc.h * cs->Kbar * w2));
+    z[0] = cscale(r[0], s);
+  } else {
+    const double a = cs->etabar + cs->mubar * w2;
+    if (a > 0.0) {
+      const double c = cs->lambar + cs->mubar;
+      const R ia = R(1.0 / a);
+      const R f = R(c / (a + c * w2));
+      const R wk[3] = {R(kx), R(ky), R(kz)};
+      cplx<R> wr;
+      wr.x = wk[0] * r[0].x + wk[1] * r[1].x + wk[2] * r[2].x;
+      wr.y = wk[0] * r[0].y + wk[1] * r[1].y + wk[2] * r[2].y;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        z[b].x = (r[b].x - f * wk[b] * wr.x) * ia;
+        z[b].y = (r[b].y - f * wk[b] * wr.y) * ia;
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) z[b] = czero<R>();
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ double wdot(cplx<R> a, cplx<R> b, int kx) {
+  const double d = (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+  return kx == 0 ? d : 2.0 * d;
+}
+
+// r = b - ax (ax nullable); bb = ||b||^2, rr = ||r||^2 (Parseval-weighted).
+// Without screening (singular elasticity) the mean mode of b is dropped.
+template <typename R, int NC>
+__global__ void __launch_bounds__(kRedThreads) k_residual(KrylovArgs a, SpecIdx ix, cplx<float>* r32) {
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  const cplx<R>* b = static_cast<const cplx<R>*>(a.b);
+  const cplx<R>* ax = static_cast<const cplx<R>*>(a.ax);
+  cplx<R>* r = static_cast<cplx<R>*>(a.r);
+  double acc[2] = {0.0, 0.0};
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
+       e += (long long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    ix.decode(e, kx, ky, kz);
+    const bool drop = a.pc.singular && e == 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const long long k = e + c * S;
+      const cplx<R> bv = drop ? czero<R>() : b[k];
+      const cplx<R> rv = ax ? csub(bv, ax[k]) : bv;
+      r[k] = rv;
+      if (r32) r32[k] = {float(rv.x), float(rv.y)};
+      acc[0] += wdot(bv, bv, kx);
+      acc[1] += wdot(rv, rv, kx);
+    }
+  }
+  if (block_partials<2>(acc, a.partials, &a.sv->counter)) {
+    double tot[2];
+    final_sums<2>(tot, a.partials, &a.sv->counter);
+    if (threadIdx.x == 0) {
+      a.sv->bb = tot[0];
+      a.sv->rr = tot[1];
+      a.sv->it = 0;
+      a.sv->done = 0;
+      a.sv->conv = 0;
+      a.sv->bad = (isfinite(tot[0]) && isfinite(tot[1])) ? 0 : 1;
+    }
+  }
+}
+
+// Crank-Nicolson start: x0 = c, b = c + h Dc, r = b - (c - h Dc).
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_cn_residual(KrylovArgs a, SpecIdx ix, const cplx<R>* c,
+                                                              const cplx<R>* dc) {
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  cplx<R>* b = static_cast<cplx<R>*>(a.b);
+  cplx<R>* r = static_cast<cplx<R>*>(a.r);
+  const R h = R(a.pc.h);
+  double acc[2] = {0.0, 0.0};
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
+       e += (long long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    ix.decode(e, kx, ky, kz);
+    const cplx<R> cv = c[e], dv = dc[e];
+    const cplx<R> bv = {cv.x + h * dv.x, cv.y + h * dv.y};
+    const cplx<R> av = {cv.x - h * dv.x, cv.y - h * dv.y};
+    const cplx<R> rv = csub(bv, av);
+    b[e] = bv;
+    r[e] = rv;
+    acc[0] += wdot(bv, bv, kx);
+    acc[1] += wdot(rv, rv, kx);
+  }
+  if (block_partials<2>(acc, a.partials, &a.sv->counter)) {
+    double tot[2];
+    final_sums<2>(tot, a.partials, &a.sv->counter);
+    if (threadIdx.x == 0) {
+      a.sv->bb = tot[0];
+      a.sv->rr = tot[1];
+      a.sv->it = 0;
+      a.sv->done = 0;
+      a.sv->conv = 0;
+      a.sv->bad = (isfinite(tot[0]) && isfinite(tot[1])) ? 0 : 1;
+    }
+  }
+}
+
+template <typename R, int NC>
+__global__ void __launch_bounds__(kRedThreads) k_pcg_start(KrylovArgs a, SpecIdx ix, int zero_x) {
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  const cplx<R>* r = static_cast<const cplx<R>*>(a.r);
+  cplx<R>* p = static_cast<cplx<R>*>(a.p);
+  cplx<R>* x = static_cast<cplx<R>*>(a.x);
+  double acc[1] = {0.0};
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
+       e += (long long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    ix.decode(e, kx, ky, kz);
+    cplx<R> rv[NC], zv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) rv[c] = r[e + c * S];
+    apply_prec<R, NC>(rv, zv, kx, ky, kz, a.cs, a.pc);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      p[e + c * S] = zv[c];
+      if (zero_x) x[e + c * S] = czero<R>();
+      acc[0] += wdot(rv[c], zv[c], kx);
+    }
+  }
+  if (block_partials<1>(acc, a.partials, &a.sv->counter)) {
+    double tot[1];
+    final_sums<1>(tot, a.partials, &a.sv->counter);
+    if (threadIdx.x == 0) {
+      a.sv->rho = tot[0];
+      a.sv->it = 0;
+      a.sv->conv = 0;
+      const bool ok = isfinite(tot[0]) && tot[0] > 0.0;
+      a.sv->bad = ok ? 0 : 1;
+      a.sv->done = ok ? 0 : 1;
+    }
+  }
+}
+
+template <typename R, int NC>
+__global__ void __launch_bounds__(kRedThreads) k_pcg_pq(KrylovArgs a, SpecIdx ix) {
+  if (a.sv->done) return;
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  const cplx<R>* p = static_cast<const cplx<R>*>(a.p);
+  const cplx<R>* q = static_cast<const cplx<R>*>(a.q);
+  double acc[1] = {0.0};
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int kx = (int)(e & ix.hmask);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[0] += wdot(p[e + c * S], q[e + c * S], kx);
+  }
+  if (block_partials<1>(acc, a.partials, &a.sv->counter)) {
+    double tot[1];
+    final_sums<1>(tot, a.partials, &a.sv->counter);
+    if (threadIdx.x == 0) {
+      a.sv->pq = tot[0];
+      if (!(isfinite(tot[0]) && tot[0] > 0.0)) {
+        a.sv->bad = 1;
+        a.sv->done = 1;
+      } else {
+        a.sv->alpha = a.sv->rho / tot[0];
+      }
+    }
+  }
+}
+
+template <typename R, int NC>
+__global__ void __launch_bounds__(kRedThreads) k_pcg_update(KrylovArgs a, SpecIdx ix) {
+  if (a.sv->done) return;
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  const R alpha = R(a.sv->alpha);
+  cplx<R>* x = static_cast<cplx<R>*>(a.x);
+  cplx<R>* r = static_cast<cplx<R>*>(a.r);
+  const cplx<R>* p = static_cast<const cplx<R>*>(a.p);
+  const cplx<R>* q = static_cast<const cplx<R>*>(a.q);
+  double acc[2] = {0.0, 0.0};
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
+       e += (long long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    ix.decode(e, kx, ky, kz);
+    cplx<R> rv[NC], zv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const long long k = e + c * S;
+      const cplx<R> pv = p[k], qv = q[k];
+      cplx<R> xv = x[k];
+      xv.x += alpha * pv.x;
+      xv.y += alpha * pv.y;
+      x[k] = xv;
+      cplx<R> rr = r[k];
+      rr.x -= alpha * qv.x;
+      rr.y -= alpha * qv.y;
+      r[k] = rr;
+      rv[c] = rr;
+    }
+    apply_prec<R, NC>(rv, zv, kx, ky, kz, a.cs, a.pc);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      acc[0] += wdot(rv[c], rv[c], kx);
+      acc[1] += wdot(rv[c], zv[c], kx);
+    }
+  }
+  if (block_partials<2>(acc, a.partials, &a.sv->counter)) {
+    double tot[2];
+    final_sums<2>(tot, a.partials, &a.sv->counter);
+    if (threadIdx.x == 0) {
+      SolveScalars* sv = a.sv;
+      sv->it += 1;
+      sv->rr = tot[0];
+      if (!(isfinite(tot[0]) && isfinite(tot[1]))) {
+        sv->bad = 1;
+        sv->done = 1;
+      } else if (!a.fixed && tot[0] <= a.thr2) {
+        sv->conv = 1;
+        sv->done = 1;
+      } else if (sv->it >= a.limit) {
+        sv->conv = a.fixed ? 1 : 0;
+        sv->done = 1;
+      } else {
+        sv->beta = tot[1] / sv->rho;
+        sv->rho = tot[1];
+      }
+    }
+  }
+}
+
+template <typename R, int NC>
+__global__ void __launch_bounds__(256) k_pcg_pupdate(KrylovArgs a, SpecIdx ix) {
+  if (a.sv->done) return;
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  const R beta = R(a.sv->beta);
+  const cplx<R>* r = static_cast<const cplx<R>*>(a.r);
+  cplx<R>* p = static_cast<cplx<R>*>(a.p);
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S) return;
+  int kx, ky, kz;
+  ix.decode(e, kx, ky, kz);
+  cplx<R> rv[NC], zv[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) rv[c] = r[e + c * S];
+  apply_prec<R, NC>(rv, zv, kx, ky, kz, a.cs, a.pc);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const cplx<R> pv = p[e + c * S];
+    p[e + c * S] = {zv[c].x + beta * pv.x, zv[c].y + beta * pv.y};
+  }
+}
+
+template <typename R, int NC>
+__global__ void __launch_bounds__(256) k_precond(KrylovArgs a, SpecIdx ix, const cplx<R>* in, cplx<R>* out) {
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S) return;
+  int kx, ky, kz;
+  ix.decode(e, kx, ky, kz);
+  cplx<R> rv[NC], zv[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) rv[c] = in[e + c * S];
+  apply_prec<R, NC>(rv, zv, kx, ky, kz, a.cs, a.pc);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[e + c * S] = zv[c];
+}
+
+#define TUMOR_NC_DISPATCH(nc, BODY)                    \
+  if ((nc) == 1) { constexpr int NCC = 1; BODY; }      \
+  else { constexpr int NCC = 3; BODY; }
+
+static inline long long spec_count(int n) { return (long long)n * n * (n / 2); }
+
+template <typename R>
+void launch_residual(const KrylovArgs& a, void* r32, hipStream_t st) {
+  const SpecIdx ix = make_idx(a.n);
+  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_residual<R, NCC>), dim3(red_blocks(spec_count(a.n))),
+                                                 dim3(kRedThreads), 0, st, a, ix,
+                                                 static_cast<cplx<float>*>(r32)));
+}
+
+template <typename R>
+void launch_cn_residual(const KrylovArgs& a, const void* c, const void* dc, hipStream_t st) {
+  const SpecIdx ix = make_idx(a.n);
+  hipLaunchKernelGGL((k_cn_residual<R>), dim3(red_blocks(spec_count(a.n))), dim3(kRedThreads), 0, st, a, ix,
+                     static_cast<const cplx<R>*>(c), static_cast<const cplx<R>*>(dc));
+}
+
+template <typename R>
+void launch_pcg_start(const KrylovArgs& a, int zero_x, hipStream_t st) {
+  const SpecIdx ix = make_idx(a.n);
+  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_start<R, NCC>), dim3(red_blocks(spec_count(a.n))),
+                                                 dim3(kRedThreads), 0, st, a, ix, zero_x));
+}
+
+template <typename R>
+void launch_pcg_pq(const KrylovArgs& a, hipStream_t st) {
+  const SpecIdx ix = make_idx(a.n);
+  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_pq<R, NCC>), dim3(red_blocks(spec_count(a.n))),
+                                                 dim3(kRedThreads), 0, st, a, ix));
+}
+
+template <typename R>
+void launch_pcg_update(const KrylovArgs& a, hipStream_t st) {
+  const SpecIdx ix = make_idx(a.n);
+  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_update<R, NCC>), dim3(red_blocks(spec_count(a.n))),
+                                                 dim3(kRedThreads), 0, st, a, ix));
+}
+
+template <typename R>
+void launch_pcg_pupdate(const KrylovArgs& a, hipStream_t st) {
+  const SpecIdx ix = make_idx(a.n);
+  const long long S = spec_count(a.n);
+  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_pupdate<R, NCC>), dim3((unsigned)((S + 255) / 256)),
+                                                 dim3(256), 0, st, a, ix));
+}
+
+template <typename R>
+void launch_precond(const KrylovArgs& a, const void* in, void* out, hipStream_t st) {
+  const SpecIdx ix = make_idx(a.n);
+  const long long S = spec_count(a.n);
+  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_precond<R, NCC>), dim3((unsigned)((S + 255) / 256)),
+                                                 dim3(256), 0, st, a, ix, static_cast<const cplx<R>*>(in),
+                                                 static_cast<cplx<R>*>(out)));
+}
+
+#define TUMOR_INST_KRYLOV(R)                                                               \
+  template void launch_residual<R>(const KrylovArgs&, void*, hipStream_t);                 \
+  template void launch_cn_residual<R>(const KrylovArgs&, const void*, const void*, hipStream_t); \
+  template void launch_pcg_start<R>(const KrylovArgs&, int, hipStream_t);                  \
+  template void launch_pcg_pq<R>(const KrylovArgs&, hipStream_t);                          \
+  template void launch_pcg_update<R>(const KrylovArgs&, hipStream_t);                      \
+  template void launch_pcg_pupdate<R>(const KrylovArgs&, hipStream_t);                     \
+  template void launch_precond<R>(const KrylovArgs&, const void*, void*, hipStream_t);
+TUMOR_INST_KRYLOV(double)
+TUMOR_INST_KRYLOV(float)
+
+// -------------------------------------------------------------- conversions
+__global__ void k_add32to64(double* x, const float* y, long long count) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) x[k] += (double)y[k];
+}
+void launch_add32to64(void* x64, const void* x32, long long count, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_add32to64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                     static_cast<double*>(x64), static_cast<const float*>(x32), count);
+}
+
+__global__ void k_f32_to_f64(const float* in, double* out, long long count) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) out[k] = (double)in[k];
+}
+void launch_f32_to_f64(const float* in, double* out, long long count, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, in, out, count);
+}
+
+__global__ void k_scale64(double* x, double s, long long count) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) x[k] *= s;
+}
+void launch_scale64(double* x, double s, long long count, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_scale64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, x, s, count);
+}
+
+}  // namespace tumor

@@ -1,0 +1,123 @@
+"""GPU parity of the building blocks against the FP64 CPU oracle, through the C ABI.
+
+Each operator of the split step (spectral derivatives, diffusion operator,
+elasticity operator, both preconditioners, the elastic force, tricubic
+interpolation) is applied by libtumor and by the oracle to the same seeded
+fields and compared element by element.
+"""
+import numpy as np
+import pytest
+
+import paper_1810_05370_amd as tm
+import synthetic
+from gpu_common import need_gpu, rel_l2, say, to_dev
+from oracle import reaction as rx
+from oracle import solvers, transport
+from oracle.model import gaussian_basis
+from oracle.spectral import Grid
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12     # single-operator FP64 relative L2 tolerance (a few FFT round-offs)
+TOL32 = 2e-6      # the same in FP32 (mixed precision kernels)
+
+
+def _sim(n, precision="fp64", seed=0):
+    torch = need_gpu()
+    inp = synthetic.workload_inputs("c1", n=n)
+    P = synthetic.params()
+    sim = tm.from_inputs(inp, P, precision=precision)
+    return torch, sim, inp, P
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_spectral_derivatives(n, precision):
+    torch, sim, inp, P = _sim(n, precision)
+    g = Grid(n)
+    c = synthetic.random_field(n, 21, 1.0)
+    tol = TOL64 if precision == "fp64" else TOL32
+    for a, name in enumerate(("deriv_x", "deriv_y", "deriv_z")):
+        say(f"deriv n={n} {precision} {name}")
+        got = sim.apply_op(name, to_dev(torch, c)).cpu().numpy()
+        assert rel_l2(got, g.deriv(c, a)) < tol, name
+    sim.close()
+
+
+@pytest.mark.parametrize("n", [16, 32, 64])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_diffusion_and_cn_preconditioner(n, precision):
+    torch, sim, inp, P = _sim(n, precision)
+    g = Grid(n)
+    K = sim.get("K").cpu().numpy()
+    z = np.zeros((n, n, n))
+    p0 = gaussian_basis(g, inp["centers"], inp["sigmas"], inp["weights"])
+    co = rx.refresh(P, p0, z, z, inp["gm"], inp["wm"], inp["csf"])
+    assert rel_l2(K, co["K"]) < 1e-15
+    c = synthetic.random_field(n, 22, 1.5)
+    tol = TOL64 if precision == "fp64" else TOL32
+    say(f"diffusion n={n} {precision}")
+    got = sim.apply_op("diffusion", to_dev(torch, c)).cpu().numpy()
+    assert rel_l2(got, solvers.diffusion_op(g, K, c)) < tol * 10
+    got = sim.apply_op("cn_precond", to_dev(torch, c)).cpu().numpy()
+    assert rel_l2(got, solvers.cn_precond(g, K.mean(), 0.01, c)) < tol
+    sim.close()
+
+
+@pytest.mark.parametrize("n", [16, 32, 64])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_elasticity_operator_and_preconditioner(n, precision):
+    torch, sim, inp, P = _sim(n, precision)
+    g = Grid(n)
+    mu, lam, eta = (sim.get(k).cpu().numpy() for k in ("mu", "lambda", "eta"))
+    u = synthetic.random_field(n, 23, 1.5, ncomp=3)
+    tol = TOL64 if precision == "fp64" else TOL32
+    say(f"elasticity n={n} {precision}")
+    got = sim.apply_op("elasticity", to_dev(torch, u)).cpu().numpy()
+    assert rel_l2(got, solvers.elasticity_op(g, mu, lam, eta, u)) < tol * 10
+    got = sim.apply_op("elast_precond", to_dev(torch, u)).cpu().numpy()
+    ref = solvers.elasticity_precond(g, mu.mean(), lam.mean(), eta.mean(), u)
+    assert rel_l2(got, ref) < tol
+    sim.close()
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_force(n):
+    torch, sim, inp, P = _sim(n)
+    g = Grid(n)
+    tau = 0.5 * np.abs(synthetic.random_field(n, 24, 2.0))
+    say(f"force n={n}")
+    got = sim.apply_op("force", to_dev(torch, tau)).cpu().numpy()
+    assert rel_l2(got, rx.elastic_force(g, P["zeta"], tau, np.zeros_like(tau))) < TOL64
+    sim.close()
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_interpolation_matches_oracle_including_wraparound(n):
+    torch, sim, inp, P = _sim(n)
+    q = synthetic.random_field(n, 25, 1.0)
+    rng = np.random.default_rng(4)
+    pts = rng.uniform(-2.5 * n, 3.5 * n, size=(3, 5000))
+    pts[:, :10] = np.round(pts[:, :10])                 # exact nodes
+    say(f"interp n={n}")
+    got = sim.interp(to_dev(torch, q), *(to_dev(torch, pts[a]) for a in range(3))).cpu().numpy()
+    ref = transport.interp(q, pts[0], pts[1], pts[2])
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.abs(q).max()
+    sim.close()
+
+
+def test_initial_condition_and_coefficients():
+    n = 32
+    torch, sim, inp, P = _sim(n)
+    g = Grid(n)
+    p0 = gaussian_basis(g, inp["centers"], inp["sigmas"], inp["weights"])
+    say("initial condition")
+    assert np.max(np.abs(sim.get("p").cpu().numpy() - p0)) < 1e-15
+    assert np.all(sim.get("o").cpu().numpy() == P["o_heal"])
+    for k in ("i", "n", "l"):
+        assert not sim.get(k).cpu().numpy().any()
+    z = np.zeros((n, n, n))
+    co = rx.refresh(P, p0, z, z, inp["gm"], inp["wm"], inp["csf"])
+    for k, ck in (("K", "K"), ("rho", "rho_p"), ("mu", "mu"), ("lambda", "lam"), ("eta", "eta")):
+        assert rel_l2(sim.get(k).cpu().numpy(), co[ck]) < 1e-15, k
+    sim.close()
