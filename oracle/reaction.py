@@ -13,7 +13,8 @@ Model terms (Sec. 2.3, Eq. e:gog and the rate laws that follow it):
 
 Readings (the paper says only that the reaction equations are solved
 explicitly, Sec. 3):
-* H(x) = (1 + tanh(x / eps)) / 2, the smoothed Heaviside, eps = 0.01;
+* H(x) = (1 + tanh(x / eps)) / 2, the smoothed Heaviside, eps = 0.01,
+  evaluated as 1 / (1 + exp(-2 x / eps)) (same function, no cancellation);
 * all rates are frozen at the start of the sub-step; the logistic terms use
   their exact flow Lambda(y, r, dt) = y e^{r dt} / (1 + y (e^{r dt} - 1)),
   the linear transfer, death, supply and edema terms are forward Euler;
@@ -35,7 +36,14 @@ import numpy as np
 
 
 def heaviside(x, eps):
-    return 0.5 * (1.0 + np.tanh(x / eps))
+    """Smoothed Heaviside (1 + tanh(x/eps))/2, evaluated as 1/(1 + exp(-2x/eps)).
+
+    The two forms are equal in exact arithmetic; the second avoids the
+    cancellation of 1 + tanh(x/eps) for x/eps << 0, where the rates it gates
+    (alpha, h) are tiny but still drive the invasive and necrotic fields.
+    """
+    with np.errstate(over="ignore"):
+        return 1.0 / (1.0 + np.exp(-2.0 * np.asarray(x, dtype=np.float64) / eps))
 
 
 def logistic_flow(y, r, t):

@@ -45,6 +45,16 @@ def test_logistic_step_matches_ode_integration():
     assert np.allclose(q, closed, rtol=1e-12)
 
 
+def test_heaviside_is_the_smoothed_step_without_cancellation():
+    eps = 0.01
+    x = np.linspace(-0.05, 0.05, 101)
+    assert np.allclose(rx.heaviside(x, eps), 0.5 * (1 + np.tanh(x / eps)), rtol=0, atol=1e-15)
+    # deep in the tail the value keeps full relative accuracy: (1+tanh(y))/2 = e^{2y}/(1+e^{2y})
+    y = -15.0
+    assert rx.heaviside(y * eps, eps) == pytest.approx(np.exp(2 * y) / (1 + np.exp(2 * y)), rel=1e-14)
+    assert rx.heaviside(-10.0, eps) == 0.0 and rx.heaviside(10.0, eps) == 1.0
+
+
 def test_oxygen_factor_matches_the_piecewise_definition():
     P = _P()
     o_inv, o_mit = P["o_inv"], 0.5 * (P["o_hyp"] + P["o_inv"])
