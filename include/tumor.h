@@ -203,7 +203,7 @@ int tumor_apply_op(tumor_ctx* ctx, int32_t op, const double* in, double* out);
 
 /* Semi-Lagrangian interpolation: out[k] = tricubic Lagrange interpolant of
  * the periodic field q at grid-index coordinates (jx[k], jy[k], jz[k]),
- * k < count (device arrays, count <= N^3). */
+ * k < count (device arrays, 0 <= count < 2^40). */
 int tumor_interp(tumor_ctx* ctx, const double* q, const double* jx, const double* jy,
                  const double* jz, int64_t count, double* out);
 

@@ -1148,7 +1148,7 @@ int tumor_apply_op(tumor_ctx* ctx, int32_t op, const double* in, double* out) {
 int tumor_interp(tumor_ctx* ctx, const double* q, const double* jx, const double* jy, const double* jz,
                  int64_t count, double* out) {
   if (!ctx) return einval("ctx is NULL");
-  if (count < 0 || count > ctx->V) return einval("count out of range");
+  if (count < 0 || count > (int64_t(1) << 40)) return einval("count out of range");
   if (count > 0 && (!q || !jx || !jy || !jz || !out)) return einval("NULL array");
   return guarded([&]() -> int {
     tumor::launch_interp(ctx->n, q, jx, jy, jz, count, out, ctx->st);

@@ -82,7 +82,9 @@ static inline int red_blocks(long long count) {
 }
 
 // ------------------------------------------------------ reaction + refresh
-__device__ __forceinline__ double heav(double x, double eps) { return 0.5 * (1.0 + tanh(x / eps)); }
+// Smoothed Heaviside (1 + tanh(x/eps))/2 in its cancellation-free form
+// 1/(1 + exp(-2x/eps)); exp overflow gives exactly 0.
+__device__ __forceinline__ double heav(double x, double eps) { return 1.0 / (1.0 + exp(-2.0 * x / eps)); }
 
 __device__ __forceinline__ double logistic_flow(double y, double r, double t) {
   const double e = exp(r * t);
@@ -282,19 +284,21 @@ template void launch_sl<float>(const SLArgs&, hipStream_t);
 
 __global__ void k_interp(int n, const double* q, const double* jx, const double* jy, const double* jz,
                          long long count, double* out) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  const double* const f[1] = {q};
-  double r[1];
-  interp_pt<double, 1>(f, jx[k], jy[k], jz[k], n, r);
-  out[k] = r[0];
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (long long)gridDim.x * blockDim.x) {
+    const double* const f[1] = {q};
+    double r[1];
+    interp_pt<double, 1>(f, jx[k], jy[k], jz[k], n, r);
+    out[k] = r[0];
+  }
 }
 
 void launch_interp(int n, const double* q, const double* jx, const double* jy, const double* jz,
                    long long count, double* out, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_interp, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, n, q, jx, jy, jz,
-                     count, out);
+  long long blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_interp, dim3((unsigned)blocks), dim3(256), 0, st, n, q, jx, jy, jz, count, out);
 }
 
 // ------------------------------------------------------------ Krylov vectors

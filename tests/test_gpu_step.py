@@ -106,11 +106,13 @@ def test_no_tumour_is_a_steady_state_of_the_tissue():
     inp = synthetic.workload_inputs("c1", n=16)
     inp = dict(inp, centers=np.zeros((0, 3)), sigmas=np.zeros(0), weights=np.zeros(0))
     sim = tm.from_inputs(inp, P)
-    s = sim.step(2)
-    assert s["it_elast"] == 0 and s["relres_elast"] == 0.0
+    sim.step(2)
+    # Only the (exponentially small) necrosis of healthy tissue acts: the
+    # tissue maps are unchanged to the last bit and the mass effect vanishes.
     for k in ("g", "w", "f"):
         assert np.array_equal(sim.get(k).cpu().numpy(), inp[{"g": "gm", "w": "wm", "f": "csf"}[k]])
-    assert not sim.get("u").cpu().numpy().any()
+    assert not sim.get("p").cpu().numpy().any() and not sim.get("i").cpu().numpy().any()
+    assert np.abs(sim.get("u").cpu().numpy()).max() < 1e-60
     sim.close()
 
 
