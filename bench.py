@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput of the operator-split multispecies glioblastoma step on one MI355X.
+
+A "step" is one whole split step (transport, three Crank-Nicolson solves,
+reaction/oxygen/edema, coefficient refresh, force and the elasticity solve)
+on the 256^3 synthetic workload (three tumour seeds, tissue maps smoothed
+over 8 cells, dt = 0.01, PCG rtol 1e-8) in the mixed precision.  The FP64
+form of the same workload is timed as well and reported beside it.
+
+Prints one JSON line.  value = split steps per second (inputs resident in
+HBM).  roofline = the dominant kernel class of the timed steps (by HIP-event
+time), its algorithmic bytes per launch over its mean launch duration,
+measured live with events on the library's stream.  cpu_baseline = the CPU
+oracle timed on a bounded sample of the same step (see --help).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "split time steps/s at 256³ (fwd, fwd+adjoint), mixed vs FP64 on one GPU"
+HBM_PEAK_GBS = 8000.0
+CLASSES = ("col64", "col32", "xelast64", "xelast32", "xdiff64", "xdiff32", "xother", "sl", "react",
+           "krylov64", "krylov32")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_form(tm, torch, inp, P, precision, steps, warmup):
+    """Warm up, find the dominant kernel class, then time `steps` steps."""
+    sim = tm.from_inputs(inp, P, precision=precision)
+    for c in CLASSES:
+        sim.kernel_timer(c, True)
+    wstats = []
+    for k in range(warmup):
+        wstats.append(sim.step(1))
+        log(f"[{precision}] warmup step {k + 1}/{warmup}: elast it {wstats[-1]['it_elast']}"
+            f" (outer {wstats[-1]['outer_elast']}), diff it {wstats[-1]['it_diff']}")
+    prof = {c: sim.kernel_timer_read(c) for c in CLASSES}
+    dominant = max(CLASSES, key=lambda c: prof[c]["ms"])
+    for c in CLASSES:
+        sim.kernel_timer(c, c == dominant)       # only the dominant class inside the timed region
+    stream = sim.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(steps):
+        stats.append(sim.step(1))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    dom = sim.kernel_timer_read(dominant)
+    log(f"[{precision}] {steps} steps: wall {wall:.3f} s, events {gpu_ms / 1e3:.3f} s;"
+        f" dominant {dominant}: {dom['launches']} launches, {dom['ms']:.1f} ms")
+    sim.close()
+    return dict(wall=wall, gpu_ms=gpu_ms, stats=stats, warm_profile=prof, dominant=dominant, dom=dom)
+
+
+def roofline(dom):
+    if dom["launches"] == 0 or dom["ms"] <= 0:
+        return None
+    per_launch = dom["bytes"] / dom["launches"]
+    mean_ms = dom["ms"] / dom["launches"]
+    achieved = per_launch / (mean_ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                kernel=None, bytes_per_launch=per_launch, mean_launch_ms=round(mean_ms, 5))
+
+
+def cpu_baseline(inp, P, iters_e, iters_d):
+    """Time the FP64 CPU oracle on a bounded sample of one 256^3 step.
+
+    Sample: one elasticity operator apply + one elasticity preconditioner
+    (one PCG iteration's operator work), one CN diffusion apply + its
+    preconditioner, the reaction/oxygen/edema/refresh sub-steps on the whole
+    grid, the force, and the semi-Lagrangian interpolations on 1/16 of the
+    grid (16 z-planes).  The step time is reconstructed as
+    SL * 16 + reaction + force + (n_e + 1) * elasticity-iteration
+    + (n_d + 1) * CN-iteration, with n_e, n_d the per-step iteration counts
+    of the same workload (FP64 run).
+    """
+    import numpy as np
+
+    from oracle import model, reaction as rx, solvers, transport
+    from oracle.spectral import Grid
+
+    n = inp["n"]
+    t_all = time.perf_counter()
+    st = model.init_state(P, n, inp["wm"], inp["gm"], inp["csf"], inp["centers"], inp["sigmas"], inp["weights"])
+    g = st.grid
+    co = st.coef
+    F = st.f
+    rng = np.random.default_rng(7)
+    u = 1e-3 * rng.standard_normal((3, n, n, n))
+
+    t = time.perf_counter()
+    Au = solvers.elasticity_op(g, co["mu"], co["lam"], co["eta"], u)
+    solvers.elasticity_precond(g, co["mubar"], co["lambar"], co["etabar"], Au)
+    t_e = time.perf_counter() - t
+    del Au
+    t = time.perf_counter()
+    q = solvers.cn_matrix(g, co["K"], 0.01, F["p"])
+    solvers.cn_precond(g, co["Kbar"], 0.01, q)
+    t_d = time.perf_counter() - t
+    del q
+    t = time.perf_counter()
+    z = np.zeros_like(F["p"])
+    p1, i1, n1, g1, w1 = rx.species_reaction(P, 0.01, F["p"], F["i"], F["n"], F["g"], F["w"], F["o"],
+                                             co["rho_p"], co["rho_i"], z)
+    o1 = rx.oxygen_reaction(P, 0.01, F["o"], p1, g1, w1)
+    rx.edema_reaction(P, 0.01, F["l"], i1)
+    rx.refresh(P, p1, i1, n1, g1, w1, F["f"])
+    t_r = time.perf_counter() - t
+    t = time.perf_counter()
+    b = rx.elastic_force(g, P["zeta"], p1, n1)
+    v = u / 0.01
+    delta = g.div(v)
+    t_f = time.perf_counter() - t
+    del b, o1
+    slab = n // 16
+    t = time.perf_counter()
+    r = np.arange(n, dtype=np.float64)
+    jz, jy, jx = np.meshgrid(r[:slab], r, r, indexing="ij")
+    s = 0.01 / g.h
+    xs = (jx - s * v[0, :slab], jy - s * v[1, :slab], jz - s * v[2, :slab])
+    vs = [transport.interp(v[a], *xs) for a in range(3)]
+    X = tuple(j - 0.5 * s * (v[a, :slab] + vs[a]) for a, j in enumerate((jx, jy, jz)))
+    for name in ("p", "i", "n", "g", "w", "f"):
+        transport.interp(F[name], *X)
+    transport.interp(delta, *X)
+    t_sl = (time.perf_counter() - t) * (n / slab)
+    step_s = t_sl + t_r + t_f + (iters_e + 1) * t_e + (iters_d + 3) * t_d
+    cores = len(os.sched_getaffinity(0))
+    log(f"cpu sample: elast iter {t_e:.2f} s, cn iter {t_d:.2f} s, reaction {t_r:.2f} s, force {t_f:.2f} s,"
+        f" SL (scaled) {t_sl:.2f} s; sample wall {time.perf_counter() - t_all:.1f} s")
+    return dict(value=round(1.0 / step_s, 6), unit="steps/s", cores=cores, kind="oracle",
+                sample=(f"FP64 NumPy/SciPy oracle at 256^3 on {cores} host threads (scipy.fft workers; NumPy "
+                        f"elementwise single-threaded): one elasticity apply+preconditioner ({t_e:.2f} s), one CN "
+                        f"apply+preconditioner ({t_d:.2f} s), reaction+refresh ({t_r:.2f} s), force+velocity "
+                        f"divergence ({t_f:.2f} s), SL interpolation on 16 of 256 z-planes scaled x16 "
+                        f"({t_sl:.2f} s); step = SL + reaction + force + (n_e+1) elasticity + (n_d+3) CN "
+                        f"iterations with n_e={iters_e:.1f}, n_d={iters_d:.1f} per step of the FP64 run"))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", help="synthetic workload name (default: the 256^3 case)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 form")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this implementation runs one simulation on exactly one GPU; "
+              "--gpus must be 1 (multi-GPU runs are not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("bench.py: --steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1810_05370_amd as tm
+    import synthetic
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    tm.load_library()
+    P = synthetic.params()
+    t = time.perf_counter()
+    inp = synthetic.workload_inputs(args.workload)
+    n = inp["n"]
+    log(f"inputs {args.workload} n={n} generated in {time.perf_counter() - t:.1f} s")
+    precision = inp["precision"]
+
+    main_run = run_form(tm, torch, inp, P, precision, args.steps, args.warmup)
+    ms_per_step = main_run["gpu_ms"] / args.steps
+    value = args.steps / (main_run["gpu_ms"] / 1e3)
+    extra = {}
+    fp64_run = None
+    if not args.no_fp64 and precision != "fp64":
+        torch.cuda.empty_cache()
+        fp64_run = run_form(tm, torch, inp, P, "fp64", args.steps, args.warmup)
+        v64 = args.steps / (fp64_run["gpu_ms"] / 1e3)
+        extra["fp64_steps_per_s"] = round(v64, 4)
+        extra["mixed_speedup_over_fp64"] = round(value / v64, 3)
+        rf = roofline(fp64_run["dom"])
+        if rf:
+            rf["kernel"] = fp64_run["dominant"]
+        extra["fp64_roofline"] = rf
+    it_e = [s["it_elast"] for s in main_run["stats"]]
+    extra["elasticity_iterations_per_step"] = it_e
+    extra["elasticity_outer_per_step"] = [s["outer_elast"] for s in main_run["stats"]]
+    extra["diffusion_iterations_last_step"] = main_run["stats"][-1]["it_diff"]
+    extra["warmup_kernel_ms"] = {c: round(v["ms"], 2) for c, v in main_run["warm_profile"].items() if v["ms"] > 0}
+    extra["wall_s"] = round(main_run["wall"], 4)
+    rl = roofline(main_run["dom"])
+    if rl:
+        rl["kernel"] = main_run["dominant"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        ref = fp64_run if fp64_run is not None else main_run
+        ne = sum(s["it_elast"] for s in ref["stats"]) / len(ref["stats"])
+        nd = sum(sum(s["it_diff"]) for s in ref["stats"]) / len(ref["stats"])
+        cpu = cpu_baseline(inp, P, ne, nd)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {n}^3 periodic grid, {precision} precision, full multispecies "
+                               f"split step (transport, CN diffusion of i/o/l, reaction, oxygen, edema, elasticity)",
+                   "n": n, "precision": precision, "dt": inp["dt"], "rtol": inp["rtol"],
+                   "tumour_seeds": int(len(inp["weights"])), "forward_only": True},
+        "roofline": rl,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

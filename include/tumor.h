@@ -214,6 +214,20 @@ int tumor_interp(tumor_ctx* ctx, const double* q, const double* jx, const double
  * array of 4 values, or NULL to clear.  TUMOR_EINVAL in the mixed precision. */
 int tumor_force_iterations(tumor_ctx* ctx, const int32_t* iters);
 
+/* Measurement hook: bracket every launch of one kernel class with HIP events
+ * on the context's stream and accumulate launches, elapsed milliseconds and
+ * the algorithmic HBM bytes of those launches (each input and output array
+ * counted once).  enable = 1 resets and starts, 0 stops.  Reading flushes
+ * pending events (it synchronises the stream). */
+enum {
+  TUMOR_K_COL64 = 0, TUMOR_K_COL32, TUMOR_K_XELAST64, TUMOR_K_XELAST32, TUMOR_K_XDIFF64,
+  TUMOR_K_XDIFF32, TUMOR_K_XOTHER, TUMOR_K_SL, TUMOR_K_REACT, TUMOR_K_KRYLOV64, TUMOR_K_KRYLOV32,
+  TUMOR_K_COUNT
+};
+int tumor_kernel_timer(tumor_ctx* ctx, int32_t kernel_class, int32_t enable);
+int tumor_kernel_timer_read(tumor_ctx* ctx, int32_t kernel_class, int64_t* launches, double* ms,
+                            double* bytes);
+
 void tumor_destroy(tumor_ctx* ctx);
 const char* tumor_last_error(void);
 int tumor_abi_version(void);

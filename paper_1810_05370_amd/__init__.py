@@ -35,6 +35,8 @@ FIELDS = {"p": 0, "i": 1, "n": 2, "o": 3, "l": 4, "g": 5, "w": 6, "f": 7, "u": 8
 OPS = {"deriv_x": 0, "deriv_y": 1, "deriv_z": 2, "diffusion": 3, "elasticity": 4,
        "elast_precond": 5, "cn_precond": 6, "force": 7}
 VECTOR_OPS = ("elasticity", "elast_precond", "force")
+KERNEL_CLASSES = {"col64": 0, "col32": 1, "xelast64": 2, "xelast32": 3, "xdiff64": 4, "xdiff32": 5,
+                  "xother": 6, "sl": 7, "react": 8, "krylov64": 9, "krylov32": 10}
 
 
 class TumorParams(ctypes.Structure):
@@ -99,6 +101,10 @@ def load_library(path: Optional[str] = None):
         "tumor_apply_op": (ctypes.c_int, [P, ctypes.c_int32, P, P]),
         "tumor_interp": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, P]),
         "tumor_force_iterations": (ctypes.c_int, [P, P]),
+        "tumor_kernel_timer": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32]),
+        "tumor_kernel_timer_read": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                                   ctypes.POINTER(ctypes.c_double),
+                                                   ctypes.POINTER(ctypes.c_double)]),
         "tumor_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
@@ -262,6 +268,17 @@ class Tumor:
         _check(self.lib.tumor_interp(self.ctx, _ptr(q), _ptr(pts[0]), _ptr(pts[1]), _ptr(pts[2]),
                                      pts[0].numel(), _ptr(out)))
         return out
+
+    def kernel_timer(self, name, enable=True):
+        _check(self.lib.tumor_kernel_timer(self.ctx, KERNEL_CLASSES[name], 1 if enable else 0))
+
+    def kernel_timer_read(self, name):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0)
+        b = ctypes.c_double(0)
+        _check(self.lib.tumor_kernel_timer_read(self.ctx, KERNEL_CLASSES[name], ctypes.byref(n),
+                                                ctypes.byref(ms), ctypes.byref(b)))
+        return dict(launches=n.value, ms=ms.value, bytes=b.value)
 
     def force_iterations(self, iters=None):
         if iters is None:

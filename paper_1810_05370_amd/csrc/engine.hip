@@ -91,6 +91,20 @@ int check_cfg(const tumor_config* c) {
   return TUMOR_OK;
 }
 
+constexpr int kMaxPend = 1024;
+
+// Event timing of one kernel class (measurement hook).
+struct KTimer {
+  int on;
+  int pending;
+  long long launches;
+  double ms;
+  double bytes;
+  hipEvent_t ev[2 * kMaxPend];
+  double pend_bytes[kMaxPend];
+  int pend_tag[kMaxPend];
+};
+
 }  // namespace
 
 struct tumor_ctx {
@@ -124,11 +138,54 @@ struct tumor_ctx {
   bool has_forced;
   tumor::RefreshConsts fc;
   tumor::ReactConsts rc;
+  KTimer* timers[TUMOR_K_COUNT];
+  int cur_tag;  // PCG iteration index of the launches being queued (-1 outside loops)
 };
 
 namespace {
 
 using Ctx = tumor_ctx;
+
+void timer_flush(Ctx& c, int cls, int valid_tag) {
+  KTimer* t = c.timers[cls];
+  if (!t || t->pending == 0) return;
+  HIPCHECK(hipEventSynchronize(t->ev[2 * t->pending - 1]));
+  for (int k = 0; k < t->pending; ++k) {
+    if (t->pend_tag[k] >= valid_tag) continue;  // launch skipped on the device (solve already done)
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, t->ev[2 * k], t->ev[2 * k + 1]));
+    t->ms += ms;
+    t->bytes += t->pend_bytes[k];
+    t->launches += 1;
+  }
+  t->pending = 0;
+}
+
+void timers_flush(Ctx& c, int valid_tag) {
+  for (int k = 0; k < TUMOR_K_COUNT; ++k) timer_flush(c, k, valid_tag);
+}
+
+// Launch f(), bracketed by events if the class is being timed.
+template <typename F>
+void timed(Ctx& c, int cls, double bytes, F&& f) {
+  KTimer* t = c.timers[cls];
+  if (!t || !t->on) {
+    f();
+    return;
+  }
+  if (t->pending == kMaxPend) timer_flush(c, cls, c.cur_tag < 0 ? 0x7fffffff : c.cur_tag);
+  HIPCHECK(hipEventRecord(t->ev[2 * t->pending], c.st));
+  f();
+  HIPCHECK(hipEventRecord(t->ev[2 * t->pending + 1], c.st));
+  t->pend_bytes[t->pending] = bytes;
+  t->pend_tag[t->pending] = c.cur_tag < 0 ? -1 : c.cur_tag;
+  t->pending++;
+}
+
+template <typename R>
+constexpr int kcls(int k64, int k32) {
+  return sizeof(R) == 8 ? k64 : k32;
+}
 
 void layout(Ctx& c, Carver& cv) {
   const long long V = c.V, S = c.S;
@@ -245,7 +302,14 @@ constexpr ColTerm TR(int s, double c = 1.0) { return ColTerm{s, SYM_RAW, c}; }
 
 template <typename R>
 void colp(Ctx& c, int axis, bool inv, const Prog& pr) {
-  tumor::launch_col_pass<R>(c.n, axis, inv, pr.p, pb<R>(c).tw, c.st);
+  bool used[tumor::kMaxCol] = {false};
+  for (int o = 0; o < pr.p.nout; ++o)
+    for (int q = 0; q < pr.p.nterm[o]; ++q) used[pr.p.term[o][q].src] = true;
+  int nin = 0;
+  for (int k = 0; k < tumor::kMaxCol; ++k) nin += used[k] ? 1 : 0;
+  const double bytes = double(nin + pr.p.nout) * double(c.V) * sizeof(R);
+  timed(c, kcls<R>(TUMOR_K_COL64, TUMOR_K_COL32), bytes,
+        [&] { tumor::launch_col_pass<R>(c.n, axis, inv, pr.p, pb<R>(c).tw, c.st); });
 }
 
 // Forward 3-D transform of coef_a * a (+ coef_b * b), physical FP64 -> spectral R.
@@ -256,7 +320,8 @@ void fwd3(Ctx& c, const double* a, const double* b, cplx<R>* out, double ca = 1.
   x.in(0, a).in(1, b);
   if (b) x.out(P.A[0], {T1(0, ca), T1(1, cb)});
   else x.out(P.A[0], {T1(0, ca)});
-  tumor::launch_xfwd<R>(c.n, to_x(x.p, 1.0), P.tw, c.st, true);
+  timed(c, TUMOR_K_XOTHER, double(b ? 2 : 1) * c.V * 8.0 + double(c.V) * sizeof(R),
+        [&] { tumor::launch_xfwd<R>(c.n, to_x(x.p, 1.0), P.tw, c.st, true); });
   colp<R>(c, 1, false, Prog().in(0, P.A[0]).out(P.B[0], {T1(0)}));
   colp<R>(c, 2, false, Prog().in(0, P.B[0]).out(out, {T1(0)}));
 }
@@ -270,7 +335,7 @@ void inv3(Ctx& c, const cplx<R>* in, R* out, double scale, int d = -1) {
   colp<R>(c, 1, true, Prog().in(0, P.A[0]).out(P.B[0], {d == 1 ? TW(0) : T1(0)}));
   Prog x;
   x.in(0, P.B[0]).out(out, {d == 0 ? TW(0) : T1(0)});
-  tumor::launch_xinv<R>(c.n, to_x(x.p, scale), P.tw, c.st);
+  timed(c, TUMOR_K_XOTHER, 2.0 * c.V * sizeof(R), [&] { tumor::launch_xinv<R>(c.n, to_x(x.p, scale), P.tw, c.st); });
 }
 
 // out = raw * in + dcoef * D in (spectral), D c = div(K grad c).
@@ -290,7 +355,8 @@ void diff_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, double raw, double dcoe
   xa.out[2] = P.A[2];
   xa.K = P.K;
   xa.skip = skip;
-  tumor::launch_xdiff<R>(c.n, xa, P.tw, c.st);
+  timed(c, kcls<R>(TUMOR_K_XDIFF64, TUMOR_K_XDIFF32), 7.0 * c.V * sizeof(R),
+        [&] { tumor::launch_xdiff<R>(c.n, xa, P.tw, c.st); });
   colp<R>(c, 1, false,
           Prog().in(0, P.A[0]).in(1, P.A[1]).in(2, P.A[2]).out(P.B[0], {T1(0), TW(1)}).out(P.B[1], {T1(2)}).skip(skip));
   Prog z;
@@ -340,7 +406,8 @@ void elast_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, const int* skip) {
   xa.lam = P.lam;
   xa.eta = P.eta;
   xa.skip = skip;
-  tumor::launch_xelast<R>(c.n, xa, P.tw, c.st);
+  timed(c, kcls<R>(TUMOR_K_XELAST64, TUMOR_K_XELAST32), 19.0 * c.V * sizeof(R),
+        [&] { tumor::launch_xelast<R>(c.n, xa, P.tw, c.st); });
   Prog yf;
   for (int k = 0; k < 8; ++k) yf.in(k, A[k]);
   yf.out(B[0], {T1(0), TW(3, -1.0)})
@@ -377,7 +444,7 @@ void force_rhs(Ctx& c, const double* pa, const double* pbp, cplx<double>* out) {
   xa.out[1] = B[1];
   xa.out[2] = B[2];
   xa.zeta = c.prm.zeta;
-  tumor::launch_xforce<double>(c.n, xa, P.tw, c.st);
+  timed(c, TUMOR_K_XOTHER, 6.0 * c.V * 8.0, [&] { tumor::launch_xforce<double>(c.n, xa, P.tw, c.st); });
   colp<double>(c, 1, false,
                Prog().in(0, B[0]).in(1, B[1]).in(2, B[2]).out(A[0], {T1(0)}).out(A[1], {T1(1)}).out(A[2], {T1(2)}));
   colp<double>(c, 2, false,
@@ -417,7 +484,8 @@ void velocity(Ctx& c) {
   Prog x;
   x.in(0, B[0]).in(1, B[1]).in(2, B[2]).in(3, B[3]);
   x.out(c.vel[0], {T1(0)}).out(c.vel[1], {T1(1)}).out(c.vel[2], {T1(2)}).out(c.vel[3], {TW(0), T1(3)});
-  tumor::launch_xinv<double>(c.n, to_x(x.p, 1.0 / (double)c.V), P.tw, c.st);
+  timed(c, TUMOR_K_XOTHER, 8.0 * c.V * 8.0,
+        [&] { tumor::launch_xinv<double>(c.n, to_x(x.p, 1.0 / (double)c.V), P.tw, c.st); });
 }
 
 // ---------------------------------------------------------------- PCG control
@@ -457,27 +525,35 @@ tumor::KrylovArgs kargs(Ctx& c, int ncomp, cplx<R>* x, tumor::SolveScalars* sv, 
 }
 
 // Plain PCG iterations after the residual r and its norms are in place.
-// `apply(p, q, skip)` computes q = A p.  Returns iterations taken.
+// `apply(p, q, skip)` computes q = A p.  Iterations are queued in chunks
+// (predicted count + 2, then 4) between scalar read-backs; kernels of an
+// iteration after convergence see the device `done` flag and return at once.
 template <typename R, typename Apply>
 int pcg_iterate(Ctx& c, tumor::KrylovArgs a, Apply apply, double thr2, int limit, bool fixed, int pred,
-                bool& conv, bool& bad) {
+                int zero_x, bool& conv, bool& bad) {
   a.thr2 = thr2;
   a.limit = limit;
   a.fixed = fixed ? 1 : 0;
-  tumor::launch_pcg_start<R>(a, 0, c.st);
+  const int kc = kcls<R>(TUMOR_K_KRYLOV64, TUMOR_K_KRYLOV32);
+  const double vb = double(a.ncomp) * double(c.V) * sizeof(R);  // one Krylov vector
+  timed(c, kc, (zero_x ? 3.0 : 2.0) * vb, [&] { tumor::launch_pcg_start<R>(a, zero_x, c.st); });
   int launched = 0;
   int chunk = std::max(1, std::min(limit, pred + 2));
   tumor::SolveScalars* sv = a.sv;
   const int* skip = &sv->done;
   for (;;) {
     for (int k = 0; k < chunk && launched < limit; ++k, ++launched) {
+      c.cur_tag = launched;
       apply(static_cast<const cplx<R>*>(a.p), static_cast<cplx<R>*>(a.q), skip);
-      tumor::launch_pcg_pq<R>(a, c.st);
-      tumor::launch_pcg_update<R>(a, c.st);
-      tumor::launch_pcg_pupdate<R>(a, c.st);
+      timed(c, kc, 2.0 * vb, [&] { tumor::launch_pcg_pq<R>(a, c.st); });
+      timed(c, kc, 6.0 * vb, [&] { tumor::launch_pcg_update<R>(a, c.st); });
+      c.cur_tag = launched + 1;  // the p update of the final iteration is skipped
+      timed(c, kc, 3.0 * vb, [&] { tumor::launch_pcg_pupdate<R>(a, c.st); });
     }
+    c.cur_tag = -1;
     HIPCHECK(hipGetLastError());
     readback(c, sv);
+    timers_flush(c, c.hsv->it);
     if (c.hsv->done || launched >= limit) break;
     chunk = 4;
   }
@@ -521,7 +597,7 @@ SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cp
     bool conv = true, bad = false;
     const bool fixed = forced >= 0;
     const int limit = fixed ? forced : c.cfg.max_it;
-    if (limit > 0) so.it = pcg_iterate<double>(c, a, A64, thr2, limit, fixed, pred, conv, bad);
+    if (limit > 0) so.it = pcg_iterate<double>(c, a, A64, thr2, limit, fixed, pred, 0, conv, bad);
     so.conv = conv;
     so.bad = bad;
     so.relres = std::sqrt(c.hsv->rr / bb);
@@ -538,7 +614,7 @@ SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cp
   const int max_outer = 30;
   int total = 0;
   while (so.outer < max_outer) {
-    tumor::launch_residual<double>(conv_args, P.r, c.st);
+    timed(c, TUMOR_K_KRYLOV64, ncomp * c.V * (16.0 + 4.0), [&] { tumor::launch_residual<double>(conv_args, P.r, c.st); });
     const double need = rtol * std::sqrt(bb / rr);
     const double in_rtol = std::max(1e-4, 0.3 * need);
     bool conv = true, bad = false;
@@ -547,32 +623,9 @@ SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cp
     tumor::KrylovArgs ai = a32;
     ai.x = P.x;
     const double thr_in = in_rtol * in_rtol * rr;
-    // pcg_start with zero_x = 1
-    ai.thr2 = thr_in;
-    ai.limit = c.cfg.max_it;
-    ai.fixed = 0;
-    tumor::launch_pcg_start<float>(ai, 1, c.st);
-    {
-      int launched = 0;
-      int chunk = std::max(1, (c.pred[which >= 0 ? which : 3] + 2) / 2 + 1);
-      const int* skip = &c.sv32->done;
-      for (;;) {
-        for (int k = 0; k < chunk && launched < ai.limit; ++k, ++launched) {
-          A32(P.p, P.q, skip);
-          tumor::launch_pcg_pq<float>(ai, c.st);
-          tumor::launch_pcg_update<float>(ai, c.st);
-          tumor::launch_pcg_pupdate<float>(ai, c.st);
-        }
-        HIPCHECK(hipGetLastError());
-        readback(c, c.sv32);
-        if (c.hsv->done || launched >= ai.limit) break;
-        chunk = 4;
-      }
-      conv = c.hsv->conv != 0;
-      bad = c.hsv->bad != 0;
-      inner_it = c.hsv->it;
-      total += inner_it;
-    }
+    inner_it = pcg_iterate<float>(c, ai, A32, thr_in, c.cfg.max_it, false,
+                                  std::max(1, c.pred[which >= 0 ? which : 3] / 2), 1, conv, bad);
+    total += inner_it;
     so.outer++;
     if (bad) {
       so.bad = true;
@@ -585,7 +638,7 @@ SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cp
     tumor::KrylovArgs ar = a;
     ar.b = bvec;
     ar.ax = c.p64.q;
-    tumor::launch_residual<double>(ar, nullptr, c.st);
+    timed(c, TUMOR_K_KRYLOV64, 3.0 * ncomp * c.V * 8.0, [&] { tumor::launch_residual<double>(ar, nullptr, c.st); });
     readback(c, c.sv64);
     rr = c.hsv->rr;
     if (c.hsv->bad) {
@@ -613,7 +666,7 @@ SolveOut cn_solve(Ctx& c, const double* src, double* dst, int which) {
   auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip) { diff_apply<float>(c, p, q, 1.0, -h, skip); };
   auto r0 = [&](tumor::KrylovArgs& a) {
     diff_apply<double>(c, x, c.p64.q, 0.0, 1.0, nullptr);
-    tumor::launch_cn_residual<double>(a, x, c.p64.q, c.st);
+    timed(c, TUMOR_K_KRYLOV64, 4.0 * c.V * 8.0, [&] { tumor::launch_cn_residual<double>(a, x, c.p64.q, c.st); });
   };
   SolveOut so = solve_system(c, 1, tumor::PREC_DIFF, h, x, b, c.cfg.rtol_diff, which, A64, A32, r0);
   inv3<double>(c, x, dst, 1.0 / (double)c.V);
@@ -628,7 +681,7 @@ SolveOut elast_solve(Ctx& c, cplx<double>* x, int which) {
   auto r0 = [&](tumor::KrylovArgs& a) {
     elast_apply<double>(c, x, c.p64.q, nullptr);
     a.ax = c.p64.q;
-    tumor::launch_residual<double>(a, nullptr, c.st);
+    timed(c, TUMOR_K_KRYLOV64, 9.0 * c.V * 8.0, [&] { tumor::launch_residual<double>(a, nullptr, c.st); });
     a.ax = nullptr;
   };
   return solve_system(c, 3, tumor::PREC_ELAST, 0.0, x, c.b64, c.cfg.rtol_elast, which, A64, A32, r0);
@@ -669,7 +722,8 @@ void refresh(Ctx& c, int do_reaction, const double* const* in, double* const* ou
   a.do_reaction = do_reaction;
   a.rc = c.rc;
   a.fc = c.fc;
-  tumor::launch_react(a, c.st);
+  const double rb = do_reaction ? (10.0 + 13.0) * c.V * 8.0 + (c.K32 ? 16.0 * c.V : 0.0) : 12.0 * c.V * 8.0;
+  timed(c, TUMOR_K_REACT, rb, [&] { tumor::launch_react(a, c.st); });
 }
 
 void refresh_state(Ctx& c) {
@@ -773,8 +827,10 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
     s.n_grid = c.n;
     s.dt = c.cfg.dt;
     s.s = c.cfg.dt / (2.0 * M_PI / c.n);
-    if (c.mixed) tumor::launch_sl<float>(s, c.st);
-    else tumor::launch_sl<double>(s, c.st);
+    timed(c, TUMOR_K_SL, 16.0 * c.V * 8.0, [&] {
+      if (c.mixed) tumor::launch_sl<float>(s, c.st);
+      else tumor::launch_sl<double>(s, c.st);
+    });
   } else {
     const int ids[6] = {P, I, N, G, W, F};
     for (int k : ids)
@@ -804,6 +860,7 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
     HIPCHECK(hipMemcpyAsync(c.Up, c.U, 3 * c.S * sizeof(cplx<double>), hipMemcpyDeviceToDevice, c.st));
   }
   c.has_forced = false;
+  timers_flush(c, 0x7fffffff);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipMemcpyAsync(c.hcs, c.cs, sizeof(tumor::CoefScalars), hipMemcpyDeviceToHost, c.st));
   HIPCHECK(hipStreamSynchronize(c.st));
@@ -985,6 +1042,7 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
     c->hcs = static_cast<tumor::CoefScalars*>(h2);
     c->pred[0] = c->pred[1] = c->pred[2] = 6;
     c->pred[3] = 30;
+    c->cur_tag = -1;
     set_consts(*c);
     twiddles(*c);
     HIPCHECK(hipMemsetAsync(c->sv64, 0, sizeof(tumor::SolveScalars), c->st));
@@ -1200,9 +1258,50 @@ int tumor_adjoint_step(tumor_ctx* ctx, double* adj, double* grad) {
   return TUMOR_ESTATE;
 }
 
+int tumor_kernel_timer(tumor_ctx* ctx, int32_t kernel_class, int32_t enable) {
+  if (!ctx) return einval("ctx is NULL");
+  if (kernel_class < 0 || kernel_class >= TUMOR_K_COUNT) return einval("unknown kernel class");
+  return guarded([&]() -> int {
+    Ctx& c = *ctx;
+    KTimer*& t = c.timers[kernel_class];
+    if (!t) {
+      t = new KTimer;
+      std::memset(t, 0, sizeof(*t));
+      for (int k = 0; k < 2 * kMaxPend; ++k) HIPCHECK(hipEventCreate(&t->ev[k]));
+    }
+    timer_flush(c, kernel_class, 0x7fffffff);
+    t->on = enable ? 1 : 0;
+    if (enable) {
+      t->launches = 0;
+      t->ms = 0.0;
+      t->bytes = 0.0;
+    }
+    return TUMOR_OK;
+  });
+}
+
+int tumor_kernel_timer_read(tumor_ctx* ctx, int32_t kernel_class, int64_t* launches, double* ms, double* bytes) {
+  if (!ctx) return einval("ctx is NULL");
+  if (kernel_class < 0 || kernel_class >= TUMOR_K_COUNT) return einval("unknown kernel class");
+  return guarded([&]() -> int {
+    Ctx& c = *ctx;
+    KTimer* t = c.timers[kernel_class];
+    if (t) timer_flush(c, kernel_class, 0x7fffffff);
+    if (launches) *launches = t ? t->launches : 0;
+    if (ms) *ms = t ? t->ms : 0.0;
+    if (bytes) *bytes = t ? t->bytes : 0.0;
+    return TUMOR_OK;
+  });
+}
+
 void tumor_destroy(tumor_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->st);
+  for (int k = 0; k < TUMOR_K_COUNT; ++k) {
+    if (!ctx->timers[k]) continue;
+    for (int e = 0; e < 2 * kMaxPend; ++e) (void)hipEventDestroy(ctx->timers[k]->ev[e]);
+    delete ctx->timers[k];
+  }
   if (ctx->hsv) (void)hipHostFree(ctx->hsv);
   if (ctx->hcs) (void)hipHostFree(ctx->hcs);
   delete ctx;

@@ -30,7 +30,7 @@ def _sim(n, precision="fp64", seed=0):
     return torch, sim, inp, P
 
 
-@pytest.mark.parametrize("n", [16, 32, 64, 128])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_spectral_derivatives(n, precision):
     torch, sim, inp, P = _sim(n, precision)
