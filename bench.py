@@ -27,8 +27,8 @@ if ROOT not in sys.path:
 
 METRIC = "split time steps/s at 256³ (fwd, fwd+adjoint), mixed vs FP64 on one GPU"
 HBM_PEAK_GBS = 8000.0
-CLASSES = ("col64", "col32", "xelast64", "xelast32", "xdiff64", "xdiff32", "xother", "sl", "react",
-           "krylov64", "krylov32")
+CLASSES = ("colinv64", "colfwd64", "colinv32", "colfwd32", "xelast64", "xelast32", "xdiff64", "xdiff32",
+           "xother", "sl", "react", "krylov64", "krylov32")
 
 
 def log(*a):
@@ -69,7 +69,8 @@ def run_form(tm, torch, inp, P, precision, steps, warmup):
     return dict(wall=wall, gpu_ms=gpu_ms, stats=stats, warm_profile=prof, dominant=dominant, dom=dom)
 
 
-def roofline(dom):
+def roofline(dom, name=None, n=256):
+    import paper_1810_05370_amd as tm
     if dom["launches"] == 0 or dom["ms"] <= 0:
         return None
     per_launch = dom["bytes"] / dom["launches"]
@@ -77,7 +78,8 @@ def roofline(dom):
     achieved = per_launch / (mean_ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                kernel=None, bytes_per_launch=per_launch, mean_launch_ms=round(mean_ms, 5))
+                kernel=tm.KERNEL_NAMES.get(name, name).format(n=n) if name else None,
+                bytes_per_launch=round(per_launch), mean_launch_us=round(mean_ms * 1e3, 2))
 
 
 def cpu_baseline(inp, P, iters_e, iters_d):
@@ -197,19 +199,14 @@ def main():
         v64 = args.steps / (fp64_run["gpu_ms"] / 1e3)
         extra["fp64_steps_per_s"] = round(v64, 4)
         extra["mixed_speedup_over_fp64"] = round(value / v64, 3)
-        rf = roofline(fp64_run["dom"])
-        if rf:
-            rf["kernel"] = fp64_run["dominant"]
-        extra["fp64_roofline"] = rf
+        extra["fp64_roofline"] = roofline(fp64_run["dom"], fp64_run["dominant"], n)
     it_e = [s["it_elast"] for s in main_run["stats"]]
     extra["elasticity_iterations_per_step"] = it_e
     extra["elasticity_outer_per_step"] = [s["outer_elast"] for s in main_run["stats"]]
     extra["diffusion_iterations_last_step"] = main_run["stats"][-1]["it_diff"]
     extra["warmup_kernel_ms"] = {c: round(v["ms"], 2) for c, v in main_run["warm_profile"].items() if v["ms"] > 0}
     extra["wall_s"] = round(main_run["wall"], 4)
-    rl = roofline(main_run["dom"])
-    if rl:
-        rl["kernel"] = main_run["dominant"]
+    rl = roofline(main_run["dom"], main_run["dominant"], n)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -220,9 +220,9 @@ int tumor_force_iterations(tumor_ctx* ctx, const int32_t* iters);
  * counted once).  enable = 1 resets and starts, 0 stops.  Reading flushes
  * pending events (it synchronises the stream). */
 enum {
-  TUMOR_K_COL64 = 0, TUMOR_K_COL32, TUMOR_K_XELAST64, TUMOR_K_XELAST32, TUMOR_K_XDIFF64,
-  TUMOR_K_XDIFF32, TUMOR_K_XOTHER, TUMOR_K_SL, TUMOR_K_REACT, TUMOR_K_KRYLOV64, TUMOR_K_KRYLOV32,
-  TUMOR_K_COUNT
+  TUMOR_K_COLINV64 = 0, TUMOR_K_COLFWD64, TUMOR_K_COLINV32, TUMOR_K_COLFWD32, TUMOR_K_XELAST64,
+  TUMOR_K_XELAST32, TUMOR_K_XDIFF64, TUMOR_K_XDIFF32, TUMOR_K_XOTHER, TUMOR_K_SL, TUMOR_K_REACT,
+  TUMOR_K_KRYLOV64, TUMOR_K_KRYLOV32, TUMOR_K_COUNT
 };
 int tumor_kernel_timer(tumor_ctx* ctx, int32_t kernel_class, int32_t enable);
 int tumor_kernel_timer_read(tumor_ctx* ctx, int32_t kernel_class, int64_t* launches, double* ms,

@@ -35,8 +35,14 @@ FIELDS = {"p": 0, "i": 1, "n": 2, "o": 3, "l": 4, "g": 5, "w": 6, "f": 7, "u": 8
 OPS = {"deriv_x": 0, "deriv_y": 1, "deriv_z": 2, "diffusion": 3, "elasticity": 4,
        "elast_precond": 5, "cn_precond": 6, "force": 7}
 VECTOR_OPS = ("elasticity", "elast_precond", "force")
-KERNEL_CLASSES = {"col64": 0, "col32": 1, "xelast64": 2, "xelast32": 3, "xdiff64": 4, "xdiff32": 5,
-                  "xother": 6, "sl": 7, "react": 8, "krylov64": 9, "krylov32": 10}
+KERNEL_CLASSES = {"colinv64": 0, "colfwd64": 1, "colinv32": 2, "colfwd32": 3, "xelast64": 4, "xelast32": 5,
+                  "xdiff64": 6, "xdiff32": 7, "xother": 8, "sl": 9, "react": 10, "krylov64": 11, "krylov32": 12}
+# rocprofv3 kernel names of each class (for cross-checking event timings against traces)
+KERNEL_NAMES = {"colinv64": "k_col_pass<double, {n}, true>", "colfwd64": "k_col_pass<double, {n}, false>",
+                "colinv32": "k_col_pass<float, {n}, true>", "colfwd32": "k_col_pass<float, {n}, false>",
+                "xelast64": "k_xelast<double, {n}>", "xelast32": "k_xelast<float, {n}>",
+                "xdiff64": "k_xdiff<double, {n}>", "xdiff32": "k_xdiff<float, {n}>", "sl": "k_sl",
+                "react": "k_react"}
 
 
 class TumorParams(ctypes.Structure):

@@ -308,7 +308,7 @@ void colp(Ctx& c, int axis, bool inv, const Prog& pr) {
   int nin = 0;
   for (int k = 0; k < tumor::kMaxCol; ++k) nin += used[k] ? 1 : 0;
   const double bytes = double(nin + pr.p.nout) * double(c.V) * sizeof(R);
-  timed(c, kcls<R>(TUMOR_K_COL64, TUMOR_K_COL32), bytes,
+  timed(c, inv ? kcls<R>(TUMOR_K_COLINV64, TUMOR_K_COLINV32) : kcls<R>(TUMOR_K_COLFWD64, TUMOR_K_COLFWD32), bytes,
         [&] { tumor::launch_col_pass<R>(c.n, axis, inv, pr.p, pb<R>(c).tw, c.st); });
 }
 
