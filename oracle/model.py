@@ -88,17 +88,20 @@ DEFAULT_CFG = dict(dt=0.01, rtol_diff=1e-8, rtol_elast=1e-8, max_it=1000,
                    edema=True, elasticity=True, advection=True)
 
 
-def step(st: State, cfg=None, forced=None):
+def step(st: State, cfg=None, forced=None, tape=None):
     """Advance ``st`` by one split step in place.  Returns a stats dict.
 
     ``forced``: optional list of four iteration counts (i, o, l diffusion and
     elasticity) to run each solve for exactly that many iterations.
+    ``tape``: optional dict that receives the step's intermediates (for the
+    discrete adjoint).
     """
     c = dict(DEFAULT_CFG)
     if cfg:
         c.update(cfg)
     P, grid, dt = st.P, st.grid, c["dt"]
     F, coef = st.f, st.coef
+    F_coef0 = coef
     fx = forced if forced is not None else (None, None, None, None)
 
     # S1: transport with the backward-difference velocity.
@@ -147,6 +150,10 @@ def step(st: State, cfg=None, forced=None):
         conv &= ok
     else:
         u_new = st.u.copy()
+    if tape is not None:
+        tape.update(v=v, adv=adv, i_dd=i_dd, o_dag=o_dag, l_dag=l_dag, coef0=F_coef0,
+                    p1=p1, i1=i1, n1=n1, g1=g1, w1=w1, o1=o1, l1=l1, coef1=coef,
+                    u_new=u_new, u=st.u, u_prev=st.u_prev, F0={k: F[k] for k in F})
     # S7: rotate.
     st.u_prev, st.u = st.u, u_new
     st.f = dict(p=p1, i=i1, n=n1, o=o1, l=l1, g=g1, w=w1, f=f1)
