@@ -66,6 +66,7 @@ typedef enum {
 #define TUMOR_F_ELASTICITY 0x2  /* mass-effect elasticity solve (Sec. 3)       */
 #define TUMOR_F_EDEMA      0x4  /* edema diffusion + reaction (Sec. 2.4)        */
 #define TUMOR_F_DEFAULT    (TUMOR_F_ADVECTION | TUMOR_F_ELASTICITY | TUMOR_F_EDEMA)
+#define TUMOR_F_ADJOINT    0x8  /* reserve adjoint scratch in the workspace      */
 
 /* Model parameters.  Names follow Table t:setup (Sec. 2.5) and the equations
  * they enter:
@@ -163,20 +164,29 @@ int tumor_step(tumor_ctx* ctx, int32_t nsteps, tumor_step_stats* last);
 int tumor_solve_elasticity(tumor_ctx* ctx, const double* force, double* u_out,
                            int32_t* iters, double* relres);
 
-/* One step of the discrete adjoint, in reverse order of the recorded forward
- * steps (requires tumor_record).  adj: device, 14 N^3 values: on input the
- * adjoint of (p,i,n,o,l,g,w,f,u,u_prev) after step k+1, on output the
- * adjoint before it.  grad: host, 5 + n_ic doubles, accumulated in place:
- * d/d(rho, k_w, k_g, k_f, lame_scale, ic_weights[0..n_ic)).  Returns
- * TUMOR_ESTATE when no recorded step is left. */
-int tumor_adjoint_step(tumor_ctx* ctx, double* adj, double* grad);
-
-/* Start recording the next `nsteps` forward steps for the adjoint, keeping
- * full checkpoints every `ckpt_every` steps (>= 1) in `tape` (device,
- * tape_bytes >= tumor_tape_bytes(...)); steps between checkpoints are
- * recomputed during the reverse sweep. */
+/* Discrete adjoint (the exact transpose of the linearised split step, every
+ * PCG solve taken as exact; the paper leaves adjoint-based inversion to
+ * future work, Sec. 5).  Requires a context created with TUMOR_F_ADJOINT.
+ *
+ * tumor_record(ctx, nsteps, ckpt_every, tape, tape_bytes): the next nsteps
+ * calls of tumor_step are recorded.  The full state (species and both
+ * displacements) is checkpointed every ckpt_every (>= 1) steps into `tape`
+ * (device, 256-byte aligned, >= tumor_tape_bytes(cfg, nsteps, ckpt_every));
+ * the tape also holds a window of ckpt_every states that the reverse sweep
+ * recomputes from the nearest checkpoint.
+ *
+ * tumor_adjoint_step(ctx, adj, grad): reverses the latest recorded step not
+ * yet reversed.  adj: device, 14 N^3 values, the adjoint of the state
+ * (p, i, n, o, l, g, w, f, u_x, u_y, u_z, uprev_x, uprev_y, uprev_z) after
+ * that step on input, before it on output.  grad: host, 5 + n_ic doubles,
+ * accumulated: d/d(rho, k_w, k_g, k_f, lame_scale, ic_weights[0..n_ic)),
+ * where rho moves rho_w and rho_g together; the ic_weights part is added when
+ * the first step (step 0) is reversed.  The forward state of the context is
+ * overwritten by the recomputation (it holds the state after the reversed
+ * step on return).  TUMOR_ESTATE: no recording, or every step reversed. */
 int tumor_tape_bytes(const tumor_config* cfg, int32_t nsteps, int32_t ckpt_every, size_t* bytes);
 int tumor_record(tumor_ctx* ctx, int32_t nsteps, int32_t ckpt_every, void* tape, size_t tape_bytes);
+int tumor_adjoint_step(tumor_ctx* ctx, double* adj, double* grad);
 
 /* Copy a field out of / into the state (device arrays of N^3, or 3 N^3 for
  * TUMOR_FIELD_U and TUMOR_FIELD_UPREV).  Coefficient fields are read only;

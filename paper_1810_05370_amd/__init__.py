@@ -30,6 +30,8 @@ STATUS_NAMES = {0: "TUMOR_OK", -1: "TUMOR_EINVAL", -2: "TUMOR_ENOMEM", -3: "TUMO
 PREC = {"fp64": 0, "mixed": 1}
 F_ADVECTION, F_ELASTICITY, F_EDEMA = 0x1, 0x2, 0x4
 F_DEFAULT = F_ADVECTION | F_ELASTICITY | F_EDEMA
+F_ADJOINT = 0x8
+GRAD_NAMES = ("rho", "k_w", "k_g", "k_f", "lame_scale")
 FIELDS = {"p": 0, "i": 1, "n": 2, "o": 3, "l": 4, "g": 5, "w": 6, "f": 7, "u": 8, "u_prev": 9,
           "K": 10, "rho": 11, "mu": 12, "lambda": 13, "eta": 14}
 OPS = {"deriv_x": 0, "deriv_y": 1, "deriv_z": 2, "diffusion": 3, "elasticity": 4,
@@ -285,6 +287,26 @@ class Tumor:
         _check(self.lib.tumor_kernel_timer_read(self.ctx, KERNEL_CLASSES[name], ctypes.byref(n),
                                                 ctypes.byref(ms), ctypes.byref(b)))
         return dict(launches=n.value, ms=ms.value, bytes=b.value)
+
+    # -- adjoint ---------------------------------------------------------
+    def record(self, nsteps, ckpt_every=1):
+        """Record the next ``nsteps`` steps for the adjoint (checkpoint every ``ckpt_every``)."""
+        torch = self._torch
+        nb = ctypes.c_size_t(0)
+        _check(self.lib.tumor_tape_bytes(ctypes.byref(self.cfg), int(nsteps), int(ckpt_every), ctypes.byref(nb)))
+        self.tape = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.tape.data_ptr()
+        ptr = base + ((-base) % 256)
+        _check(self.lib.tumor_record(self.ctx, int(nsteps), int(ckpt_every), ctypes.c_void_p(ptr), nb.value))
+        self.tape_bytes = nb.value
+
+    def adjoint_step(self, adj, grad):
+        """Reverse one recorded step.  adj: (14, n, n, n) float64 device tensor, updated in
+        place.  grad: float64 numpy array of 5 + n_ic entries, accumulated in place."""
+        import numpy as np
+        assert adj.dtype == self._torch.float64 and adj.is_contiguous() and adj.numel() == 14 * self.n ** 3
+        assert isinstance(grad, np.ndarray) and grad.dtype == np.float64 and grad.size == 5 + self.n_ic
+        _check(self.lib.tumor_adjoint_step(self.ctx, _ptr(adj), grad.ctypes.data_as(ctypes.c_void_p)))
 
     def force_iterations(self, iters=None):
         if iters is None:

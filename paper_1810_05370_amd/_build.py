@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtumor.so")
-SOURCES = ["engine.hip", "pointwise.hip", "fft_f64.hip", "fft_f32.hip"]
+SOURCES = ["engine.hip", "pointwise.hip", "adjoint.hip", "fft_f64.hip", "fft_f32.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

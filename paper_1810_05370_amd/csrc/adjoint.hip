@@ -1,0 +1,448 @@
+// Adjoint kernels of the split step (gfx950, FP64).
+//
+// Each kernel is the transpose of the linearisation of one forward sub-step:
+//   k_react_adj : species reaction, oxygen and edema updates (pointwise)
+//   k_coef_adj  : Lame / screening mixture -> species adjoints, d/d lame_scale
+//   k_s0_adj    : step coefficients K, rho -> w, g, f and d/d(k_w, k_g, k_f, rho)
+//   k_force_adj : pointwise part of the force b = zeta tanh(tau) G tau
+//   k_sl_adj    : semi-Lagrangian transport (interpolation transpose by FP64
+//                 atomic scatter, velocity sensitivity through X and X*)
+//   k_ic_adj    : projections onto the Gaussian initial-condition basis
+// Parameter sums use deterministic block partials + last-block totals.
+#include <cmath>
+
+#include "adjoint.hpp"
+
+namespace tumor {
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block partials + last block: adds the grid totals of v[] to gs->g[slot0 + k].
+template <int NV>
+__device__ void reduce_into(double (&v)[NV], double* part, GradScalars* gs, int slot0) {
+  __shared__ double sh[NV][4];
+  __shared__ int last;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double s = wave_sum_d(v[k]);
+    if (lane == 0) sh[k][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[(long long)blockIdx.x * NV + k] = sh[k][0] + sh[k][1] + sh[k][2] + sh[k][3];
+    __threadfence();
+    last = (atomicAdd(&gs->counter, 1u) == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const volatile double* vp = part;
+  double t[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) t[k] = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t[k] += vp[(long long)b * NV + k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double s = wave_sum_d(t[k]);
+    if (lane == 0) sh[k][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) gs->g[slot0 + k] += sh[k][0] + sh[k][1] + sh[k][2] + sh[k][3];
+    gs->counter = 0u;
+  }
+}
+
+static inline int rblocks(long long V) {
+  long long b = (V + 255) / 256;
+  return (int)(b > 1024 ? 1024 : (b < 1 ? 1 : b));
+}
+
+// ----------------------------------------------------------- pointwise math
+__device__ __forceinline__ double H(double x, double eps) { return 1.0 / (1.0 + exp(-2.0 * x / eps)); }
+__device__ __forceinline__ double dH(double x, double eps) {
+  const double h = H(x, eps);
+  return (2.0 / eps) * h * (1.0 - h);
+}
+__device__ __forceinline__ void logistic_partials(double y, double r, double t, double& ly, double& lr,
+                                                  double& val) {
+  const double e = exp(r * t);
+  const double D = 1.0 + y * (e - 1.0);
+  ly = e / (D * D);
+  lr = t * e * y * (1.0 - y) / (D * D);
+  val = y * e / D;
+}
+
+// Reaction + oxygen + edema transpose.  L[] are the adjoints of the step's
+// outputs p', i', n', o', l', g', w' on entry; on exit L[P], L[N], L[G], L[W]
+// hold the adjoints of p, n, g, w after transport, L[O] that of o after
+// diffusion, L[L] that of l after diffusion; idd = adjoint of i after
+// diffusion (including the dD term), ddb = adjoint of dD, rb = adjoint of
+// rho_p + rho_inv_frac * adjoint of rho_i.
+__global__ void __launch_bounds__(256) k_react_adj(ReactAdjArgs a) {
+  const ReactConsts& rc = a.rc;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.V;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double dt = rc.dt, eps = rc.eps;
+    const double p = a.p_dag[v], idag = a.i_dag[v], i = a.i_dd[v], n = a.n_dag[v], g = a.g_dag[v],
+                 w = a.w_dag[v], o = a.o_dag[v];
+    const double i1 = a.i1[v], g1 = a.g1[v], w1 = a.w1[v];
+    const double rho_p = a.rho_w * a.w0[v] + a.rho_g * a.g0[v];
+    const double rho_i = rc.rho_inv_frac * rho_p;
+    double Pb = a.L[0][v], Ib = a.L[1][v], Nb = a.L[2][v], Ob = a.L[3][v], Lb = a.L[4][v], Gb = a.L[5][v],
+           Wb = a.L[6][v];
+    // edema: l' = l + dt (delta_e i'/(i'+dh)(1-i') - delta_l l)
+    double ldag_b = Lb;
+    if (rc.edema) {
+      ldag_b = Lb * (1.0 - dt * rc.delta_l);
+      const double dh = rc.delta_half;
+      Ib += Lb * dt * rc.delta_e * (dh * (1.0 - i1) / ((i1 + dh) * (i1 + dh)) - i1 / (i1 + dh));
+    }
+    // oxygen: o' = o + dt (-delta_p p' + delta_s (o_heal - o)(g' + w'))
+    double odag_b = Ob * (1.0 - dt * rc.delta_s * (g1 + w1));
+    Pb += Ob * (-dt * rc.delta_p);
+    const double gwo = Ob * dt * rc.delta_s * (rc.o_heal - o);
+    Gb += gwo;
+    Wb += gwo;
+    // species reaction
+    const double Ha = H(rc.o_inv - o, eps);
+    const double alpha = rc.alpha0 * Ha;
+    const double alpha_o = -rc.alpha0 * dH(rc.o_inv - o, eps);
+    const double Hb = H(rc.sigma_b - p - i, eps);
+    const double beta = rc.beta0 * Hb * o;
+    const double beta_pi = -rc.beta0 * dH(rc.sigma_b - p - i, eps) * o;
+    const double beta_o = rc.beta0 * Hb;
+    const double h = rc.gamma * H(rc.o_hyp - o, eps);
+    const double h_o = -rc.gamma * dH(rc.o_hyp - o, eps);
+    double kap = (o - rc.o_mit) / (rc.o_inv - rc.o_mit);
+    kap = kap < 0.0 ? 0.0 : (kap > 1.0 ? 1.0 : kap);
+    const double kap_o = (o >= rc.o_mit && o <= rc.o_inv) ? 1.0 / (rc.o_inv - rc.o_mit) : 0.0;
+    double Lpy, Lpr, Lp, Liy, Lir, Li;
+    logistic_partials(p, rho_p * kap, dt, Lpy, Lpr, Lp);
+    logistic_partials(i, rho_i * kap, dt, Liy, Lir, Li);
+    const double dD = i - idag;
+    const double S = dD + (Lp - p) + (Li - i);
+    const double gw = g + w;
+    const bool small = gw < 1e-12;
+    const double phig = small ? 0.5 : g / gw;
+    const double phiw = small ? 0.5 : w / gw;
+    const double inv2 = small ? 0.0 : 1.0 / (gw * gw);
+    const double dphig_g = w * inv2, dphig_w = -g * inv2, dphiw_g = -w * inv2, dphiw_w = g * inv2;
+    const double Sb = -phig * Gb - phiw * Wb;
+    const double tot = p + i + g + w;
+    const double p_b = Pb * (Lpy + dt * (-alpha + beta_pi * i - h)) + Ib * dt * (alpha - beta_pi * i) +
+                       Nb * dt * h + Sb * (Lpy - 1.0);
+    const double i_b = Pb * dt * (beta + beta_pi * i) + Ib * (Liy + dt * (-beta - beta_pi * i - h)) + Nb * dt * h +
+                       Sb * (Liy - 1.0);
+    const double g_b = Nb * dt * h + Gb * (1.0 - dphig_g * S - dt * h) + Wb * (-dphiw_g * S);
+    const double w_b = Nb * dt * h + Gb * (-dphig_w * S) + Wb * (1.0 - dphiw_w * S - dt * h);
+    const double o_b = Pb * (Lpr * rho_p * kap_o + dt * (-alpha_o * p + beta_o * i - h_o * p)) +
+                       Ib * (Lir * rho_i * kap_o + dt * (alpha_o * p - beta_o * i - h_o * i)) +
+                       Nb * dt * h_o * tot + Sb * (Lpr * rho_p + Lir * rho_i) * kap_o - Gb * dt * h_o * g -
+                       Wb * dt * h_o * w;
+    const double rp_b = (Pb + Sb) * Lpr * kap;
+    const double ri_b = (Ib + Sb) * Lir * kap;
+    a.L[0][v] = p_b;
+    a.L[2][v] = Nb;
+    a.L[5][v] = g_b;
+    a.L[6][v] = w_b;
+    a.L[3][v] = odag_b + o_b;
+    a.L[4][v] = ldag_b;
+    a.idd[v] = i_b + Sb;
+    a.ddb[v] = Sb;
+    a.rb[v] = rp_b + rc.rho_inv_frac * ri_b;
+  }
+}
+
+// Lame / screening mixture transposed (S5) and d/d lame_scale.
+__global__ void __launch_bounds__(256) k_coef_adj(CoefAdjArgs a) {
+  double acc[1] = {0.0};
+  const RefreshConsts& fc = a.fc;  // scaled by lame_scale
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.V;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double mb = a.mub[v], lb = a.lamb[v], eb = a.etab[v];
+    const double p = a.p1[v], i = a.i1[v], n = a.n1[v], g = a.g1[v], w = a.w1[v], f = a.f1[v];
+    const double tau = p + i + n;
+    const double tb = fc.mu_t * mb + fc.la_t * lb + fc.eta_t * eb;
+    a.L[0][v] += tb;
+    a.L[1][v] += tb;
+    a.L[2][v] += tb;
+    a.L[5][v] += fc.mu_g * mb + fc.la_g * lb + fc.eta_h * eb;
+    a.L[6][v] += fc.mu_w * mb + fc.la_w * lb + fc.eta_h * eb;
+    a.L[7][v] += fc.mu_f * mb + fc.la_f * lb + fc.eta_h * eb;
+    const double mu = fc.mu_w * w + fc.mu_g * g + fc.mu_f * f + fc.mu_t * tau;
+    const double la = fc.la_w * w + fc.la_g * g + fc.la_f * f + fc.la_t * tau;
+    acc[0] += (mu * mb + la * lb) * a.inv_scale;
+  }
+  reduce_into<1>(acc, a.partials, a.gs, 4);
+}
+
+// Step coefficients (S0) transposed: K = k_w w + k_g g + k_f f, rho_p = rho_w w + rho_g g.
+__global__ void __launch_bounds__(256) k_s0_adj(S0AdjArgs a) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.V;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double kb = a.Kb[v], rb = a.rb[v];
+    const double w0 = a.w0[v], g0 = a.g0[v], f0 = a.f0[v];
+    a.Lw[v] += a.k_w * kb + a.rho_w * rb;
+    a.Lg[v] += a.k_g * kb + a.rho_g * rb;
+    a.Lf[v] += a.k_f * kb;
+    acc[0] += (w0 + g0) * rb;
+    acc[1] += w0 * kb;
+    acc[2] += g0 * kb;
+    acc[3] += f0 * kb;
+  }
+  reduce_into<4>(acc, a.partials, a.gs, 0);
+}
+
+// Force b = zeta tanh(tau) G tau, tau = p + n, with b_bar_a = -y_a:
+// taub -= zeta sech^2(tau) (G_a tau) y_a ;  W_a = -zeta tanh(tau) y_a.
+__global__ void k_force_adj(long long V, double zeta, const double* p, const double* n, const double* gtau,
+                            const double* y, double* taub, double* W) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const double t = tanh(p[v] + n[v]);
+  taub[v] -= zeta * (1.0 - t * t) * gtau[v] * y[v];
+  W[v] = -zeta * t * y[v];
+}
+
+__global__ void k_acc_prod(long long V, double coef, const double* x, const double* y, double* out) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < V) out[v] += coef * x[v] * y[v];
+}
+
+__global__ void k_axpy(long long V, double coef, const double* x, double* out) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < V) out[v] += coef * x[v];
+}
+
+// out = x + coef * y
+__global__ void k_xpay(long long V, const double* x, double coef, const double* y, double* out) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < V) out[v] = x[v] + coef * y[v];
+}
+
+// ------------------------------------------------------- semi-Lagrangian
+__device__ __forceinline__ void lw4(double t, double (&w)[4], double (&d)[4]) {
+  w[0] = -t * (t - 1.0) * (t - 2.0) / 6.0;
+  w[1] = (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0;
+  w[2] = -(t + 1.0) * t * (t - 2.0) / 2.0;
+  w[3] = (t + 1.0) * t * (t - 1.0) / 6.0;
+  d[0] = -(3.0 * t * t - 6.0 * t + 2.0) / 6.0;
+  d[1] = (3.0 * t * t - 4.0 * t - 1.0) / 2.0;
+  d[2] = -(3.0 * t * t - 2.0 * t - 2.0) / 2.0;
+  d[3] = (3.0 * t * t - 1.0) / 6.0;
+}
+
+struct Stencil {
+  int ix, iy, iz;
+  double wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
+  __device__ __forceinline__ void set(double jx, double jy, double jz) {
+    const double bx = floor(jx), by = floor(jy), bz = floor(jz);
+    lw4(jx - bx, wx, dx);
+    lw4(jy - by, wy, dy);
+    lw4(jz - bz, wz, dz);
+    ix = (int)(long long)bx;
+    iy = (int)(long long)by;
+    iz = (int)(long long)bz;
+  }
+};
+
+// Value and gradient (d/dj along x, y, z) of NF interpolants at one stencil.
+template <int NF>
+__device__ __forceinline__ void gather_grad(const Stencil& s, const double* const (&q)[NF], int n,
+                                            double (&val)[NF], double (&gx)[NF], double (&gy)[NF],
+                                            double (&gz)[NF]) {
+  const int m = n - 1;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) val[f] = gx[f] = gy[f] = gz[f] = 0.0;
+  for (int c = 0; c < 4; ++c) {
+    const long long zo = (long long)((s.iz + c - 1) & m) * n * n;
+    for (int b = 0; b < 4; ++b) {
+      const long long yo = zo + (long long)((s.iy + b - 1) & m) * n;
+      const double wzy = s.wz[c] * s.wy[b], dzy = s.dz[c] * s.wy[b], wzdy = s.wz[c] * s.dy[b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const long long idx = yo + ((s.ix + a - 1) & m);
+        const double w = wzy * s.wx[a], wgx = wzy * s.dx[a], wgy = wzdy * s.wx[a], wgz = dzy * s.wx[a];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const double qv = q[f][idx];
+          val[f] += w * qv;
+          gx[f] += wgx * qv;
+          gy[f] += wgy * qv;
+          gz[f] += wgz * qv;
+        }
+      }
+    }
+  }
+}
+
+template <int NF>
+__device__ __forceinline__ void scatter(const Stencil& s, double* const (&out)[NF], const double (&val)[NF], int n) {
+  const int m = n - 1;
+  for (int c = 0; c < 4; ++c) {
+    const long long zo = (long long)((s.iz + c - 1) & m) * n * n;
+    for (int b = 0; b < 4; ++b) {
+      const long long yo = zo + (long long)((s.iy + b - 1) & m) * n;
+      const double wzy = s.wz[c] * s.wy[b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const long long idx = yo + ((s.ix + a - 1) & m);
+        const double w = wzy * s.wx[a];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) unsafeAtomicAdd(out[f] + idx, w * val[f]);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sl_adj(SLAdjArgs a) {
+  const int n = a.n_grid;
+  const long long V = (long long)n * n * n;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int jx = (int)(v % n), jy = (int)((v / n) % n), jz = (int)(v / ((long long)n * n));
+  const double s = a.s, dt = a.dt;
+  const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v], d0 = a.div[v];
+  // X* and v(X*)
+  Stencil st_s;
+  st_s.set(jx - s * vx, jy - s * vy, jz - s * vz);
+  const double* const vel[3] = {a.vx, a.vy, a.vz};
+  double vs[3], vsx[3], vsy[3], vsz[3];
+  gather_grad<3>(st_s, vel, n, vs, vsx, vsy, vsz);
+  // X and the fields there
+  Stencil st;
+  st.set(jx - 0.5 * s * (vx + vs[0]), jy - 0.5 * s * (vy + vs[1]), jz - 0.5 * s * (vz + vs[2]));
+  const double* const fl[7] = {a.q[0], a.q[1], a.q[2], a.q[3], a.q[4], a.q[5], a.div};
+  double q[7], qx[7], qy[7], qz[7];
+  gather_grad<7>(st, fl, n, q, qx, qy, qz);
+  const double dX = q[6];
+  const double cfac = 1.0 - 0.5 * dt * (dX + d0) + 0.5 * dt * dt * dX * d0;
+  double bar[7];
+  double cbar = 0.0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double lam = a.lam[k][v];
+    cbar += lam * q[k];
+    bar[k] = lam * cfac;
+  }
+  bar[5] = a.lam[5][v];
+  bar[6] = cbar * (-0.5 * dt + 0.5 * dt * dt * d0);
+  const double ddirect = cbar * (-0.5 * dt + 0.5 * dt * dt * dX);
+  double Jb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    Jb[0] += bar[k] * qx[k];
+    Jb[1] += bar[k] * qy[k];
+    Jb[2] += bar[k] * qz[k];
+  }
+  double* const outs[7] = {a.out[0], a.out[1], a.out[2], a.out[3], a.out[4], a.out[5], a.divb};
+  scatter<7>(st, outs, bar, n);
+  unsafeAtomicAdd(a.divb + v, ddirect);
+  // X = x - s/2 (v + v*), v* = I[v](X*), X* = x - s v
+  double vsb[3], vown[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    vsb[b] = -0.5 * s * Jb[b];
+    vown[b] = -0.5 * s * Jb[b];
+  }
+  double Jsb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    Jsb[0] += vsb[b] * vsx[b];
+    Jsb[1] += vsb[b] * vsy[b];
+    Jsb[2] += vsb[b] * vsz[b];
+  }
+#pragma unroll
+  for (int b = 0; b < 3; ++b) vown[b] += -s * Jsb[b];
+  double* const vb[3] = {a.vb[0], a.vb[1], a.vb[2]};
+  scatter<3>(st_s, vb, vsb, n);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) unsafeAtomicAdd(a.vb[b] + v, vown[b]);
+}
+
+// ------------------------------------------------------ initial condition
+// part[k * nb + block] = sum over the block's voxels of phi_k * lam_p.
+__global__ void __launch_bounds__(256) k_ic_adj(int n, const double* ic, int n_ic, const double* lam_p,
+                                                double* part) {
+  const long long V = (long long)n * n * n;
+  const int k = blockIdx.y;
+  const double h = 2.0 * M_PI / n, twopi = 2.0 * M_PI;
+  const double* c = ic + 5 * k;
+  double acc = 0.0;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < V;
+       v += (long long)gridDim.x * blockDim.x) {
+    const int jx = (int)(v % n), jy = (int)((v / n) % n), jz = (int)(v / ((long long)n * n));
+    double dx = h * jx - c[0], dy = h * jy - c[1], dz = h * jz - c[2];
+    dx -= twopi * rint(dx / twopi);
+    dy -= twopi * rint(dy / twopi);
+    dz -= twopi * rint(dz / twopi);
+    const double d2 = dz * dz + dy * dy + dx * dx;
+    acc += exp(-d2 / (2.0 * c[3] * c[3])) * lam_p[v];
+  }
+  __shared__ double sh[4];
+  const double s = wave_sum_d(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(long long)k * gridDim.x + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void k_ic_adj_sum(const double* part, int nb, int n_ic, double* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_ic) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(long long)k * nb + b];
+  out[k] = s;
+}
+
+// ------------------------------------------------------------- launchers
+static inline unsigned pw_blocks(long long V) { return (unsigned)((V + 255) / 256); }
+
+void launch_react_adj(const ReactAdjArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_react_adj, dim3(rblocks(a.V)), dim3(256), 0, st, a);
+}
+void launch_coef_adj(const CoefAdjArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_coef_adj, dim3(rblocks(a.V)), dim3(256), 0, st, a);
+}
+void launch_s0_adj(const S0AdjArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_s0_adj, dim3(rblocks(a.V)), dim3(256), 0, st, a);
+}
+void launch_force_adj(long long V, double zeta, const double* p, const double* n, const double* gtau,
+                      const double* y, double* taub, double* W, hipStream_t st) {
+  hipLaunchKernelGGL(k_force_adj, dim3(pw_blocks(V)), dim3(256), 0, st, V, zeta, p, n, gtau, y, taub, W);
+}
+void launch_acc_prod(long long V, double coef, const double* x, const double* y, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_acc_prod, dim3(pw_blocks(V)), dim3(256), 0, st, V, coef, x, y, out);
+}
+void launch_axpy(long long V, double coef, const double* x, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy, dim3(pw_blocks(V)), dim3(256), 0, st, V, coef, x, out);
+}
+void launch_xpay(long long V, const double* x, double coef, const double* y, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_xpay, dim3(pw_blocks(V)), dim3(256), 0, st, V, x, coef, y, out);
+}
+void launch_sl_adj(const SLAdjArgs& a, hipStream_t st) {
+  const long long V = (long long)a.n_grid * a.n_grid * a.n_grid;
+  hipLaunchKernelGGL(k_sl_adj, dim3(pw_blocks(V)), dim3(256), 0, st, a);
+}
+int ic_adj_blocks(int n) { return rblocks((long long)n * n * n); }
+void launch_ic_adj(int n, const double* ic, int n_ic, const double* lam_p, double* part, double* out,
+                   hipStream_t st) {
+  if (n_ic <= 0) return;
+  const int nb = ic_adj_blocks(n);
+  hipLaunchKernelGGL(k_ic_adj, dim3(nb, n_ic), dim3(256), 0, st, n, ic, n_ic, lam_p, part);
+  hipLaunchKernelGGL(k_ic_adj_sum, dim3((n_ic + 63) / 64), dim3(64), 0, st, part, nb, n_ic, out);
+}
+
+}  // namespace tumor

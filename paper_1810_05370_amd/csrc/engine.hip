@@ -19,6 +19,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.hpp"
 #include "kernels.hpp"
 #include "passes.hpp"
 #include "tumor.h"
@@ -85,7 +86,7 @@ int check_cfg(const tumor_config* c) {
   if (!(c->rtol_diff > 0.0 && c->rtol_diff < 1.0)) return TUMOR_EINVAL;
   if (!(c->rtol_elast > 0.0 && c->rtol_elast < 1.0)) return TUMOR_EINVAL;
   if (c->max_it < 1) return TUMOR_EINVAL;
-  if (c->flags & ~TUMOR_F_DEFAULT) return TUMOR_EINVAL;
+  if (c->flags & ~(TUMOR_F_DEFAULT | TUMOR_F_ADJOINT)) return TUMOR_EINVAL;
   for (int k = 0; k < 4; ++k)
     if (c->reserved[k] != 0) return TUMOR_EINVAL;
   return TUMOR_OK;
@@ -114,9 +115,20 @@ struct tumor_ctx {
   int n;
   long long V, S;
   bool mixed;
+  bool adj;  // adjoint scratch present
   int flags;
   double* F[8];
   double* G[8];
+  double* Rdd[3];  // diffusion outputs i'', o', l' (kept for the adjoint)
+  // adjoint scratch (TUMOR_F_ADJOINT)
+  double *MB, *LB, *EB, *TB, *T[4], *Y[3], *KB, *RB, *IDD, *DDB, *SLO[6], *DB, *VB[3];
+  tumor::GradScalars* gs;
+  // recording for the adjoint
+  char* tape;
+  size_t tape_bytes;
+  int rec_active, rec_nsteps, rec_K, rec_steps, rev_done, win_start;
+  int n_ic;
+  double* ic_host;  // n_ic x (cx, cy, cz, sigma, weight)
   cplx<double>* U;
   cplx<double>* Up;
   cplx<double>* Un;
@@ -133,7 +145,7 @@ struct tumor_ctx {
   // host side
   tumor::SolveScalars* hsv;
   tumor::CoefScalars* hcs;
-  int pred[4];
+  int pred[8];
   int forced[4];
   bool has_forced;
   tumor::RefreshConsts fc;
@@ -232,6 +244,23 @@ void layout(Ctx& c, Carver& cv) {
   c.p32.mu = c.mu32;
   c.p32.lam = c.lam32;
   c.p32.eta = c.eta32;
+  for (int k = 0; k < 3; ++k) c.Rdd[k] = cv.take<double>(V);
+  if (c.adj) {
+    c.MB = cv.take<double>(V);
+    c.LB = cv.take<double>(V);
+    c.EB = cv.take<double>(V);
+    c.TB = cv.take<double>(V);
+    for (int k = 0; k < 4; ++k) c.T[k] = cv.take<double>(V);
+    for (int k = 0; k < 3; ++k) c.Y[k] = cv.take<double>(V);
+    c.KB = cv.take<double>(V);
+    c.RB = cv.take<double>(V);
+    c.IDD = cv.take<double>(V);
+    c.DDB = cv.take<double>(V);
+    for (int k = 0; k < 6; ++k) c.SLO[k] = cv.take<double>(V);
+    c.DB = cv.take<double>(V);
+    for (int k = 0; k < 3; ++k) c.VB[k] = cv.take<double>(V);
+    c.gs = cv.take<tumor::GradScalars>(1);
+  }
   c.sv64 = cv.take<tumor::SolveScalars>(1);
   c.sv32 = cv.take<tumor::SolveScalars>(1);
   c.cs = cv.take<tumor::CoefScalars>(1);
@@ -245,6 +274,7 @@ size_t workspace_size(const tumor_config& cfg) {
   c.V = (long long)cfg.n * cfg.n * cfg.n;
   c.S = c.V / 2;
   c.mixed = cfg.precision == TUMOR_PREC_MIXED;
+  c.adj = (cfg.flags & TUMOR_F_ADJOINT) != 0;
   Carver cv{nullptr, 0, true};
   layout(c, cv);
   return (cv.off + 255) & ~size_t(255);
@@ -587,7 +617,7 @@ SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cp
   }
   const double thr2 = rtol * rtol * bb;
   int forced = -1;
-  if (c.has_forced && which >= 0) forced = c.forced[which];
+  if (c.has_forced && which >= 0 && which < 4) forced = c.forced[which];
   if (forced < 0 && rr <= thr2) {
     so.relres = std::sqrt(rr / bb);
     return so;
@@ -838,12 +868,13 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
   }
   // S2: Crank-Nicolson diffusion of i, o (and l).
   SolveOut sd[3];
-  sd[0] = cn_solve(c, c.G[I], c.F[I], 0);
-  sd[1] = cn_solve(c, c.F[O], c.F[O], 1);
-  if (c.flags & TUMOR_F_EDEMA) sd[2] = cn_solve(c, c.F[L], c.F[L], 2);
+  sd[0] = cn_solve(c, c.G[I], c.Rdd[0], 0);
+  sd[1] = cn_solve(c, c.F[O], c.Rdd[1], 1);
+  if (c.flags & TUMOR_F_EDEMA) sd[2] = cn_solve(c, c.F[L], c.Rdd[2], 2);
+  else HIPCHECK(hipMemcpyAsync(c.Rdd[2], c.F[L], c.V * sizeof(double), hipMemcpyDeviceToDevice, c.st));
   // S3-S5: reaction, oxygen, edema, refresh.
   {
-    const double* in[9] = {c.G[P], c.G[I], c.F[I], c.G[N], c.G[G], c.G[W], c.F[O], c.F[L], c.G[F]};
+    const double* in[9] = {c.G[P], c.G[I], c.Rdd[0], c.G[N], c.G[G], c.G[W], c.Rdd[1], c.Rdd[2], c.G[F]};
     double* out[8] = {c.F[P], c.F[I], c.F[N], c.F[G], c.F[W], c.F[O], c.F[L], c.F[F]};
     refresh(c, 1, in, out);
   }
@@ -953,6 +984,270 @@ void apply_op_t(Ctx& c, int op, const double* in, double* out) {
   }
 }
 
+// ------------------------------------------------------------------ adjoint
+size_t slot_doubles(long long V) { return (size_t)(14 * V); }
+size_t slot_bytes(long long V) { return (slot_doubles(V) * sizeof(double) + 255) & ~size_t(255); }
+
+double* tape_slot(Ctx& c, int k) { return reinterpret_cast<double*>(c.tape + (size_t)k * slot_bytes(c.V)); }
+int n_ckpt(int nsteps, int K) { return (nsteps + K - 1) / K; }
+
+void save_state(Ctx& c, double* slot) {
+  const size_t fb = c.V * sizeof(double);
+  for (int k = 0; k < 8; ++k) HIPCHECK(hipMemcpyAsync(slot + k * c.V, c.F[k], fb, hipMemcpyDeviceToDevice, c.st));
+  const size_t ub = 3 * c.S * sizeof(cplx<double>);
+  HIPCHECK(hipMemcpyAsync(slot + 8 * c.V, c.U, ub, hipMemcpyDeviceToDevice, c.st));
+  HIPCHECK(hipMemcpyAsync(slot + 11 * c.V, c.Up, ub, hipMemcpyDeviceToDevice, c.st));
+}
+
+void load_state(Ctx& c, const double* slot) {
+  const size_t fb = c.V * sizeof(double);
+  for (int k = 0; k < 8; ++k) HIPCHECK(hipMemcpyAsync(c.F[k], slot + k * c.V, fb, hipMemcpyDeviceToDevice, c.st));
+  const size_t ub = 3 * c.S * sizeof(cplx<double>);
+  HIPCHECK(hipMemcpyAsync(c.U, slot + 8 * c.V, ub, hipMemcpyDeviceToDevice, c.st));
+  HIPCHECK(hipMemcpyAsync(c.Up, slot + 11 * c.V, ub, hipMemcpyDeviceToDevice, c.st));
+  refresh_state(c);
+}
+
+// out = G_a in1 + G_b in2 (physical, FP64), derivatives along a, b (0, 1, 2 = x, y, z).
+void inv3_sum(Ctx& c, const cplx<double>* in1, int a, const cplx<double>* in2, int b, double* out) {
+  PrecBufs<double>& P = c.p64;
+  colp<double>(c, 2, true, Prog().in(0, in1).in(1, in2).out(P.A[0], {a == 2 ? TW(0) : T1(0)}).out(
+                                P.A[1], {b == 2 ? TW(1) : T1(1)}));
+  colp<double>(c, 1, true,
+               Prog().in(0, P.A[0]).in(1, P.A[1]).out(P.B[0], {a == 1 ? TW(0) : T1(0)}).out(
+                   P.B[1], {b == 1 ? TW(1) : T1(1)}));
+  Prog x;
+  x.in(0, P.B[0]).in(1, P.B[1]).out(out, {a == 0 ? TW(0) : T1(0), b == 0 ? TW(1) : T1(1)});
+  tumor::launch_xinv<double>(c.n, to_x(x.p, 1.0 / (double)c.V), P.tw, c.st);
+}
+
+void zero(Ctx& c, double* p, long long count) {
+  HIPCHECK(hipMemsetAsync(p, 0, count * sizeof(double), c.st));
+}
+
+// Adjoint solve A y = rhs (physical rhs, ncomp blocks) with x0 = 0; y stays
+// spectral in c.Un.  kind: diffusion (A = 1 - dt/2 D_K) or elasticity.
+SolveOut adjoint_solve(Ctx& c, int ncomp, const double* rhs, int which) {
+  for (int k = 0; k < ncomp; ++k) fwd3<double>(c, rhs + k * c.V, nullptr, c.b64 + k * c.S);
+  cplx<double>* x = c.Un;
+  HIPCHECK(hipMemsetAsync(x, 0, ncomp * c.S * sizeof(cplx<double>), c.st));
+  const double h = 0.5 * c.cfg.dt;
+  auto r0 = [&](tumor::KrylovArgs& a) {
+    a.ax = nullptr;
+    tumor::launch_residual<double>(a, nullptr, c.st);
+  };
+  if (ncomp == 1) {
+    auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip) { diff_apply<double>(c, p, q, 1.0, -h, skip); };
+    auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip) { diff_apply<float>(c, p, q, 1.0, -h, skip); };
+    return solve_system(c, 1, tumor::PREC_DIFF, h, x, c.b64, c.cfg.rtol_diff, which, A64, A32, r0);
+  }
+  auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip) { elast_apply<double>(c, p, q, skip); };
+  auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip) { elast_apply<float>(c, p, q, skip); };
+  return solve_system(c, 3, tumor::PREC_ELAST, 0.0, x, c.b64, c.cfg.rtol_elast, which, A64, A32, r0);
+}
+
+// CN adjoint: y = A^-1 cbar_plus; out = (1 + dt/2 D) y; KB += -dt/2 sum_a G_a y G_a (c- + c+).
+void cn_adjoint(Ctx& c, const double* cbar_plus, double* out, const double* cm, const double* cp, int which) {
+  adjoint_solve(c, 1, cbar_plus, which);
+  const double h = 0.5 * c.cfg.dt;
+  PrecBufs<double>& P = c.p64;
+  diff_apply<double>(c, c.Un, P.q, 1.0, h, nullptr);
+  inv3<double>(c, P.q, out, 1.0 / (double)c.V);
+  fwd3<double>(c, cm, cp, P.r);  // spectrum of c- + c+
+  for (int a = 0; a < 3; ++a) {
+    inv3<double>(c, c.Un, c.T[0], 1.0 / (double)c.V, a);
+    inv3<double>(c, P.r, c.T[1], 1.0 / (double)c.V, a);
+    tumor::launch_acc_prod(c.V, -h, c.T[0], c.T[1], c.KB, c.st);
+  }
+}
+
+// Reverse one recorded step.  On entry the forward step from X^m has just been
+// recomputed: F = q^{m+1}, U = u^{m+1}, Up = u^m, G = transported fields,
+// Rdd = (i'', o', l'), vel = (v^m, div v^m); x0 holds X^m.
+void adjoint_core(Ctx& c, const double* x0, double* adj, int m, double* grad) {
+  enum { P, I, N, O, L, G, W, F };
+  const long long V = c.V;
+  double* Lm[14];
+  for (int k = 0; k < 14; ++k) Lm[k] = adj + k * V;
+  const double* F0[8];
+  for (int k = 0; k < 8; ++k) F0[k] = x0 + k * V;
+  const double iV = 1.0 / (double)V;
+  HIPCHECK(hipMemsetAsync(c.gs, 0, sizeof(tumor::GradScalars), c.st));
+  zero(c, c.KB, V);
+  PrecBufs<double>& PB = c.p64;
+  // ---- S6 elasticity and force, S5 mixture
+  if (c.flags & TUMOR_F_ELASTICITY) {
+    adjoint_solve(c, 3, Lm[8], 7);  // y (spectral) in Un
+    zero(c, c.EB, V);
+    zero(c, c.MB, V);
+    zero(c, c.T[2], V);
+    zero(c, c.T[3], V);
+    for (int a = 0; a < 3; ++a) {
+      inv3<double>(c, c.Un + a * c.S, c.Y[a], iV);
+      inv3<double>(c, c.U + a * c.S, c.T[0], iV);
+      tumor::launch_acc_prod(V, -1.0, c.Y[a], c.T[0], c.EB, c.st);
+    }
+    for (int a = 0; a < 3; ++a) {
+      for (int b = a; b < 3; ++b) {
+        inv3_sum(c, c.Un + a * c.S, b, c.Un + b * c.S, a, c.T[0]);
+        inv3_sum(c, c.U + a * c.S, b, c.U + b * c.S, a, c.T[1]);
+        tumor::launch_acc_prod(V, a == b ? -0.5 : -1.0, c.T[0], c.T[1], c.MB, c.st);
+        if (a == b) {
+          tumor::launch_axpy(V, 0.5, c.T[0], c.T[2], c.st);
+          tumor::launch_axpy(V, 0.5, c.T[1], c.T[3], c.st);
+        }
+      }
+    }
+    zero(c, c.LB, V);
+    tumor::launch_acc_prod(V, -1.0, c.T[2], c.T[3], c.LB, c.st);
+    // force: tau = p' + n', b_bar = -y
+    zero(c, c.TB, V);
+    fwd3<double>(c, c.F[P], c.F[N], PB.r);
+    for (int a = 0; a < 3; ++a) {
+      inv3<double>(c, PB.r, c.T[0], iV, a);
+      tumor::launch_force_adj(V, c.prm.zeta, c.F[P], c.F[N], c.T[0], c.Y[a], c.TB, c.T[1], c.st);
+      fwd3<double>(c, c.T[1], nullptr, PB.p);
+      inv3<double>(c, PB.p, c.T[0], iV, a);
+      tumor::launch_axpy(V, -1.0, c.T[0], c.TB, c.st);
+    }
+    tumor::launch_axpy(V, 1.0, c.TB, Lm[P], c.st);
+    tumor::launch_axpy(V, 1.0, c.TB, Lm[N], c.st);
+    tumor::CoefAdjArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.mub = c.MB;
+    ca.lamb = c.LB;
+    ca.etab = c.EB;
+    ca.p1 = c.F[P];
+    ca.i1 = c.F[I];
+    ca.n1 = c.F[N];
+    ca.g1 = c.F[G];
+    ca.w1 = c.F[W];
+    ca.f1 = c.F[F];
+    for (int k = 0; k < 8; ++k) ca.L[k] = Lm[k];
+    ca.fc = c.fc;
+    ca.inv_scale = 1.0 / c.prm.lame_scale;
+    ca.partials = c.partials;
+    ca.gs = c.gs;
+    ca.V = V;
+    tumor::launch_coef_adj(ca, c.st);
+  } else {
+    for (int a = 0; a < 3; ++a) tumor::launch_axpy(V, 1.0, Lm[8 + a], Lm[11 + a], c.st);
+  }
+  // ---- S4b, S4, S3
+  {
+    tumor::ReactAdjArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.p_dag = c.G[P];
+    ra.i_dag = c.G[I];
+    ra.i_dd = c.Rdd[0];
+    ra.n_dag = c.G[N];
+    ra.g_dag = c.G[G];
+    ra.w_dag = c.G[W];
+    ra.o_dag = c.Rdd[1];
+    ra.i1 = c.F[I];
+    ra.g1 = c.F[G];
+    ra.w1 = c.F[W];
+    ra.w0 = F0[W];
+    ra.g0 = F0[G];
+    ra.rho_w = c.prm.rho_w;
+    ra.rho_g = c.prm.rho_g;
+    const int ids[7] = {P, I, N, O, L, G, W};
+    for (int k = 0; k < 7; ++k) ra.L[k] = Lm[ids[k]];
+    ra.idd = c.IDD;
+    ra.ddb = c.DDB;
+    ra.rb = c.RB;
+    ra.V = V;
+    ra.rc = c.rc;
+    tumor::launch_react_adj(ra, c.st);
+  }
+  // ---- S2 (coefficients K of the step start)
+  {
+    const double* in[9] = {F0[P], F0[I], F0[I], F0[N], F0[G], F0[W], F0[O], F0[L], F0[F]};
+    double* out[8] = {nullptr};
+    refresh(c, 0, in, out);
+  }
+  cn_adjoint(c, c.IDD, Lm[I], c.G[I], c.Rdd[0], 4);
+  tumor::launch_axpy(V, -1.0, c.DDB, Lm[I], c.st);
+  cn_adjoint(c, Lm[O], Lm[O], F0[O], c.Rdd[1], 5);
+  if (c.flags & TUMOR_F_EDEMA) cn_adjoint(c, Lm[L], Lm[L], F0[L], c.Rdd[2], 6);
+  // ---- S1 transport
+  if (c.flags & TUMOR_F_ADVECTION) {
+    for (int k = 0; k < 6; ++k) zero(c, c.SLO[k], V);
+    zero(c, c.DB, V);
+    for (int k = 0; k < 3; ++k) zero(c, c.VB[k], V);
+    tumor::SLAdjArgs sa;
+    sa.vx = c.vel[0];
+    sa.vy = c.vel[1];
+    sa.vz = c.vel[2];
+    sa.div = c.vel[3];
+    const int ids[6] = {P, I, N, G, W, F};
+    for (int k = 0; k < 6; ++k) {
+      sa.q[k] = F0[ids[k]];
+      sa.lam[k] = Lm[ids[k]];
+      sa.out[k] = c.SLO[k];
+    }
+    sa.divb = c.DB;
+    for (int k = 0; k < 3; ++k) sa.vb[k] = c.VB[k];
+    sa.n_grid = c.n;
+    sa.dt = c.cfg.dt;
+    sa.s = c.cfg.dt / (2.0 * M_PI / c.n);
+    tumor::launch_sl_adj(sa, c.st);
+    fwd3<double>(c, c.DB, nullptr, PB.r);
+    for (int a = 0; a < 3; ++a) {
+      inv3<double>(c, PB.r, c.T[0], iV, a);
+      tumor::launch_axpy(V, -1.0, c.T[0], c.VB[a], c.st);
+    }
+    for (int k = 0; k < 6; ++k)
+      HIPCHECK(hipMemcpyAsync(Lm[ids[k]], c.SLO[k], V * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+  } else {
+    for (int k = 0; k < 3; ++k) zero(c, c.VB[k], V);
+  }
+  // ---- S0
+  {
+    tumor::S0AdjArgs sa;
+    sa.Kb = c.KB;
+    sa.rb = c.RB;
+    sa.w0 = F0[W];
+    sa.g0 = F0[G];
+    sa.f0 = F0[F];
+    sa.Lw = Lm[W];
+    sa.Lg = Lm[G];
+    sa.Lf = Lm[F];
+    sa.k_w = c.prm.k_w;
+    sa.k_g = c.prm.k_g;
+    sa.k_f = c.prm.k_f;
+    sa.rho_w = c.prm.rho_w;
+    sa.rho_g = c.prm.rho_g;
+    sa.partials = c.partials;
+    sa.gs = c.gs;
+    sa.V = V;
+    tumor::launch_s0_adj(sa, c.st);
+  }
+  // ---- displacement slots: v = (u^m - u^{m-1}) / dt
+  const double idt = 1.0 / c.cfg.dt;
+  for (int a = 0; a < 3; ++a) {
+    tumor::launch_xpay(V, Lm[11 + a], idt, c.VB[a], Lm[8 + a], c.st);
+    HIPCHECK(hipMemsetAsync(Lm[11 + a], 0, V * sizeof(double), c.st));
+    tumor::launch_axpy(V, -idt, c.VB[a], Lm[11 + a], c.st);
+  }
+  // ---- initial-condition weights after the first step
+  double* icg = nullptr;
+  if (m == 0 && c.n_ic > 0) {
+    HIPCHECK(hipMemcpyAsync(c.T[2], c.ic_host, 5 * (size_t)c.n_ic * sizeof(double), hipMemcpyHostToDevice, c.st));
+    tumor::launch_ic_adj(c.n, c.T[2], c.n_ic, Lm[P], c.T[3], c.T[1], c.st);
+    icg = c.T[1];
+  }
+  HIPCHECK(hipGetLastError());
+  tumor::GradScalars hg;
+  HIPCHECK(hipMemcpyAsync(&hg, c.gs, sizeof(hg), hipMemcpyDeviceToHost, c.st));
+  std::vector<double> gic(c.n_ic > 0 ? c.n_ic : 1);
+  if (icg) HIPCHECK(hipMemcpyAsync(gic.data(), icg, c.n_ic * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIPCHECK(hipStreamSynchronize(c.st));
+  for (int k = 0; k < 5; ++k) grad[k] += hg.g[k];
+  if (icg)
+    for (int k = 0; k < c.n_ic; ++k) grad[5 + k] += gic[k];
+}
+
 template <typename Fn>
 int guarded(Fn fn) {
   try {
@@ -1029,7 +1324,9 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
     c->V = V;
     c->S = V / 2;
     c->mixed = cfg->precision == TUMOR_PREC_MIXED;
-    c->flags = cfg->flags == 0 ? TUMOR_F_DEFAULT : cfg->flags;
+    c->adj = (cfg->flags & TUMOR_F_ADJOINT) != 0;
+    c->flags = (cfg->flags & TUMOR_F_DEFAULT) == 0 ? TUMOR_F_DEFAULT : (cfg->flags & TUMOR_F_DEFAULT);
+    c->win_start = -1;
     int dev_count = 0;
     if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) throw Fail(TUMOR_EDEVICE, "no HIP device");
     Carver cv{static_cast<char*>(workspace), 0, false};
@@ -1040,8 +1337,8 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
     HIPCHECK(hipHostMalloc(&h2, sizeof(tumor::CoefScalars), hipHostMallocDefault));
     c->hsv = static_cast<tumor::SolveScalars*>(h1);
     c->hcs = static_cast<tumor::CoefScalars*>(h2);
-    c->pred[0] = c->pred[1] = c->pred[2] = 6;
-    c->pred[3] = 30;
+    c->pred[0] = c->pred[1] = c->pred[2] = c->pred[4] = c->pred[5] = c->pred[6] = 6;
+    c->pred[3] = c->pred[7] = 30;
     c->cur_tag = -1;
     set_consts(*c);
     twiddles(*c);
@@ -1071,6 +1368,9 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
         HIPCHECK(hipMemcpyAsync(c->G[0], ic.data(), ic.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
       tumor::launch_ic(c->n, c->G[0], n_ic, c->F[P], c->st);
       HIPCHECK(hipStreamSynchronize(c->st));  // host vectors go out of scope
+      c->n_ic = n_ic;
+      c->ic_host = new double[5 * (size_t)n_ic + 1];
+      std::memcpy(c->ic_host, ic.data(), ic.size() * sizeof(double));
     }
     const size_t ub = 3 * c->S * sizeof(cplx<double>);
     HIPCHECK(hipMemsetAsync(c->U, 0, ub, c->st));
@@ -1084,6 +1384,7 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
   if (rc != TUMOR_OK) {
     if (c->hsv) (void)hipHostFree(c->hsv);
     if (c->hcs) (void)hipHostFree(c->hcs);
+    delete[] c->ic_host;
     delete c;
     return rc;
   }
@@ -1097,8 +1398,13 @@ int tumor_step(tumor_ctx* ctx, int32_t nsteps, tumor_step_stats* last) {
   return guarded([&]() -> int {
     int status = TUMOR_OK;
     tumor_step_stats st;
+    Ctx& c = *ctx;
     for (int s = 0; s < nsteps; ++s) {
-      do_step(*ctx, &st, status);
+      if (c.rec_active && c.rev_done == 0 && c.rec_steps < c.rec_nsteps) {
+        if (c.rec_steps % c.rec_K == 0) save_state(c, tape_slot(c, c.rec_steps / c.rec_K));
+        c.rec_steps++;
+      }
+      do_step(c, &st, status);
       if (status == TUMOR_ENAN) break;
     }
     if (last && nsteps > 0) *last = st;
@@ -1232,30 +1538,75 @@ int tumor_force_iterations(tumor_ctx* ctx, const int32_t* iters) {
 }
 
 int tumor_tape_bytes(const tumor_config* cfg, int32_t nsteps, int32_t ckpt_every, size_t* bytes) {
-  (void)cfg;
-  (void)nsteps;
-  (void)ckpt_every;
-  (void)bytes;
-  g_err = "the adjoint tape is not available in this build";
-  return TUMOR_ESTATE;
+  if (check_cfg(cfg) != TUMOR_OK) return einval("invalid tumor_config");
+  if (!bytes) return einval("bytes is NULL");
+  if (nsteps < 1 || ckpt_every < 1) return einval("nsteps and ckpt_every must be >= 1");
+  const long long V = (long long)cfg->n * cfg->n * cfg->n;
+  const int K = std::min(ckpt_every, nsteps);
+  *bytes = (size_t)(n_ckpt(nsteps, K) + K) * slot_bytes(V);
+  return TUMOR_OK;
 }
 
 int tumor_record(tumor_ctx* ctx, int32_t nsteps, int32_t ckpt_every, void* tape, size_t tape_bytes) {
-  (void)ctx;
-  (void)nsteps;
-  (void)ckpt_every;
-  (void)tape;
-  (void)tape_bytes;
-  g_err = "the adjoint tape is not available in this build";
-  return TUMOR_ESTATE;
+  if (!ctx) return einval("ctx is NULL");
+  if (!ctx->adj) {
+    g_err = "the context was created without TUMOR_F_ADJOINT";
+    return TUMOR_ESTATE;
+  }
+  if (nsteps < 1 || ckpt_every < 1) return einval("nsteps and ckpt_every must be >= 1");
+  if (!tape || (reinterpret_cast<uintptr_t>(tape) & 255u)) return einval("tape must be a 256-byte aligned device pointer");
+  size_t need = 0;
+  int rc = tumor_tape_bytes(&ctx->cfg, nsteps, ckpt_every, &need);
+  if (rc != TUMOR_OK) return rc;
+  if (tape_bytes < need) {
+    g_err = "tape too small: need " + std::to_string(need) + " bytes";
+    return TUMOR_ENOMEM;
+  }
+  if (ctx->n_ic > 256) return einval("the adjoint supports at most 256 initial-condition centres");
+  ctx->tape = static_cast<char*>(tape);
+  ctx->tape_bytes = tape_bytes;
+  ctx->rec_active = 1;
+  ctx->rec_nsteps = nsteps;
+  ctx->rec_K = std::min(ckpt_every, nsteps);
+  ctx->rec_steps = 0;
+  ctx->rev_done = 0;
+  ctx->win_start = -1;
+  return TUMOR_OK;
 }
 
 int tumor_adjoint_step(tumor_ctx* ctx, double* adj, double* grad) {
   if (!ctx) return einval("ctx is NULL");
-  (void)adj;
-  (void)grad;
-  g_err = "no recorded forward step to reverse";
-  return TUMOR_ESTATE;
+  if (!adj || !grad) return einval("adj/grad is NULL");
+  if (!ctx->rec_active || ctx->rec_steps - ctx->rev_done <= 0) {
+    g_err = "no recorded forward step left to reverse";
+    return TUMOR_ESTATE;
+  }
+  return guarded([&]() -> int {
+    Ctx& c = *ctx;
+    const int m = c.rec_steps - 1 - c.rev_done;
+    const int K = c.rec_K;
+    const int nck = n_ckpt(c.rec_nsteps, K);
+    if (c.win_start < 0 || m < c.win_start || m >= c.win_start + K) {
+      // rebuild the window of states X^ws .. X^m from checkpoint m / K
+      const int ws = (m / K) * K;
+      load_state(c, tape_slot(c, m / K));
+      int status = TUMOR_OK;
+      for (int j = ws; j <= m; ++j) {
+        save_state(c, tape_slot(c, nck + (j - ws)));
+        if (j < m) do_step(c, nullptr, status);
+      }
+      if (status == TUMOR_ENAN) throw Fail(TUMOR_ENAN, "non-finite value while recomputing the forward window");
+      c.win_start = ws;
+    }
+    const double* x0 = tape_slot(c, nck + (m - c.win_start));
+    load_state(c, x0);
+    int status = TUMOR_OK;
+    do_step(c, nullptr, status);
+    if (status == TUMOR_ENAN) throw Fail(TUMOR_ENAN, "non-finite value while recomputing the forward step");
+    adjoint_core(c, x0, adj, m, grad);
+    c.rev_done++;
+    return TUMOR_OK;
+  });
 }
 
 int tumor_kernel_timer(tumor_ctx* ctx, int32_t kernel_class, int32_t enable) {
@@ -1304,6 +1655,7 @@ void tumor_destroy(tumor_ctx* ctx) {
   }
   if (ctx->hsv) (void)hipHostFree(ctx->hsv);
   if (ctx->hcs) (void)hipHostFree(ctx->hcs);
+  delete[] ctx->ic_host;
   delete ctx;
 }
 
