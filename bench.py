@@ -69,6 +69,42 @@ def run_form(tm, torch, inp, P, precision, steps, warmup):
     return dict(wall=wall, gpu_ms=gpu_ms, stats=stats, warm_profile=prof, dominant=dominant, dom=dom)
 
 
+def run_adjoint(tm, torch, inp, P, precision, steps, warmup, ckpt):
+    """Forward + adjoint throughput: `steps` recorded steps then their reverse sweep."""
+    import numpy as np
+    torch.cuda.reset_peak_memory_stats()
+    sim = tm.from_inputs(inp, P, precision=precision, flags=tm.F_DEFAULT | tm.F_ADJOINT)
+    for k in range(warmup):
+        sim.step(1)
+    sim.record(steps, ckpt)
+    n = inp["n"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tau = sim.get("p") + sim.get("i") + sim.get("n")
+    lam = torch.zeros((14, n, n, n), dtype=torch.float64, device=tau.device)
+    h3 = (2 * np.pi / n) ** 3
+    for k in range(3):
+        lam[k].copy_(h3 * 0.1 * tau)          # seed of 1/2 h^3 ||tau - 0.9 tau||^2
+    grad = np.zeros(5 + len(inp["weights"]))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for k in range(steps):
+        sim.adjoint_step(lam, grad)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    peak = torch.cuda.max_memory_allocated() / 2 ** 30
+    log(f"[{precision} adjoint] {steps} recorded steps {t1 - t0:.2f} s, reverse sweep {t3 - t2:.2f} s "
+        f"(checkpoint every {ckpt}); peak allocated {peak:.1f} GiB")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return dict(fwd_s=t1 - t0, adj_s=t3 - t2, steps_per_s=steps / ((t1 - t0) + (t3 - t2)), peak_gib=peak,
+                grad_head=[float(v) for v in grad[:5]])
+
+
 def roofline(dom, name=None, n=256):
     import paper_1810_05370_amd as tm
     if dom["launches"] == 0 or dom["ms"] <= 0:
@@ -165,6 +201,10 @@ def main():
     ap.add_argument("--workload", default="c3", help="synthetic workload name (default: the 256^3 case)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint form")
+    ap.add_argument("--adjoint-workload", default="c5", help="workload of the forward+adjoint form")
+    ap.add_argument("--adjoint-steps", type=int, default=10)
+    ap.add_argument("--ckpt-every", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this implementation runs one simulation on exactly one GPU; "
@@ -207,6 +247,18 @@ def main():
     extra["warmup_kernel_ms"] = {c: round(v["ms"], 2) for c, v in main_run["warm_profile"].items() if v["ms"] > 0}
     extra["wall_s"] = round(main_run["wall"], 4)
     rl = roofline(main_run["dom"], main_run["dominant"], n)
+
+    if not args.no_adjoint:
+        ainp = synthetic.workload_inputs(args.adjoint_workload)
+        for prec in (("mixed", "fp64") if not args.no_fp64 else ("mixed",)):
+            r = run_adjoint(tm, torch, ainp, P, prec, args.adjoint_steps, 2, args.ckpt_every)
+            key = "fwd_adjoint_steps_per_s" if prec == "mixed" else "fwd_adjoint_fp64_steps_per_s"
+            extra[key] = round(r["steps_per_s"], 4)
+            extra[key.replace("steps_per_s", "detail")] = dict(
+                workload=f"{args.adjoint_workload}: {ainp['n']}^3, {len(ainp['weights'])} initial-condition weights",
+                recorded_steps=args.adjoint_steps, ckpt_every=args.ckpt_every, forward_s=round(r["fwd_s"], 3),
+                reverse_s=round(r["adj_s"], 3), peak_allocated_gib=round(r["peak_gib"], 2),
+                grad_rho_kw_kg_kf_scale=r["grad_head"])
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -112,3 +112,36 @@ def test_adjoint_requires_a_recording():
         sim.record(2, 1)          # no adjoint scratch in this context
     assert e.value.code == tm.ESTATE
     sim.close()
+
+
+def test_autograd_function_gradient_and_directional_fd():
+    torch = need_gpu()
+    from paper_1810_05370_amd.autograd import SimSpec, simulate, theta_from
+    steps = 3
+    P, inp, target = _case("c4", 16, steps, dict(delta_p=60.0))
+    spec = SimSpec(inputs=inp, params=P, steps=steps, ckpt_every=2, rtol=1e-12, max_it=2000)
+    h3 = (2 * np.pi / 16) ** 3
+    tgt = torch.as_tensor(target).cuda()
+
+    def loss_of(theta):
+        tau = simulate(theta, spec)
+        return 0.5 * h3 * ((tau - tgt) ** 2).sum()
+
+    theta = theta_from(P, inp["weights"]).requires_grad_(True)
+    L = loss_of(theta)
+    L.backward()
+    g = theta.grad.numpy()
+    # against the oracle
+    L_o, gr, gw, lam_o = adj.gradient(P, inp, steps, target, ORACLE_CFG)
+    g_o = np.array([gr[k] for k in adj.GRAD_NAMES] + list(gw))
+    assert abs(L.item() - L_o) < 1e-9 * L_o
+    assert rel_l2(g, g_o) < 1e-8
+    # directional central difference on the GPU
+    rng = np.random.default_rng(5)
+    d = torch.as_tensor(rng.standard_normal(g.size) * np.r_[1.0, 0.01, 0.01, 0.01, 0.1, 0.05 * np.ones(g.size - 5)])
+    e = 1e-6
+    with torch.no_grad():
+        th = theta.detach()
+        fd = (loss_of(th + e * d).item() - loss_of(th - e * d).item()) / (2 * e)
+    say("directional", fd, float(g @ d.numpy()))
+    assert abs(fd - g @ d.numpy()) < 1e-6 * abs(fd)
