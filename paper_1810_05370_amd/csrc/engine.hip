@@ -330,6 +330,14 @@ constexpr ColTerm T1(int s, double c = 1.0) { return ColTerm{s, SYM_ONE, c}; }
 constexpr ColTerm TW(int s, double c = 1.0) { return ColTerm{s, SYM_IW, c}; }
 constexpr ColTerm TR(int s, double c = 1.0) { return ColTerm{s, SYM_RAW, c}; }
 
+// Krylov work fused into an operator apply (see ZPUpdateArgs / ColProg.dsv).
+struct Fuse {
+  bool pupdate;  // first pass: p = M^-1 r + beta p (in place) before transforming p
+  const void* r;
+  tumor::SolveScalars* sv;
+  tumor::PrecConsts pc;
+};
+
 template <typename R>
 void colp(Ctx& c, int axis, bool inv, const Prog& pr) {
   bool used[tumor::kMaxCol] = {false};
@@ -337,7 +345,10 @@ void colp(Ctx& c, int axis, bool inv, const Prog& pr) {
     for (int q = 0; q < pr.p.nterm[o]; ++q) used[pr.p.term[o][q].src] = true;
   int nin = 0;
   for (int k = 0; k < tumor::kMaxCol; ++k) nin += used[k] ? 1 : 0;
-  const double bytes = double(nin + pr.p.nout) * double(c.V) * sizeof(R);
+  int ndot = 0;
+  if (pr.p.dsv)
+    for (int o = 0; o < pr.p.nout; ++o) ndot += pr.p.dotp[o] ? 1 : 0;
+  const double bytes = double(nin + pr.p.nout + ndot) * double(c.V) * sizeof(R);
   timed(c, inv ? kcls<R>(TUMOR_K_COLINV64, TUMOR_K_COLINV32) : kcls<R>(TUMOR_K_COLFWD64, TUMOR_K_COLFWD32), bytes,
         [&] { tumor::launch_col_pass<R>(c.n, axis, inv, pr.p, pb<R>(c).tw, c.st); });
 }
@@ -368,11 +379,33 @@ void inv3(Ctx& c, const cplx<R>* in, R* out, double scale, int d = -1) {
   timed(c, TUMOR_K_XOTHER, 2.0 * c.V * sizeof(R), [&] { tumor::launch_xinv<R>(c.n, to_x(x.p, scale), P.tw, c.st); });
 }
 
+// Fused first pass: p = M^-1 r + beta p, then the z-inverse transforms of p
+// and i w_z p per component into outs[2a], outs[2a+1].
+template <typename R>
+void zinv_pupdate(Ctx& c, int ncomp, const Fuse& f, cplx<R>* p, void* const* outs) {
+  tumor::ZPUpdateArgs za;
+  std::memset(&za, 0, sizeof(za));
+  za.r = f.r;
+  za.p = p;
+  for (int k = 0; k < 2 * ncomp; ++k) za.out[k] = outs[k];
+  za.sv = f.sv;
+  za.cs = c.cs;
+  za.pc = f.pc;
+  timed(c, kcls<R>(TUMOR_K_COLINV64, TUMOR_K_COLINV32), 5.0 * ncomp * double(c.V) * sizeof(R),
+        [&] { tumor::launch_zinv_pupdate<R>(c.n, ncomp, za, pb<R>(c).tw, c.st); });
+}
+
 // out = raw * in + dcoef * D in (spectral), D c = div(K grad c).
 template <typename R>
-void diff_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, double raw, double dcoef, const int* skip) {
+void diff_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, double raw, double dcoef, const int* skip,
+                const Fuse* fz = nullptr) {
   PrecBufs<R>& P = pb<R>(c);
-  colp<R>(c, 2, true, Prog().in(0, in).out(P.A[0], {T1(0)}).out(P.A[1], {TW(0)}).skip(skip));
+  if (fz && fz->pupdate) {
+    void* outs[2] = {P.A[0], P.A[1]};
+    zinv_pupdate<R>(c, 1, *fz, const_cast<cplx<R>*>(in), outs);
+  } else {
+    colp<R>(c, 2, true, Prog().in(0, in).out(P.A[0], {T1(0)}).out(P.A[1], {TW(0)}).skip(skip));
+  }
   colp<R>(c, 1, true,
           Prog().in(0, P.A[0]).in(1, P.A[1]).out(P.B[0], {T1(0)}).out(P.B[1], {TW(0)}).out(P.B[2], {T1(1)}).skip(
               skip));
@@ -393,16 +426,25 @@ void diff_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, double raw, double dcoe
   z.in(0, P.B[0]).in(1, P.B[1]).in(2, in).skip(skip);
   if (raw != 0.0) z.out(out, {TR(2, raw), T1(0, dcoef), TW(1, dcoef)});
   else z.out(out, {T1(0, dcoef), TW(1, dcoef)});
+  if (fz) {
+    z.p.dotp[0] = in;
+    z.p.dsv = fz->sv;
+    z.p.dpart = c.partials;
+  }
   colp<R>(c, 2, false, z);
 }
 
 // out = (eta - L) in on 3-component spectra.
 template <typename R>
-void elast_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, const int* skip) {
+void elast_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, const int* skip, const Fuse* fz = nullptr) {
   PrecBufs<R>& P = pb<R>(c);
   const long long S = c.S;
   auto** A = P.A;
   auto** B = P.B;
+  if (fz && fz->pupdate) {
+    void* outs[6] = {A[0], A[3], A[1], A[4], A[2], A[5]};
+    zinv_pupdate<R>(c, 3, *fz, const_cast<cplx<R>*>(in), outs);
+  } else
   colp<R>(c, 2, true,
           Prog()
               .in(0, in)
@@ -454,6 +496,11 @@ void elast_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, const int* skip) {
       .out(out + S, {T1(1), TW(4, -1.0)})
       .out(out + 2 * S, {T1(2), TW(5, -1.0)})
       .skip(skip);
+  if (fz) {
+    for (int k = 0; k < 3; ++k) zf.p.dotp[k] = in + k * S;
+    zf.p.dsv = fz->sv;
+    zf.p.dpart = c.partials;
+  }
   colp<R>(c, 2, false, zf);
 }
 
@@ -574,11 +621,11 @@ int pcg_iterate(Ctx& c, tumor::KrylovArgs a, Apply apply, double thr2, int limit
   for (;;) {
     for (int k = 0; k < chunk && launched < limit; ++k, ++launched) {
       c.cur_tag = launched;
-      apply(static_cast<const cplx<R>*>(a.p), static_cast<cplx<R>*>(a.q), skip);
-      timed(c, kc, 2.0 * vb, [&] { tumor::launch_pcg_pq<R>(a, c.st); });
+      // iteration k: (p = M^-1 r + beta p fused into the first pass for k > 0),
+      // q = A p with alpha = rho / <p, q> fused into the last pass, then x, r
+      Fuse fz{launched > 0, a.r, sv, a.pc};
+      apply(static_cast<const cplx<R>*>(a.p), static_cast<cplx<R>*>(a.q), skip, &fz);
       timed(c, kc, 6.0 * vb, [&] { tumor::launch_pcg_update<R>(a, c.st); });
-      c.cur_tag = launched + 1;  // the p update of the final iteration is skipped
-      timed(c, kc, 3.0 * vb, [&] { tumor::launch_pcg_pupdate<R>(a, c.st); });
     }
     c.cur_tag = -1;
     HIPCHECK(hipGetLastError());
@@ -692,8 +739,12 @@ SolveOut cn_solve(Ctx& c, const double* src, double* dst, int which) {
   cplx<double>* x = c.Un;  // free between elasticity solves
   cplx<double>* b = c.b64;
   fwd3<double>(c, src, nullptr, x);
-  auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip) { diff_apply<double>(c, p, q, 1.0, -h, skip); };
-  auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip) { diff_apply<float>(c, p, q, 1.0, -h, skip); };
+  auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip, const Fuse* fz = nullptr) {
+      diff_apply<double>(c, p, q, 1.0, -h, skip, fz);
+    };
+  auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip, const Fuse* fz = nullptr) {
+      diff_apply<float>(c, p, q, 1.0, -h, skip, fz);
+    };
   auto r0 = [&](tumor::KrylovArgs& a) {
     diff_apply<double>(c, x, c.p64.q, 0.0, 1.0, nullptr);
     timed(c, TUMOR_K_KRYLOV64, 4.0 * c.V * 8.0, [&] { tumor::launch_cn_residual<double>(a, x, c.p64.q, c.st); });
@@ -706,8 +757,12 @@ SolveOut cn_solve(Ctx& c, const double* src, double* dst, int which) {
 // Elasticity solve (eta - L) u = rhs, rhs spectral in b64, warm start from U.
 SolveOut elast_solve(Ctx& c, cplx<double>* x, int which) {
   HIPCHECK(hipMemcpyAsync(x, c.U, 3 * c.S * sizeof(cplx<double>), hipMemcpyDeviceToDevice, c.st));
-  auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip) { elast_apply<double>(c, p, q, skip); };
-  auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip) { elast_apply<float>(c, p, q, skip); };
+  auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip, const Fuse* fz = nullptr) {
+    elast_apply<double>(c, p, q, skip, fz);
+  };
+  auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip, const Fuse* fz = nullptr) {
+    elast_apply<float>(c, p, q, skip, fz);
+  };
   auto r0 = [&](tumor::KrylovArgs& a) {
     elast_apply<double>(c, x, c.p64.q, nullptr);
     a.ax = c.p64.q;
@@ -1037,12 +1092,20 @@ SolveOut adjoint_solve(Ctx& c, int ncomp, const double* rhs, int which) {
     tumor::launch_residual<double>(a, nullptr, c.st);
   };
   if (ncomp == 1) {
-    auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip) { diff_apply<double>(c, p, q, 1.0, -h, skip); };
-    auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip) { diff_apply<float>(c, p, q, 1.0, -h, skip); };
+    auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip, const Fuse* fz = nullptr) {
+      diff_apply<double>(c, p, q, 1.0, -h, skip, fz);
+    };
+    auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip, const Fuse* fz = nullptr) {
+      diff_apply<float>(c, p, q, 1.0, -h, skip, fz);
+    };
     return solve_system(c, 1, tumor::PREC_DIFF, h, x, c.b64, c.cfg.rtol_diff, which, A64, A32, r0);
   }
-  auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip) { elast_apply<double>(c, p, q, skip); };
-  auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip) { elast_apply<float>(c, p, q, skip); };
+  auto A64 = [&](const cplx<double>* p, cplx<double>* q, const int* skip, const Fuse* fz = nullptr) {
+    elast_apply<double>(c, p, q, skip, fz);
+  };
+  auto A32 = [&](const cplx<float>* p, cplx<float>* q, const int* skip, const Fuse* fz = nullptr) {
+    elast_apply<float>(c, p, q, skip, fz);
+  };
   return solve_system(c, 3, tumor::PREC_ELAST, 0.0, x, c.b64, c.cfg.rtol_elast, which, A64, A32, r0);
 }
 

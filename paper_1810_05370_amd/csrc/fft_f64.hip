@@ -3,6 +3,7 @@
 
 namespace tumor {
 template void launch_col_pass<double>(int, int, bool, const ColProg&, const void*, hipStream_t);
+template void launch_zinv_pupdate<double>(int, int, const ZPUpdateArgs&, const void*, hipStream_t);
 template void launch_xinv<double>(int, const XProg&, const void*, hipStream_t);
 template void launch_xfwd<double>(int, const XProg&, const void*, hipStream_t, bool);
 template void launch_xelast<double>(int, const XElastArgs&, const void*, hipStream_t);

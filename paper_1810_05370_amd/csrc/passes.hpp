@@ -21,6 +21,7 @@
 //               forward transform, all in registers.
 #pragma once
 #include "fft.hpp"
+#include "kernels.hpp"
 
 namespace tumor {
 
@@ -45,6 +46,24 @@ struct ColProg {
   int nterm[kMaxCol];
   ColTerm term[kMaxCol][kMaxTerms];
   const int* skip;  // if non-null and *skip != 0 the launch does nothing
+  // Optional fused Krylov inner product of a forward z pass: with dsv set,
+  // alpha = rho / sum_o <dotp[o], out[o]> (Parseval-weighted) is published
+  // to dsv by the last block.
+  const void* dotp[kMaxCol];
+  SolveScalars* dsv;
+  double* dpart;
+};
+
+// First (inverse z) pass of a Krylov operator apply with the direction update
+// fused in: p = M^-1 r + beta p (in place), then out[2a] = IFFT_z(p_a) and
+// out[2a+1] = IFFT_z(i w_z p_a) for the NC components.
+struct ZPUpdateArgs {
+  const void* r;
+  void* p;
+  void* out[6];
+  SolveScalars* sv;
+  const CoefScalars* cs;
+  PrecConsts pc;
 };
 
 // Rows of the x pass: generic programs.
@@ -99,6 +118,8 @@ struct PassGeom {
 template <typename R>
 void launch_col_pass(int n, int axis /*1 = y, 2 = z*/, bool inverse, const ColProg& prog,
                      const void* tw, hipStream_t st);
+template <typename R>
+void launch_zinv_pupdate(int n, int ncomp, const ZPUpdateArgs& a, const void* tw, hipStream_t st);
 template <typename R>
 void launch_xinv(int n, const XProg& prog, const void* tw, hipStream_t st);
 template <typename R>

@@ -4,19 +4,35 @@
 #include <string>
 
 #include "passes.hpp"
+#include "prec.hpp"
 
 namespace tumor {
 
 // ----------------------------------------------------------------- geometry
 // Column tiles: TC adjacent kxp columns, TP = N/8 threads per column.
-template <int N>
+template <int N, typename R>
 struct ColCfg {
   static constexpr int TP = N / 8;
   static constexpr int TCW = 256 / TP;
-  static constexpr int TC = (N / 2) < (TCW < 8 ? 8 : TCW) ? (N / 2) : (TCW < 8 ? 8 : TCW);
+  static constexpr int TCMIN = 128 / (2 * (int)sizeof(R));  // 128-byte contiguous segments
+  static constexpr int TC0 = TCW < TCMIN ? TCMIN : TCW;
+  static constexpr int TC = (N / 2) < TC0 ? (N / 2) : TC0;
   static constexpr int THREADS = TC * TP;
   static constexpr int LDS = N * TC + N / 8 + 1;
 };
+
+template <typename R>
+struct ColCfgOf {
+  template <int N>
+  using T = ColCfg<N, R>;
+};
+
+// Copy the twiddle table into LDS (all threads), so butterflies read LDS.
+template <typename R, int N>
+__device__ __forceinline__ void stage_twiddles(cplx<R>* stw, const cplx<R>* __restrict__ tw) {
+  for (int k = threadIdx.x; k < N; k += blockDim.x) stw[k] = tw[k];
+  __syncthreads();
+}
 
 // Row tiles: RW rows of L = N/2 packed complex values, TP = L/8 threads each.
 template <int N>
@@ -34,48 +50,121 @@ __device__ __forceinline__ int xwave(int k) {  // x wave number of packed index 
   return k;                                    // k = 0 carries both kx = 0 and kx = N/2: w = 0
 }
 
+// Block sum of v, then the last block of the grid totals the partials in a
+// fixed order and sets alpha = rho / total (or flags a breakdown).
+__device__ __forceinline__ double wave_sum_f(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ void fused_alpha(double v, SolveScalars* sv, double* part) {
+  __shared__ double sh[16];
+  __shared__ int last;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  const int nb = gridDim.x * gridDim.y;
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  v = wave_sum_f(v);
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w];
+    part[bid] = s;
+    __threadfence();
+    last = (atomicAdd(&sv->counter, 1u) == (unsigned)nb - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const volatile double* vp = part;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) t += vp[b];
+  t = wave_sum_f(t);
+  __syncthreads();
+  if (lane == 0) sh[wv] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w];
+    sv->pq = s;
+    if (!(isfinite(s) && s > 0.0)) {
+      sv->bad = 1;
+      sv->done = 1;
+    } else {
+      sv->alpha = sv->rho / s;
+    }
+    sv->counter = 0u;
+  }
+}
+
 // ---------------------------------------------------------------- col pass
-template <typename R, int N, bool INV>
-__global__ void __launch_bounds__(ColCfg<N>::THREADS)
-    k_col_pass(ColProg prog, long long fstride, long long astride, const cplx<R>* __restrict__ tw) {
+template <typename R, int N, bool INV, bool DOT = false>
+__global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
+    k_col_pass(ColProg prog, long long fstride, long long astride, const cplx<R>* __restrict__ twg) {
   if (prog.skip && *prog.skip) return;
-  using Cfg = ColCfg<N>;
+  using Cfg = ColCfg<N, R>;
   constexpr int TP = Cfg::TP, TC = Cfg::TC;
   __shared__ R sre[Cfg::LDS];
   __shared__ R sim[Cfg::LDS];
+  __shared__ cplx<R> stw[N];
+  stage_twiddles<R, N>(stw, twg);
+  const cplx<R>* tw = stw;
   const int tid = threadIdx.x;
   const int col = tid % TC;
   const int t = tid / TC;
   const long long base = (long long)blockIdx.y * fstride + (long long)blockIdx.x * TC + col;
   const LdsView<R> lds{sre + col, sim + col, TC, 1};
+  double dotacc = 0.0;
+  // Software pipelining: the input column of the next FFT job is loaded into
+  // `nxt` before the current job's FFT, whose barriers wait on LDS only.
+  auto load_col = [&](cplx<R>(&dst)[8], int src) {
+    const cplx<R>* __restrict__ sp = static_cast<const cplx<R>*>(prog.in[src]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dst[j] = sp[base + (long long)(t + TP * j) * astride];
+  };
+  cplx<R> nxt[8];
+  load_col(nxt, prog.term[0][0].src);
   for (int o = 0; o < prog.nout; ++o) {
     cplx<R> acc[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] = czero<R>();
     const int nt = prog.nterm[o];
     if constexpr (INV) {
-      for (int q = 0; q < nt; ++q) {
-        const ColTerm tm = prog.term[o][q];
-        const cplx<R>* __restrict__ src = static_cast<const cplx<R>*>(prog.in[tm.src]);
+      {
+        const ColTerm tm = prog.term[o][0];
         const R cf = R(tm.coef);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          const int n = t + TP * j;
-          cplx<R> v = src[base + (long long)n * astride];
-          if (tm.sym == SYM_IW) v = ciw(v, R(wavenum<N>(n)));
+          cplx<R> v = nxt[j];
+          if (tm.sym == SYM_IW) v = ciw(v, R(wavenum<N>(t + TP * j)));
+          acc[j] = {cf * v.x, cf * v.y};
+        }
+      }
+      for (int q = 1; q < nt; ++q) {
+        const ColTerm tm = prog.term[o][q];
+        const R cf = R(tm.coef);
+        cplx<R> tmp[8];
+        load_col(tmp, tm.src);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          cplx<R> v = tmp[j];
+          if (tm.sym == SYM_IW) v = ciw(v, R(wavenum<N>(t + TP * j)));
           acc[j].x += cf * v.x;
           acc[j].y += cf * v.y;
         }
       }
+      if (o + 1 < prog.nout) load_col(nxt, prog.term[o + 1][0].src);
       fft_block<R, N, true, 1>(acc, lds, t, tw);
     } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = czero<R>();
       for (int q = 0; q < nt; ++q) {
         const ColTerm tm = prog.term[o][q];
-        const cplx<R>* __restrict__ src = static_cast<const cplx<R>*>(prog.in[tm.src]);
         const R cf = R(tm.coef);
         cplx<R> tmp[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) tmp[j] = src[base + (long long)(t + TP * j) * astride];
+        for (int j = 0; j < 8; ++j) tmp[j] = nxt[j];
+        if (q + 1 < nt) load_col(nxt, prog.term[o][q + 1].src);
+        else if (o + 1 < prog.nout) load_col(nxt, prog.term[o + 1][0].src);
         if (tm.sym != SYM_RAW) fft_block<R, N, false, 1>(tmp, lds, t, tw);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -89,6 +178,75 @@ __global__ void __launch_bounds__(ColCfg<N>::THREADS)
     cplx<R>* __restrict__ dst = static_cast<cplx<R>*>(prog.out[o]);
 #pragma unroll
     for (int j = 0; j < 8; ++j) dst[base + (long long)(t + TP * j) * astride] = acc[j];
+    if constexpr (DOT) {
+      const cplx<R>* __restrict__ pp = static_cast<const cplx<R>*>(prog.dotp[o]);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const cplx<R> pv = pp[base + (long long)(t + TP * j) * astride];
+        dotacc += (double)pv.x * (double)acc[j].x + (double)pv.y * (double)acc[j].y;
+      }
+    }
+  }
+  if constexpr (DOT) {
+    // Parseval weight: the packed kx = 0 column counts once, the others twice
+    const int kxp = blockIdx.x * TC + col;
+    dotacc *= (kxp == 0) ? 1.0 : 2.0;
+    fused_alpha(dotacc, prog.dsv, prog.dpart);
+  }
+}
+
+template <typename R, int N, int NC>
+__global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
+    k_zinv_pupdate(ZPUpdateArgs a, const cplx<R>* __restrict__ twg) {
+  if (a.sv->done) return;
+  using Cfg = ColCfg<N, R>;
+  constexpr int TP = Cfg::TP, TC = Cfg::TC;
+  constexpr long long C = N / 2;
+  constexpr long long S = (long long)N * N * C;
+  constexpr long long astride = (long long)N * C;
+  __shared__ R sre[Cfg::LDS];
+  __shared__ R sim[Cfg::LDS];
+  __shared__ cplx<R> stw[N];
+  stage_twiddles<R, N>(stw, twg);
+  const cplx<R>* tw = stw;
+  const int tid = threadIdx.x;
+  const int col = tid % TC;
+  const int t = tid / TC;
+  const int kx = blockIdx.x * TC + col;
+  const int ky = wavenum<N>(blockIdx.y);
+  const long long base = (long long)blockIdx.y * C + kx;
+  const LdsView<R> lds{sre + col, sim + col, TC, 1};
+  const R beta = R(a.sv->beta);
+  const cplx<R>* __restrict__ r = static_cast<const cplx<R>*>(a.r);
+  cplx<R>* __restrict__ p = static_cast<cplx<R>*>(a.p);
+  cplx<R> pn[NC][8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int n = t + TP * j;
+    const long long idx = base + (long long)n * astride;
+    cplx<R> rv[NC], zv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) rv[c] = r[c * S + idx];
+    apply_prec<R, NC>(rv, zv, kx, ky, wavenum<N>(n), a.cs, a.pc);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const cplx<R> pv = p[c * S + idx];
+      pn[c][j] = {zv[c].x + beta * pv.x, zv[c].y + beta * pv.y};
+      p[c * S + idx] = pn[c][j];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      cplx<R> acc[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = d ? ciw(pn[c][j], R(wavenum<N>(t + TP * j))) : pn[c][j];
+      fft_block<R, N, true, 1>(acc, lds, t, tw);
+      cplx<R>* __restrict__ dst = static_cast<cplx<R>*>(a.out[2 * c + d]);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dst[base + (long long)(t + TP * j) * astride] = acc[j];
+    }
   }
 }
 
@@ -205,6 +363,9 @@ __device__ __forceinline__ cplx<R> iwx(cplx<R> a, int k) {
   constexpr int L = RC::L, TP = RC::TP;                              \
   __shared__ R sre[RC::RW * RC::LP];                                 \
   __shared__ R sim[RC::RW * RC::LP];                                 \
+  __shared__ cplx<R> stw[N];                                         \
+  stage_twiddles<R, N>(stw, twg);                                    \
+  const cplx<R>* tw = stw;                                           \
   const int t = threadIdx.x % TP;                                    \
   const int rl = threadIdx.x / TP;                                   \
   const long long row = (long long)blockIdx.x * RC::RW + rl;         \
@@ -216,7 +377,7 @@ __device__ __forceinline__ cplx<R> iwx(cplx<R> a, int k) {
 
 // ------------------------------------------------------------- x kernels
 template <typename R, int N>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xinv(XProg prog, const cplx<R>* __restrict__ tw) {
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xinv(XProg prog, const cplx<R>* __restrict__ twg) {
   if (prog.skip && *prog.skip) return;
   TUMOR_ROW_SETUP(N)
   const R scale = R(prog.scale);
@@ -230,7 +391,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xinv(XProg prog, const c
 }
 
 template <typename R, int N, typename RIN>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xfwd(XProg prog, const cplx<R>* __restrict__ tw) {
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xfwd(XProg prog, const cplx<R>* __restrict__ twg) {
   if (prog.skip && *prog.skip) return;
   TUMOR_ROW_SETUP(N)
   for (int o = 0; o < prog.nout; ++o) {
@@ -255,7 +416,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xfwd(XProg prog, const c
 }
 
 template <typename R, int N>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xelast(XElastArgs a, const cplx<R>* __restrict__ tw) {
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xelast(XElastArgs a, const cplx<R>* __restrict__ twg) {
   if (a.skip && *a.skip) return;
   TUMOR_ROW_SETUP(N)
   const R invV = R(1.0) / (R(N) * R(N) * R(N));
@@ -334,7 +495,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xelast(XElastArgs a, con
 }
 
 template <typename R, int N>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdiff(XDiffArgs a, const cplx<R>* __restrict__ tw) {
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdiff(XDiffArgs a, const cplx<R>* __restrict__ twg) {
   if (a.skip && *a.skip) return;
   TUMOR_ROW_SETUP(N)
   const R invV = R(1.0) / (R(N) * R(N) * R(N));
@@ -365,7 +526,7 @@ template <>
 __device__ __forceinline__ float rtanh<float>(float x) { return tanhf(x); }
 
 template <typename R, int N>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xforce(XForceArgs a, const cplx<R>* __restrict__ tw) {
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xforce(XForceArgs a, const cplx<R>* __restrict__ twg) {
   TUMOR_ROW_SETUP(N)
   const R invV = R(1.0) / (R(N) * R(N) * R(N));
   const cplx<R>* T = static_cast<const cplx<R>*>(a.in[0]) + soff;
@@ -405,13 +566,28 @@ void launch_col_pass(int n, int axis, bool inverse, const ColProg& prog, const v
   const long long astride = axis == 1 ? C : (long long)n * C;
   const cplx<R>* twp = static_cast<const cplx<R>*>(tw);
   TUMOR_DISPATCH_N(n, {
-    dim3 grid(C / ColCfg<NN>::TC, NN);
+    using Cfg = typename ColCfgOf<R>::template T<NN>;
+    dim3 grid(C / Cfg::TC, NN);
     if (inverse)
-      hipLaunchKernelGGL((k_col_pass<R, NN, true>), grid, dim3(ColCfg<NN>::THREADS), 0, st, prog, fstride,
-                         astride, twp);
+      hipLaunchKernelGGL((k_col_pass<R, NN, true>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride, astride, twp);
+    else if (prog.dsv)
+      hipLaunchKernelGGL((k_col_pass<R, NN, false, true>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride, astride,
+                         twp);
     else
-      hipLaunchKernelGGL((k_col_pass<R, NN, false>), grid, dim3(ColCfg<NN>::THREADS), 0, st, prog, fstride,
-                         astride, twp);
+      hipLaunchKernelGGL((k_col_pass<R, NN, false>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride, astride, twp);
+  });
+}
+
+template <typename R>
+void launch_zinv_pupdate(int n, int ncomp, const ZPUpdateArgs& a, const void* tw, hipStream_t st) {
+  const cplx<R>* twp = static_cast<const cplx<R>*>(tw);
+  TUMOR_DISPATCH_N(n, {
+    using Cfg = typename ColCfgOf<R>::template T<NN>;
+    dim3 grid((NN / 2) / Cfg::TC, NN);
+    if (ncomp == 1)
+      hipLaunchKernelGGL((k_zinv_pupdate<R, NN, 1>), grid, dim3(Cfg::THREADS), 0, st, a, twp);
+    else
+      hipLaunchKernelGGL((k_zinv_pupdate<R, NN, 3>), grid, dim3(Cfg::THREADS), 0, st, a, twp);
   });
 }
 
