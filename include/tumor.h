@@ -164,6 +164,14 @@ int tumor_step(tumor_ctx* ctx, int32_t nsteps, tumor_step_stats* last);
 int tumor_solve_elasticity(tumor_ctx* ctx, const double* force, double* u_out,
                            int32_t* iters, double* relres);
 
+/* Run the transport sub-step alone on the current state (Sec. 3, first two
+ * items of the multispecies splitting): velocity u_t^n = (u^n - u^{n-1}) / dt
+ * and the semi-Lagrangian step of p, i, n, g, w (conservative form) and f,
+ * exactly as tumor_step does it.  out: device, 6 N^3 values, the transported
+ * p, i, n, g, w, f in that order.  max_cfl: host, nullable, receives
+ * max |dt u_t^n| / h.  The state is unchanged. */
+int tumor_transport(tumor_ctx* ctx, double* out, double* max_cfl);
+
 /* Discrete adjoint (the exact transpose of the linearised split step, every
  * PCG solve taken as exact; the paper leaves adjoint-based inversion to
  * future work, Sec. 5).  Requires a context created with TUMOR_F_ADJOINT.
@@ -232,7 +240,10 @@ int tumor_force_iterations(tumor_ctx* ctx, const int32_t* iters);
 enum {
   TUMOR_K_COLINV64 = 0, TUMOR_K_COLFWD64, TUMOR_K_COLINV32, TUMOR_K_COLFWD32, TUMOR_K_XELAST64,
   TUMOR_K_XELAST32, TUMOR_K_XDIFF64, TUMOR_K_XDIFF32, TUMOR_K_XOTHER, TUMOR_K_SL, TUMOR_K_REACT,
-  TUMOR_K_KRYLOV64, TUMOR_K_KRYLOV32, TUMOR_K_COUNT
+  TUMOR_K_KRYLOV64, TUMOR_K_KRYLOV32,
+  TUMOR_K_ZINVP64, TUMOR_K_ZINVP32,      /* first pass with the fused direction update  */
+  TUMOR_K_COLDOT64, TUMOR_K_COLDOT32,    /* last pass with the fused inner product      */
+  TUMOR_K_COUNT
 };
 int tumor_kernel_timer(tumor_ctx* ctx, int32_t kernel_class, int32_t enable);
 int tumor_kernel_timer_read(tumor_ctx* ctx, int32_t kernel_class, int64_t* launches, double* ms,

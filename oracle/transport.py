@@ -53,28 +53,44 @@ def grid_indices(n):
     return jx, jy, jz
 
 
-def departure_points(grid, v, dt):
-    """RK2 departure points X (grid-index units) for velocity v = (vx, vy, vz)."""
-    jx, jy, jz = grid_indices(grid.n)
+def _at(field, nodes):
+    """Values of a grid field at integer grid nodes (all nodes when nodes is None)."""
+    if nodes is None:
+        return field
+    jx, jy, jz = nodes
+    return field[jz.astype(np.int64), jy.astype(np.int64), jx.astype(np.int64)]
+
+
+def departure_points(grid, v, dt, nodes=None):
+    """RK2 departure points X (grid-index units) for velocity v = (vx, vy, vz).
+
+    nodes: optional (jx, jy, jz) integer grid-index arrays; the points are
+    then computed for those arrival nodes only (same arithmetic)."""
+    jx, jy, jz = grid_indices(grid.n) if nodes is None else nodes
     s = dt / grid.h
-    xs = (jx - s * v[0], jy - s * v[1], jz - s * v[2])
+    v0 = [_at(v[a], nodes) for a in range(3)]
+    xs = (jx - s * v0[0], jy - s * v0[1], jz - s * v0[2])
     vs = [interp(v[a], *xs) for a in range(3)]
-    return (jx - 0.5 * s * (v[0] + vs[0]),
-            jy - 0.5 * s * (v[1] + vs[1]),
-            jz - 0.5 * s * (v[2] + vs[2]))
+    return (jx - 0.5 * s * (v0[0] + vs[0]),
+            jy - 0.5 * s * (v0[1] + vs[1]),
+            jz - 0.5 * s * (v0[2] + vs[2]))
 
 
-def advect(grid, fields, v, dt):
-    """One SL step: conservative transport of p, i, n, g, w; plain transport of f."""
+def advect(grid, fields, v, dt, nodes=None):
+    """One SL step: conservative transport of p, i, n, g, w; plain transport of f.
+
+    nodes: optional (jx, jy, jz) integer grid-index arrays; the step is then
+    evaluated at those arrival nodes only (same arithmetic as the whole grid)."""
     delta = grid.div(v)
-    X = departure_points(grid, v, dt)
+    X = departure_points(grid, v, dt, nodes)
     delta_X = interp(delta, *X)
+    delta_here = _at(delta, nodes)
     out = {}
     for name in ("p", "i", "n", "g", "w"):
         q_X = interp(fields[name], *X)
         g0 = -q_X * delta_X
         q_star = q_X + dt * g0
-        g_star = -q_star * delta
+        g_star = -q_star * delta_here
         out[name] = q_X + 0.5 * dt * (g0 + g_star)
     out["f"] = interp(fields["f"], *X)
     return out

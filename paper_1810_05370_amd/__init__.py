@@ -38,10 +38,14 @@ OPS = {"deriv_x": 0, "deriv_y": 1, "deriv_z": 2, "diffusion": 3, "elasticity": 4
        "elast_precond": 5, "cn_precond": 6, "force": 7}
 VECTOR_OPS = ("elasticity", "elast_precond", "force")
 KERNEL_CLASSES = {"colinv64": 0, "colfwd64": 1, "colinv32": 2, "colfwd32": 3, "xelast64": 4, "xelast32": 5,
-                  "xdiff64": 6, "xdiff32": 7, "xother": 8, "sl": 9, "react": 10, "krylov64": 11, "krylov32": 12}
+                  "xdiff64": 6, "xdiff32": 7, "xother": 8, "sl": 9, "react": 10, "krylov64": 11, "krylov32": 12,
+                  "zinvp64": 13, "zinvp32": 14, "coldot64": 15, "coldot32": 16}
 # rocprofv3 kernel names of each class (for cross-checking event timings against traces)
-KERNEL_NAMES = {"colinv64": "k_col_pass<double, {n}, true>", "colfwd64": "k_col_pass<double, {n}, false>",
-                "colinv32": "k_col_pass<float, {n}, true>", "colfwd32": "k_col_pass<float, {n}, false>",
+KERNEL_NAMES = {"colinv64": "k_col_pass<double, {n}, true, false>",
+                "colfwd64": "k_col_pass<double, {n}, false, false>",
+                "colinv32": "k_col_pass<float, {n}, true, false>", "colfwd32": "k_col_pass<float, {n}, false, false>",
+                "coldot64": "k_col_pass<double, {n}, false, true>", "coldot32": "k_col_pass<float, {n}, false, true>",
+                "zinvp64": "k_zinv_pupdate<double, {n}, 1|3>", "zinvp32": "k_zinv_pupdate<float, {n}, 1|3>",
                 "xelast64": "k_xelast<double, {n}>", "xelast32": "k_xelast<float, {n}>",
                 "xdiff64": "k_xdiff<double, {n}>", "xdiff32": "k_xdiff<float, {n}>", "sl": "k_sl",
                 "react": "k_react"}
@@ -99,6 +103,7 @@ def load_library(path: Optional[str] = None):
         "tumor_step": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(TumorStepStats)]),
         "tumor_solve_elasticity": (ctypes.c_int, [P, P, P, ctypes.POINTER(ctypes.c_int32),
                                                   ctypes.POINTER(ctypes.c_double)]),
+        "tumor_transport": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_double)]),
         "tumor_adjoint_step": (ctypes.c_int, [P, P, P]),
         "tumor_tape_bytes": (ctypes.c_int, [ctypes.POINTER(TumorConfig), ctypes.c_int32, ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_size_t)]),
@@ -242,6 +247,16 @@ class Tumor:
         _check(self.lib.tumor_solve_elasticity(self.ctx, _ptr(force) if force is not None else None,
                                                _ptr(u), ctypes.byref(it), ctypes.byref(rr)))
         return u, it.value, rr.value
+
+    def transport(self):
+        """The transport sub-step alone: (6, N, N, N) tensor of the transported
+        p, i, n, g, w, f, and max |dt v| / h.  The state is unchanged."""
+        torch = self._torch
+        n = self.n
+        out = torch.empty((6, n, n, n), dtype=torch.float64, device=self.device)
+        cfl = ctypes.c_double(0)
+        _check(self.lib.tumor_transport(self.ctx, _ptr(out), ctypes.byref(cfl)))
+        return out, cfl.value
 
     def get(self, name):
         torch = self._torch

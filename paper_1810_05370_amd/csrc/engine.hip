@@ -213,8 +213,11 @@ void layout(Ctx& c, Carver& cv) {
   c.eta = cv.take<double>(V);
   for (int k = 0; k < 4; ++k) c.vel[k] = cv.take<double>(V);
   c.b64 = cv.take<cplx<double>>(3 * S);
-  for (int k = 0; k < 8; ++k) c.p64.A[k] = cv.take<cplx<double>>(S);
-  for (int k = 0; k < 8; ++k) c.p64.B[k] = cv.take<cplx<double>>(S);
+  // The 16 FP64 pass buffers are one contiguous block: during transport it
+  // holds the node-interleaved gather copies (12 V values, see launch_sl).
+  cplx<double>* ab = cv.take<cplx<double>>(16 * S);
+  for (int k = 0; k < 8; ++k) c.p64.A[k] = ab + k * S;
+  for (int k = 0; k < 8; ++k) c.p64.B[k] = ab + (8 + k) * S;
   c.p64.x = nullptr;  // the elasticity solve iterates directly in Un
   c.p64.r = cv.take<cplx<double>>(3 * S);
   c.p64.p = cv.take<cplx<double>>(3 * S);
@@ -349,7 +352,9 @@ void colp(Ctx& c, int axis, bool inv, const Prog& pr) {
   if (pr.p.dsv)
     for (int o = 0; o < pr.p.nout; ++o) ndot += pr.p.dotp[o] ? 1 : 0;
   const double bytes = double(nin + pr.p.nout + ndot) * double(c.V) * sizeof(R);
-  timed(c, inv ? kcls<R>(TUMOR_K_COLINV64, TUMOR_K_COLINV32) : kcls<R>(TUMOR_K_COLFWD64, TUMOR_K_COLFWD32), bytes,
+  const int cls = inv ? kcls<R>(TUMOR_K_COLINV64, TUMOR_K_COLINV32)
+                      : (pr.p.dsv ? kcls<R>(TUMOR_K_COLDOT64, TUMOR_K_COLDOT32) : kcls<R>(TUMOR_K_COLFWD64, TUMOR_K_COLFWD32));
+  timed(c, cls, bytes,
         [&] { tumor::launch_col_pass<R>(c.n, axis, inv, pr.p, pb<R>(c).tw, c.st); });
 }
 
@@ -391,7 +396,7 @@ void zinv_pupdate(Ctx& c, int ncomp, const Fuse& f, cplx<R>* p, void* const* out
   za.sv = f.sv;
   za.cs = c.cs;
   za.pc = f.pc;
-  timed(c, kcls<R>(TUMOR_K_COLINV64, TUMOR_K_COLINV32), 5.0 * ncomp * double(c.V) * sizeof(R),
+  timed(c, kcls<R>(TUMOR_K_ZINVP64, TUMOR_K_ZINVP32), 5.0 * ncomp * double(c.V) * sizeof(R),
         [&] { tumor::launch_zinv_pupdate<R>(c.n, ncomp, za, pb<R>(c).tw, c.st); });
 }
 
@@ -597,6 +602,7 @@ tumor::KrylovArgs kargs(Ctx& c, int ncomp, cplx<R>* x, tumor::SolveScalars* sv, 
   a.ncomp = ncomp;
   a.pc.h = h;
   a.pc.kind = kind;
+  a.scale32 = 1.0;
   a.pc.singular = (kind == tumor::PREC_ELAST && c.prm.eta_tumor == 0.0 && c.prm.eta_healthy == 0.0) ? 1 : 0;
   return a;
 }
@@ -691,6 +697,13 @@ SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cp
   const int max_outer = 30;
   int total = 0;
   while (so.outer < max_outer) {
+    // The FP32 copy of the residual is scaled by a power of two that brings its
+    // root-mean-square value near 1 (exact, and invisible to PCG's ratios), so
+    // that a residual below FP32's range still yields a correction; the
+    // correction is unscaled when it is added to x.
+    const double rms = std::sqrt(rr / double(cnt));
+    const double sc = (rms > 0.0 && std::isfinite(rms)) ? std::ldexp(1.0, -std::ilogb(rms)) : 1.0;
+    conv_args.scale32 = sc;
     timed(c, TUMOR_K_KRYLOV64, ncomp * c.V * (16.0 + 4.0), [&] { tumor::launch_residual<double>(conv_args, P.r, c.st); });
     const double need = rtol * std::sqrt(bb / rr);
     const double in_rtol = std::max(1e-4, 0.3 * need);
@@ -699,7 +712,7 @@ SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cp
     // inner solve with x32 = 0, r32 from above; threshold relative to ||r32||
     tumor::KrylovArgs ai = a32;
     ai.x = P.x;
-    const double thr_in = in_rtol * in_rtol * rr;
+    const double thr_in = in_rtol * in_rtol * rr * sc * sc;
     inner_it = pcg_iterate<float>(c, ai, A32, thr_in, c.cfg.max_it, false,
                                   std::max(1, c.pred[which >= 0 ? which : 3] / 2), 1, conv, bad);
     total += inner_it;
@@ -709,7 +722,7 @@ SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cp
       so.conv = false;
       break;
     }
-    tumor::launch_add32to64(x, P.x, cnt, c.st);
+    tumor::launch_add32to64(x, P.x, 1.0 / sc, cnt, c.st);
     // r64 = b - A64 x64
     A64(x, c.p64.q, nullptr);
     tumor::KrylovArgs ar = a;
@@ -885,37 +898,49 @@ void twiddles(Ctx& c) {
   HIPCHECK(hipStreamSynchronize(c.st));
 }
 
+// S1 (Sec. 3): velocity u_t^n = (u^n - u^{n-1}) / dt and its divergence,
+// then the semi-Lagrangian step of p, i, n, g, w, f into outs[0..5] (in that
+// order).  max |dt v| / h lands in cs->cfl_bits.
+void transport(Ctx& c, double* const (&outs)[6]) {
+  enum { P, I, N, O, L, G, W, F };
+  velocity(c);
+  tumor::SLArgs s;
+  s.vx = c.vel[0];
+  s.vy = c.vel[1];
+  s.vz = c.vel[2];
+  s.div = c.vel[3];
+  s.p = c.F[P];
+  s.i = c.F[I];
+  s.n = c.F[N];
+  s.g = c.F[G];
+  s.w = c.F[W];
+  s.f = c.F[F];
+  s.po = outs[0];
+  s.io = outs[1];
+  s.no = outs[2];
+  s.go = outs[3];
+  s.wo = outs[4];
+  s.fo = outs[5];
+  s.n_grid = c.n;
+  s.dt = c.cfg.dt;
+  s.s = c.cfg.dt / (2.0 * M_PI / c.n);
+  // FP32: scan 6 + pack 10 FP64 reads, 12 FP32 writes; gather 4 FP64 + 12 FP32
+  // reads, 6 FP64 writes.  FP64: CFL 3 reads; gather 10 reads, 6 writes.
+  HIPCHECK(hipMemsetAsync(&c.cs->cfl_bits, 0, 7 * sizeof(unsigned long long), c.st));  // cfl + qmax[6]
+  timed(c, TUMOR_K_SL, (c.mixed ? 26.0 * 8.0 + 24.0 * 4.0 : 19.0 * 8.0) * c.V, [&] {
+    if (c.mixed) tumor::launch_sl<float>(s, c.p64.A[0], c.cs, c.st);
+    else tumor::launch_sl<double>(s, c.p64.A[0], c.cs, c.st);
+  });
+}
+
 void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
   enum { P, I, N, O, L, G, W, F };
   const int n = c.n;
   (void)n;
   // S1: transport with u_t^n = (u^n - u^{n-1}) / dt
   if (c.flags & TUMOR_F_ADVECTION) {
-    velocity(c);
-    tumor::SLArgs s;
-    s.vx = c.vel[0];
-    s.vy = c.vel[1];
-    s.vz = c.vel[2];
-    s.div = c.vel[3];
-    s.p = c.F[P];
-    s.i = c.F[I];
-    s.n = c.F[N];
-    s.g = c.F[G];
-    s.w = c.F[W];
-    s.f = c.F[F];
-    s.po = c.G[P];
-    s.io = c.G[I];
-    s.no = c.G[N];
-    s.go = c.G[G];
-    s.wo = c.G[W];
-    s.fo = c.G[F];
-    s.n_grid = c.n;
-    s.dt = c.cfg.dt;
-    s.s = c.cfg.dt / (2.0 * M_PI / c.n);
-    timed(c, TUMOR_K_SL, 16.0 * c.V * 8.0, [&] {
-      if (c.mixed) tumor::launch_sl<float>(s, c.st);
-      else tumor::launch_sl<double>(s, c.st);
-    });
+    double* const outs[6] = {c.G[P], c.G[I], c.G[N], c.G[G], c.G[W], c.G[F]};
+    transport(c, outs);
   } else {
     const int ids[6] = {P, I, N, G, W, F};
     for (int k : ids)
@@ -968,7 +993,12 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
     stats->outer_elast = se.outer;
     stats->relres_elast = se.relres;
     for (int k = 0; k < 8; ++k) stats->mass[k] = c.hcs->mass[k] * h * h * h;
-    stats->max_cfl = -1.0;
+    if (c.flags & TUMOR_F_ADVECTION) {
+      const unsigned long long bits = c.hcs->cfl_bits;
+      std::memcpy(&stats->max_cfl, &bits, sizeof(double));
+    } else {
+      stats->max_cfl = 0.0;
+    }
   }
   if (any_bad) {
     status = TUMOR_ENAN;
@@ -1499,6 +1529,24 @@ int tumor_solve_elasticity(tumor_ctx* ctx, const double* force, double* u_out, i
     if (!so.conv) {
       g_err = "elasticity PCG reached max_it";
       return TUMOR_ENOCONV;
+    }
+    return TUMOR_OK;
+  });
+}
+
+int tumor_transport(tumor_ctx* ctx, double* out, double* max_cfl) {
+  if (!ctx) return einval("ctx is NULL");
+  if (!out) return einval("out is NULL");
+  return guarded([&]() -> int {
+    Ctx& c = *ctx;
+    double* const outs[6] = {out, out + c.V, out + 2 * c.V, out + 3 * c.V, out + 4 * c.V, out + 5 * c.V};
+    transport(c, outs);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(c.hcs, c.cs, sizeof(tumor::CoefScalars), hipMemcpyDeviceToHost, c.st));
+    HIPCHECK(hipStreamSynchronize(c.st));
+    if (max_cfl) {
+      const unsigned long long bits = c.hcs->cfl_bits;
+      std::memcpy(max_cfl, &bits, sizeof(double));
     }
     return TUMOR_OK;
   });

@@ -36,6 +36,10 @@ struct CoefScalars {
   uint32_t counter;
   int32_t bad;
   int32_t pad[2];
+  // Written by the transport (reset before it): bits of non-negative doubles,
+  // which order like unsigned integers, so blocks combine them by atomic max.
+  unsigned long long cfl_bits;      // max |dt v| / h
+  unsigned long long qmax_bits[6];  // max |q| of p, i, n, g, w, f (mixed precision only)
 };
 
 // Constants of the coefficient refresh (Eqs. e:diffusion_tensor,
@@ -86,8 +90,11 @@ struct SLArgs {
   int n_grid;
   double dt, s;  // s = dt / h
 };
+// Packs the gathered fields into `packed` (12 V values of RC: v4 then q8),
+// then runs the step.  cs->cfl_bits and cs->qmax_bits must be zero on entry;
+// max |dt v| / h is max-combined into cfl_bits.
 template <typename RC>
-void launch_sl(const SLArgs& a, hipStream_t st);
+void launch_sl(const SLArgs& a, void* packed, CoefScalars* cs, hipStream_t st);
 
 // Tricubic Lagrange interpolation at arbitrary grid-index points.
 void launch_interp(int n, const double* q, const double* jx, const double* jy, const double* jz,
@@ -113,6 +120,7 @@ struct KrylovArgs {
   double thr2;   // convergence threshold on ||r||^2
   int limit;     // iteration limit (max_it or a forced count)
   int fixed;     // 1: ignore convergence, stop at `limit`
+  double scale32;  // launch_residual: r32 = float(scale32 * r), a power of two
 };
 
 // r = b - ax (ax nullable: r = b); bb, rr -> sv.  Optionally r32 = float(r).
@@ -137,7 +145,8 @@ void launch_pcg_pupdate(const KrylovArgs& a, hipStream_t st);
 template <typename R>
 void launch_precond(const KrylovArgs& a, const void* in, void* out, hipStream_t st);
 // x64 += x32 over ncomp blocks
-void launch_add32to64(void* x64, const void* x32, long long count, hipStream_t st);
+// x64 += s * double(x32)
+void launch_add32to64(void* x64, const void* x32, double s, long long count, hipStream_t st);
 // physical float -> double
 void launch_f32_to_f64(const float* in, double* out, long long count, hipStream_t st);
 void launch_scale64(double* x, double s, long long count, hipStream_t st);

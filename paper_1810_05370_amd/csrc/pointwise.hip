@@ -5,6 +5,7 @@
 // partials in a fixed order and publishes the result to device scalars that
 // later kernels and the host read.  The grid size of a reduction kernel is a
 // fixed function of the problem size, so results do not depend on timing.
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -240,48 +241,231 @@ __device__ __forceinline__ void interp_pt(const double* const (&q)[NF], double j
   }
 }
 
+// Power-of-two scale 2^-e that brings max |q| = m to [1, 2) (1 for m = 0 or
+// a non-finite m).  Multiplying by it is exact, so a field can be rounded to
+// FP32 after scaling without leaving FP32's normal range, and unscaled in FP64.
+__device__ __forceinline__ double pow2_scale(unsigned long long bits) {
+  const double m = __longlong_as_double((long long)bits);
+  return (m > 0.0 && m < INFINITY) ? ldexp(1.0, -ilogb(m)) : 1.0;
+}
+
+// max |q| of the six transported fields (mixed precision): block maxima,
+// combined by atomic max on the bits of the non-negative doubles.
+__global__ void __launch_bounds__(256) k_sl_scan(SLArgs a, CoefScalars* cs) {
+  const double* const q[6] = {a.p, a.i, a.n, a.g, a.w, a.f};
+  const long long V = (long long)a.n_grid * a.n_grid * a.n_grid;
+  double m[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < V; v += (long long)gridDim.x * 256) {
+#pragma unroll
+    for (int f = 0; f < 6; ++f) m[f] = fmax(m[f], fabs(q[f][v]));
+  }
+  __shared__ double sh[6][4];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    double t = m[f];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t = fmax(t, __shfl_xor(t, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[f][threadIdx.x >> 6] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int f = threadIdx.x;
+    const double t = fmax(fmax(sh[f][0], sh[f][1]), fmax(sh[f][2], sh[f][3]));
+    atomicMax(&cs->qmax_bits[f], (unsigned long long)__double_as_longlong(t));
+  }
+}
+
+// max over a 256-thread block of c, combined into cs->cfl_bits.
+__device__ __forceinline__ void block_max_cfl(double c, CoefScalars* cs) {
+  if (!(c >= 0.0)) c = INFINITY;  // a NaN velocity reports an infinite CFL number
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c = fmax(c, __shfl_xor(c, off, 64));
+  __shared__ double sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    atomicMax(&cs->cfl_bits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// Node-interleaved copies of the gathered fields (the interpolation type RC):
+//   v4[node] = (v_x, v_y, v_z, 0)                       gathered at X*
+//   q8[node] = (s_p p, s_i i, s_n n, s_g g, s_w w, s_f f, div v, 0)   at X
+// with s_q the power-of-two scale of max |q| (used for FP32 only).
+// Scaling by a power of two and rounding commute, and the interpolation and
+// the Heun update are linear in q, so the packed copies change no result
+// while FP32 values stay in range; fields far below it (the necrotic cells
+// early on, say) keep FP32's relative precision instead of flushing to zero.
+// The copies turn the ten separate gathers of every stencil node into one
+// (v4) and one (q8) contiguous load.  The same pass publishes
+// max |dt v| / h with one atomic max per block.
 template <typename RC>
-__global__ void __launch_bounds__(256) k_sl(SLArgs a) {
+__global__ void __launch_bounds__(256) k_sl_pack(SLArgs a, RC* __restrict__ v4, RC* __restrict__ q8,
+                                                 CoefScalars* cs) {
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;  // the grid covers V exactly
+  const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v];
+  RC* o = v4 + 4 * v;
+  o[0] = RC(vx);
+  o[1] = RC(vy);
+  o[2] = RC(vz);
+  o[3] = RC(0);
+  const double* const src[6] = {a.p, a.i, a.n, a.g, a.w, a.f};
+  RC* q = q8 + 8 * v;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const double sc = sizeof(RC) == sizeof(double) ? 1.0 : pow2_scale(cs->qmax_bits[f]);
+    q[f] = RC(sc * src[f][v]);
+  }
+  q[6] = RC(a.div[v]);
+  q[7] = RC(0);
+  block_max_cfl(a.s * sqrt(vx * vx + vy * vy + vz * vz), cs);
+}
+
+// FP64 transport: only the CFL number (the gather reads the fields in place).
+__global__ void __launch_bounds__(256) k_sl_cfl(SLArgs a, CoefScalars* cs) {
+  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;  // the grid covers V exactly
+  const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v];
+  block_max_cfl(a.s * sqrt(vx * vx + vy * vy + vz * vz), cs);
+}
+
+// W consecutive RC values of one stencil node (16-byte vector loads; q is
+// 16-byte aligned because W * sizeof(RC) is a multiple of 16).
+template <typename RC, int W>
+__device__ __forceinline__ void load_node(const RC* __restrict__ q, RC (&o)[W]) {
+  typedef RC vec2 __attribute__((ext_vector_type(16 / sizeof(RC))));
+  constexpr int L = 16 / sizeof(RC);
+#pragma unroll
+  for (int k = 0; k < W / L; ++k) {
+    const vec2 t = reinterpret_cast<const vec2*>(q)[k];
+#pragma unroll
+    for (int e = 0; e < L; ++e) o[k * L + e] = t[e];
+  }
+}
+
+// Tricubic Lagrange interpolation of a node-interleaved field group at one
+// point (grid-index coordinates in FP64; weights and sums in RC).  The
+// arithmetic and its order are those of interp_pt.
+template <typename RC, int W, int NF>
+__device__ __forceinline__ void interp_packed(const RC* __restrict__ q, double jx, double jy, double jz, int n,
+                                              RC (&out)[NF]) {
+  const double bx = floor(jx), by = floor(jy), bz = floor(jz);
+  RC wx[4], wy[4], wz[4];
+  lagrange4<RC>(RC(jx - bx), wx);
+  lagrange4<RC>(RC(jy - by), wy);
+  lagrange4<RC>(RC(jz - bz), wz);
+  const int ix = (int)(long long)bx, iy = (int)(long long)by, iz = (int)(long long)bz;
+  const int m = n - 1;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) out[f] = RC(0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const long long zo = (long long)((iz + c - 1) & m) * n * n;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const long long yo = zo + (long long)((iy + b - 1) & m) * n;
+      const RC wzy = wz[c] * wy[b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const long long idx = yo + ((ix + a - 1) & m);
+        const RC wt = wzy * wx[a];
+        RC val[W];
+        load_node<RC, W>(q + W * idx, val);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) out[f] += wt * val[f];
+      }
+    }
+  }
+}
+
+// Semi-Lagrangian step of the transported fields (Sec. 3): RK2
+// characteristics X* = x - dt v(x), X = x - dt/2 (v(x) + v(X*)), tricubic
+// values at X, and Heun's method for the conservative source
+// g(nu, x) = -nu div v(x) of p, i, n, g, w; f is transported without source.
+//
+// One block per 16 x 4 x 4 brick of voxels (x fastest).  Blocks are handed
+// to the eight XCDs in turn, so block b is mapped to brick
+// (b mod 8) * (bricks / 8) + b / 8: each XCD sweeps one contiguous z slab,
+// and consecutive bricks of a slab form 256 x 16 x 16 groups (x, then 4
+// bricks in z, then y), so that the stencils of the bricks an XCD runs at
+// once overlap in its L2.
+template <typename RC>
+__global__ void __launch_bounds__(256) k_sl_gather(SLArgs a, const RC* __restrict__ v4, const RC* __restrict__ q8,
+                                                   const CoefScalars* cs) {
   const int n = a.n_grid;
-  const long long V = (long long)n * n * n;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= V) return;
-  const int jx = (int)(v % n), jy = (int)((v / n) % n), jz = (int)(v / ((long long)n * n));
+  const unsigned nb = gridDim.x;
+  const unsigned id = (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3);
+  const unsigned nbx = (unsigned)n >> 4, nby = (unsigned)n >> 2;
+  const unsigned bx = id % nbx;
+  unsigned r = id / nbx;
+  const unsigned zl = r & 3u;
+  r >>= 2;
+  const unsigned by = r % nby, zg = r / nby;
+  const int t = threadIdx.x;
+  const int jx = (int)(bx * 16) + (t & 15);
+  const int jy = (int)(by * 4) + ((t >> 4) & 3);
+  const int jz = (int)((zg * 4 + zl) * 4) + (t >> 6);
+  const long long v = ((long long)jz * n + jy) * n + jx;
   const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v];
   const double s = a.s;
-  // RK2 characteristics (Sec. 3): X* = x - dt v(x), X = x - dt/2 (v(x) + v(X*)).
-  const double* const vel[3] = {a.vx, a.vy, a.vz};
   RC vs[3];
-  interp_pt<RC, 3>(vel, jx - s * vx, jy - s * vy, jz - s * vz, n, vs);
+  RC qx[7];
+  if constexpr (sizeof(RC) == sizeof(double)) {
+    // FP64: the fields are gathered where they are (a packed copy would only
+    // add its padding to the bytes every stencil node moves).
+    const double* const vel[3] = {a.vx, a.vy, a.vz};
+    interp_pt<RC, 3>(vel, jx - s * vx, jy - s * vy, jz - s * vz, n, vs);
+  } else {
+    interp_packed<RC, 4, 3>(v4, jx - s * vx, jy - s * vy, jz - s * vz, n, vs);
+  }
   const double Xx = jx - 0.5 * s * (vx + (double)vs[0]);
   const double Xy = jy - 0.5 * s * (vy + (double)vs[1]);
   const double Xz = jz - 0.5 * s * (vz + (double)vs[2]);
-  const double* const fl[7] = {a.p, a.i, a.n, a.g, a.w, a.f, a.div};
-  RC qx[7];
-  interp_pt<RC, 7>(fl, Xx, Xy, Xz, n, qx);
-  // Heun with g(nu, x) = -nu div v(x).
+  if constexpr (sizeof(RC) == sizeof(double)) {
+    const double* const fl[7] = {a.p, a.i, a.n, a.g, a.w, a.f, a.div};
+    interp_pt<RC, 7>(fl, Xx, Xy, Xz, n, qx);
+  } else {
+    interp_packed<RC, 8, 7>(q8, Xx, Xy, Xz, n, qx);
+  }
   const RC dt = RC(a.dt);
   const RC dX = qx[6];
   const RC d0 = RC(a.div[v]);
-  double* const outs[5] = {a.po, a.io, a.no, a.go, a.wo};
+  double* const outs[6] = {a.po, a.io, a.no, a.go, a.wo, a.fo};
+  double unscale[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    unscale[k] = sizeof(RC) == sizeof(double) ? 1.0 : 1.0 / pow2_scale(cs->qmax_bits[k]);
+  // Heun is linear in q: it runs on the scaled values, unscaled in FP64.
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     const RC qt = qx[k];
     const RC g0 = -qt * dX;
     const RC qs = qt + dt * g0;
     const RC gs = -qs * d0;
-    outs[k][v] = (double)(qt + RC(0.5) * dt * (g0 + gs));
+    outs[k][v] = (double)(qt + RC(0.5) * dt * (g0 + gs)) * unscale[k];
   }
-  a.fo[v] = (double)qx[5];
+  outs[5][v] = (double)qx[5] * unscale[5];
 }
 
+// n is a power of two >= 16 (checked at init): V = n^3 is a multiple of 256,
+// the number of bricks n^3 / 256 is a multiple of 8, and n / 4 (bricks
+// along z) a multiple of 4, as k_sl_gather's brick map needs.
 template <typename RC>
-void launch_sl(const SLArgs& a, hipStream_t st) {
+void launch_sl(const SLArgs& a, void* packed, CoefScalars* cs, hipStream_t st) {
   const long long V = (long long)a.n_grid * a.n_grid * a.n_grid;
-  hipLaunchKernelGGL(k_sl<RC>, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, a);
+  RC* v4 = static_cast<RC*>(packed);
+  RC* q8 = v4 + 4 * V;
+  if (sizeof(RC) != sizeof(double)) {
+    const long long blocks = std::min<long long>(V / 256, 4096);
+    hipLaunchKernelGGL(k_sl_scan, dim3((unsigned)blocks), dim3(256), 0, st, a, cs);
+    hipLaunchKernelGGL(k_sl_pack<RC>, dim3((unsigned)(V / 256)), dim3(256), 0, st, a, v4, q8, cs);
+  } else {
+    hipLaunchKernelGGL(k_sl_cfl, dim3((unsigned)(V / 256)), dim3(256), 0, st, a, cs);
+  }
+  hipLaunchKernelGGL(k_sl_gather<RC>, dim3((unsigned)(V / 256)), dim3(256), 0, st, a, v4, q8, cs);
 }
-template void launch_sl<double>(const SLArgs&, hipStream_t);
-template void launch_sl<float>(const SLArgs&, hipStream_t);
+template void launch_sl<double>(const SLArgs&, void*, CoefScalars*, hipStream_t);
+template void launch_sl<float>(const SLArgs&, void*, CoefScalars*, hipStream_t);
 
 __global__ void k_interp(int n, const double* q, const double* jx, const double* jy, const double* jz,
                          long long count, double* out) {
@@ -346,7 +530,7 @@ __global__ void __launch_bounds__(kRedThreads) k_residual(KrylovArgs a, SpecIdx 
       const cplx<R> bv = drop ? czero<R>() : b[k];
       const cplx<R> rv = ax ? csub(bv, ax[k]) : bv;
       r[k] = rv;
-      if (r32) r32[k] = {float(rv.x), float(rv.y)};
+      if (r32) r32[k] = {float(a.scale32 * rv.x), float(a.scale32 * rv.y)};
       acc[0] += wdot(bv, bv, kx);
       acc[1] += wdot(rv, rv, kx);
     }
@@ -633,14 +817,14 @@ TUMOR_INST_KRYLOV(double)
 TUMOR_INST_KRYLOV(float)
 
 // -------------------------------------------------------------- conversions
-__global__ void k_add32to64(double* x, const float* y, long long count) {
+__global__ void k_add32to64(double* x, const float* y, double s, long long count) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < count) x[k] += (double)y[k];
+  if (k < count) x[k] += (double)y[k] * s;
 }
-void launch_add32to64(void* x64, const void* x32, long long count, hipStream_t st) {
+void launch_add32to64(void* x64, const void* x32, double s, long long count, hipStream_t st) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_add32to64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
-                     static_cast<double*>(x64), static_cast<const float*>(x32), count);
+                     static_cast<double*>(x64), static_cast<const float*>(x32), s, count);
 }
 
 __global__ void k_f32_to_f64(const float* in, double* out, long long count) {

@@ -56,11 +56,11 @@ PARAM_ORDER = tuple(TABLE_SETUP.keys())
 # The five workloads: grid size, precision, step count, tissue smoothing
 # width (cells), tumour-seed recipe.
 WORKLOADS = {
-    "c1": dict(index=0, n=32, precision="fp64", steps=10, sigma_cells=2.0, seeds="single"),
-    "c2": dict(index=1, n=128, precision="fp64", steps=100, sigma_cells=4.0, seeds="three"),
-    "c3": dict(index=2, n=256, precision="mixed", steps=100, sigma_cells=8.0, seeds="three"),
-    "c4": dict(index=3, n=128, precision="fp64", steps=50, sigma_cells=4.0, seeds="lattice"),
-    "c5": dict(index=4, n=256, precision="mixed", steps=200, sigma_cells=8.0, seeds="lattice"),
+    "seed1_n32": dict(seed=0, n=32, precision="fp64", steps=10, sigma_cells=2.0, seeds="single"),
+    "seeds3_n128": dict(seed=1, n=128, precision="fp64", steps=100, sigma_cells=4.0, seeds="three"),
+    "seeds3_n256": dict(seed=2, n=256, precision="mixed", steps=100, sigma_cells=8.0, seeds="three"),
+    "lattice_n128": dict(seed=3, n=128, precision="fp64", steps=50, sigma_cells=4.0, seeds="lattice"),
+    "lattice_n256": dict(seed=4, n=256, precision="mixed", steps=200, sigma_cells=8.0, seeds="lattice"),
 }
 
 
@@ -125,8 +125,8 @@ def workload_inputs(name: str, n: int | None = None):
     """All inputs of a named workload (optionally at another grid size)."""
     wl = WORKLOADS[name]
     nn = wl["n"] if n is None else int(n)
-    wm, gm, csf = tissue_maps(nn, wl["sigma_cells"], wl["index"])
-    centers, sigmas, weights = tumor_seeds(wl["seeds"], wl["index"])
+    wm, gm, csf = tissue_maps(nn, wl["sigma_cells"], wl["seed"])
+    centers, sigmas, weights = tumor_seeds(wl["seeds"], wl["seed"])
     return dict(n=nn, wm=wm, gm=gm, csf=csf, centers=centers, sigmas=sigmas,
                 weights=weights, steps=wl["steps"], precision=wl["precision"],
                 dt=0.01, rtol=1e-8)

@@ -72,7 +72,7 @@ def _case(name, n, steps, params=None):
 @pytest.mark.parametrize("ckpt", [1, 2])
 def test_adjoint_matches_oracle_16(ckpt):
     steps = 3
-    P, inp, target = _case("c4", 16, steps, dict(delta_p=60.0))
+    P, inp, target = _case("lattice_n128", 16, steps, dict(delta_p=60.0))
     say(f"adjoint n=16 steps={steps} ckpt={ckpt}")
     L, gr, gw, lam_o = adj.gradient(P, inp, steps, target, ORACLE_CFG)
     lam_g, grad_g = _gpu_gradient(inp, P, steps, target, ckpt)
@@ -81,7 +81,7 @@ def test_adjoint_matches_oracle_16(ckpt):
 
 def test_adjoint_matches_oracle_32_hypoxic():
     steps = 4
-    P, inp, target = _case("c1", 32, steps, dict(delta_p=60.0))
+    P, inp, target = _case("seed1_n32", 32, steps, dict(delta_p=60.0))
     say(f"adjoint n=32 steps={steps}")
     L, gr, gw, lam_o = adj.gradient(P, inp, steps, target, ORACLE_CFG)
     lam_g, grad_g = _gpu_gradient(inp, P, steps, target, 3)
@@ -90,7 +90,7 @@ def test_adjoint_matches_oracle_32_hypoxic():
 
 def test_mixed_precision_adjoint():
     steps = 3
-    P, inp, target = _case("c4", 16, steps, dict(delta_p=60.0))
+    P, inp, target = _case("lattice_n128", 16, steps, dict(delta_p=60.0))
     L, gr, gw, lam_o = adj.gradient(P, inp, steps, target, ORACLE_CFG)
     lam_g, grad_g = _gpu_gradient(inp, P, steps, target, 2, precision="mixed", rtol=1e-10)
     # The seed h^3 (tau_T - tau_target) is a difference of two nearby states,
@@ -103,7 +103,7 @@ def test_mixed_precision_adjoint():
 def test_adjoint_requires_a_recording():
     need_gpu()
     P = synthetic.params()
-    inp = synthetic.workload_inputs("c1", n=16)
+    inp = synthetic.workload_inputs("seed1_n32", n=16)
     sim = tm.from_inputs(inp, P)
     import torch
     lam = torch.zeros((14, 16, 16, 16), dtype=torch.float64, device="cuda")
@@ -120,7 +120,7 @@ def test_autograd_function_gradient_and_directional_fd():
     torch = need_gpu()
     from paper_1810_05370_amd.autograd import SimSpec, simulate, theta_from
     steps = 3
-    P, inp, target = _case("c4", 16, steps, dict(delta_p=60.0))
+    P, inp, target = _case("lattice_n128", 16, steps, dict(delta_p=60.0))
     spec = SimSpec(inputs=inp, params=P, steps=steps, ckpt_every=2, rtol=1e-12, max_it=2000)
     h3 = (2 * np.pi / 16) ** 3
     tgt = torch.as_tensor(target).cuda()

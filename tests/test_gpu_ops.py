@@ -24,7 +24,7 @@ TOL32 = 2e-6      # the same in FP32 (mixed precision kernels)
 
 def _sim(n, precision="fp64", seed=0):
     torch = need_gpu()
-    inp = synthetic.workload_inputs("c1", n=n)
+    inp = synthetic.workload_inputs("seed1_n32", n=n)
     P = synthetic.params()
     sim = tm.from_inputs(inp, P, precision=precision)
     return torch, sim, inp, P

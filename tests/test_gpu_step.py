@@ -70,32 +70,32 @@ def _run_case(P, inp, steps, flags=tm.F_DEFAULT, cfg=None, tol=1e-10):
 
 def test_small_grid_two_steps():
     P = synthetic.params()
-    _run_case(P, synthetic.workload_inputs("c1", n=16), 2)
+    _run_case(P, synthetic.workload_inputs("seed1_n32", n=16), 2)
 
 
-def test_workload_c1_ten_steps_32():
+def test_single_seed_workload_ten_steps_32():
     # The 32^3, 10-step FP64 workload.
     P = synthetic.params()
-    _run_case(P, synthetic.workload_inputs("c1"), 10)
+    _run_case(P, synthetic.workload_inputs("seed1_n32"), 10)
 
 
 def test_hypoxic_regime_exercises_invasion_necrosis_and_edema():
     # Strong oxygen consumption drives the tumour core hypoxic within a few
     # steps, so the p -> i switch, necrosis and the edema source are active.
     P = synthetic.params(delta_p=60.0)
-    st, stats = _run_case(P, synthetic.workload_inputs("c1", n=32), 6)
+    st, stats = _run_case(P, synthetic.workload_inputs("seed1_n32", n=32), 6)
     assert st.f["i"].max() > 1e-3 and st.f["n"].max() > 1e-3 and st.f["l"].max() > 1e-4
 
 
 def test_three_seed_workload_at_64():
     P = synthetic.params()
-    inp = synthetic.workload_inputs("c2", n=64)
+    inp = synthetic.workload_inputs("seeds3_n128", n=64)
     _run_case(P, inp, 3)
 
 
 def test_sub_step_switches():
     P = synthetic.params(delta_p=60.0)
-    inp = synthetic.workload_inputs("c1", n=16)
+    inp = synthetic.workload_inputs("seed1_n32", n=16)
     _run_case(P, inp, 3, flags=tm.F_ELASTICITY, cfg=dict(advection=False, edema=False))
     _run_case(P, inp, 3, flags=tm.F_ADVECTION | tm.F_EDEMA, cfg=dict(elasticity=False))
 
@@ -103,7 +103,7 @@ def test_sub_step_switches():
 def test_no_tumour_is_a_steady_state_of_the_tissue():
     need_gpu()
     P = synthetic.params()
-    inp = synthetic.workload_inputs("c1", n=16)
+    inp = synthetic.workload_inputs("seed1_n32", n=16)
     inp = dict(inp, centers=np.zeros((0, 3)), sigmas=np.zeros(0), weights=np.zeros(0))
     sim = tm.from_inputs(inp, P)
     sim.step(2)
@@ -119,7 +119,7 @@ def test_no_tumour_is_a_steady_state_of_the_tissue():
 def test_mixed_precision_matches_fp64_oracle():
     need_gpu()
     P = synthetic.params()
-    inp = synthetic.workload_inputs("c1")
+    inp = synthetic.workload_inputs("seed1_n32")
     steps = 10
     st, stats = _oracle(P, inp, steps)
     sim = tm.from_inputs(inp, P, precision="mixed")
@@ -130,12 +130,31 @@ def test_mixed_precision_matches_fp64_oracle():
     sim.close()
 
 
+def test_mixed_precision_with_fields_below_fp32_range():
+    """A tumour of amplitude 5e-31: forces, residuals and the necrotic cells lie
+    far below FP32's normal range, so the FP32 stages work on power-of-two
+    scaled copies; the result must still match the FP64 oracle."""
+    need_gpu()
+    P = synthetic.params(delta_p=60.0)
+    inp = synthetic.workload_inputs("seed1_n32", n=16)
+    inp = dict(inp, weights=1e-30 * np.asarray(inp["weights"]))
+    steps = 4
+    st, stats = _oracle(P, inp, steps)
+    assert 0.0 < np.abs(st.u).max() < 1e-40
+    sim = tm.from_inputs(inp, P, precision="mixed")
+    for k in range(steps):
+        s = sim.step(1)
+        assert s["relres_elast"] <= 1e-8 and max(s["relres_diff"]) <= 1e-8, s
+    _compare(sim, st, 1e-5, "mixed tiny n=16")
+    sim.close()
+
+
 def test_elasticity_solve_entry_point():
     need_gpu()
     import torch
     from oracle import reaction as rx, solvers
     P = synthetic.params()
-    inp = synthetic.workload_inputs("c1", n=32)
+    inp = synthetic.workload_inputs("seed1_n32", n=32)
     sim = tm.from_inputs(inp, P)
     st = model.init_state(P, 32, inp["wm"], inp["gm"], inp["csf"], inp["centers"], inp["sigmas"], inp["weights"])
     co = st.coef
@@ -155,7 +174,7 @@ def test_elasticity_solve_entry_point():
 def test_invalid_arguments_on_a_live_context():
     need_gpu()
     P = synthetic.params()
-    sim = tm.from_inputs(synthetic.workload_inputs("c1", n=16), P)
+    sim = tm.from_inputs(synthetic.workload_inputs("seed1_n32", n=16), P)
     lib = sim.lib
     assert lib.tumor_get_field(sim.ctx, 99, None) == tm.EINVAL
     assert lib.tumor_apply_op(sim.ctx, 42, None, None) == tm.EINVAL
@@ -169,7 +188,7 @@ def test_invalid_arguments_on_a_live_context():
 def test_max_it_reports_no_convergence():
     need_gpu()
     P = synthetic.params()
-    sim = tm.from_inputs(synthetic.workload_inputs("c1", n=16), P, max_it=2)
+    sim = tm.from_inputs(synthetic.workload_inputs("seed1_n32", n=16), P, max_it=2)
     with pytest.raises(tm.TumorError) as e:
         sim.step(1)
     assert e.value.code == tm.ENOCONV

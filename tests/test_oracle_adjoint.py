@@ -167,7 +167,7 @@ def test_reaction_adjoint_matches_finite_differences(o_range):
 
 def _grad_case(n=16, steps=3, seed_params=None):
     P = synthetic.params(**(seed_params or {}))
-    inp = synthetic.workload_inputs("c4", n=n)
+    inp = synthetic.workload_inputs("lattice_n128", n=n)
     # target from a run with perturbed parameters
     Pt = dict(P, rho_w=P["rho_w"] * 1.1, rho_g=P["rho_g"] * 1.1, k_w=P["k_w"] * 0.9)
     st, _ = model.run(Pt, inp, steps, TIGHT)
@@ -215,7 +215,7 @@ def test_directional_gradient_on_all_species_slots():
     steps = 2
     n = 12
     P = synthetic.params(delta_p=60.0)
-    inp = synthetic.workload_inputs("c1", n=n)
+    inp = synthetic.workload_inputs("seed1_n32", n=n)
     st0 = model.init_state(P, n, inp["wm"], inp["gm"], inp["csf"], inp["centers"], inp["sigmas"], inp["weights"])
     target = 0.8 * (st0.f["p"])
     rng = np.random.default_rng(11)

@@ -22,7 +22,7 @@ def test_gaussian_basis_peak_symmetry_and_periodic_wrap():
 
 def test_diffusion_plus_reaction_conserve_total_cell_density_pointwise():
     P = synthetic.params()
-    inp = synthetic.workload_inputs("c1", n=16)
+    inp = synthetic.workload_inputs("seed1_n32", n=16)
     st = model.init_state(P, 16, inp["wm"], inp["gm"], inp["csf"], inp["centers"], inp["sigmas"], inp["weights"])
     rng = np.random.default_rng(3)
     st.f["i"] = 0.2 * rng.uniform(size=st.f["i"].shape)
@@ -35,7 +35,7 @@ def test_diffusion_plus_reaction_conserve_total_cell_density_pointwise():
 
 def test_global_mass_is_constant_without_transport():
     P = synthetic.params()
-    inp = synthetic.workload_inputs("c1", n=16)
+    inp = synthetic.workload_inputs("seed1_n32", n=16)
     st = model.init_state(P, 16, inp["wm"], inp["gm"], inp["csf"], inp["centers"], inp["sigmas"], inp["weights"])
     m0 = sum(st.f[k].sum() for k in "pingw")
     for s in range(3):
@@ -48,7 +48,7 @@ def test_step_order_and_elasticity_certificate():
     # One full step on a tiny grid: the displacement solves the elasticity
     # system built from the refreshed coefficients and the new species.
     P = synthetic.params()
-    inp = synthetic.workload_inputs("c1", n=16)
+    inp = synthetic.workload_inputs("seed1_n32", n=16)
     st = model.init_state(P, 16, inp["wm"], inp["gm"], inp["csf"], inp["centers"], inp["sigmas"], inp["weights"])
     cfg = dict(rtol_elast=1e-11)
     s1 = model.step(st, cfg)
@@ -66,7 +66,7 @@ def test_step_order_and_elasticity_certificate():
 
 def test_run_is_deterministic():
     P = synthetic.params()
-    inp = synthetic.workload_inputs("c1", n=16)
+    inp = synthetic.workload_inputs("seed1_n32", n=16)
     a, sa = model.run(P, inp, 2)
     b, sb = model.run(P, inp, 2)
     for k in model.FIELDS:

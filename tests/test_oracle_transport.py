@@ -100,3 +100,18 @@ def test_advection_is_linear_and_conservative_source_vanishes_for_solenoidal_flo
     vs = np.stack([np.sin(y3), np.cos(z3), np.sin(x3)]) * 5.0
     o = transport.advect(g, {k: a for k in "pingwf"}, vs, dt)
     assert np.max(np.abs(o["p"] - o["f"])) < 1e-13
+
+
+def test_sampled_nodes_equal_the_whole_grid_step():
+    """advect(..., nodes=...) evaluates the same step at a subset of nodes."""
+    n, dt = 16, 0.01
+    g = Grid(n)
+    rng = np.random.default_rng(3)
+    v = [0.3 * g.ifft(g.fft(rng.standard_normal((n, n, n)))) / dt * g.h for _ in range(3)]
+    fields = {k: rng.random((n, n, n)) for k in ("p", "i", "n", "g", "w", "f")}
+    full = transport.advect(g, fields, v, dt)
+    idx = rng.integers(0, n, size=(3, 50))
+    nodes = tuple(a.astype(np.float64) for a in idx)
+    part = transport.advect(g, fields, v, dt, nodes=nodes)
+    for k in full:
+        assert np.array_equal(part[k], full[k][idx[2], idx[1], idx[0]]), k
