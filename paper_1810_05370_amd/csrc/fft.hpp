@@ -113,24 +113,17 @@ template <> struct Radix<128> { static constexpr int S = 3, r2 = 4, r3 = 4; };
 template <> struct Radix<256> { static constexpr int S = 3, r2 = 8, r3 = 4; };
 template <> struct Radix<512> { static constexpr int S = 3, r2 = 8, r3 = 8; };
 
-// LDS view of one transform: element `pos` lives at re[a], im[a] with
-// a = pos*ls + (pos/8)*pad (the pad breaks power-of-two bank strides).
+// LDS view of one transform: element `pos` lives at buf[a] (a complex value,
+// one 8- or 16-byte LDS access) with a = pos*ls + (pos/8)*pad (the pad breaks
+// power-of-two bank strides).
 template <typename R>
 struct LdsView {
-  R* re;
-  R* im;
+  cplx<R>* buf;
   int ls;
   int pad;
   __device__ __forceinline__ int addr(int pos) const { return pos * ls + (pos >> 3) * pad; }
-  __device__ __forceinline__ void put(int pos, cplx<R> v) const {
-    const int a = addr(pos);
-    re[a] = v.x;
-    im[a] = v.y;
-  }
-  __device__ __forceinline__ cplx<R> get(int pos) const {
-    const int a = addr(pos);
-    return {re[a], im[a]};
-  }
+  __device__ __forceinline__ void put(int pos, cplx<R> v) const { buf[addr(pos)] = v; }
+  __device__ __forceinline__ cplx<R> get(int pos) const { return buf[addr(pos)]; }
 };
 
 template <typename R, int L, bool INV, int TWS, int r, int p, bool LAST>

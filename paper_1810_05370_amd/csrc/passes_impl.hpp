@@ -39,7 +39,9 @@ template <int N>
 struct RowCfg {
   static constexpr int L = N / 2;
   static constexpr int TP = L / 8;
-  static constexpr int RW0 = 256 / TP;
+  // One wave per block: the LDS exchanges of a row transform then wait on
+  // that wave alone, and independent waves hide each other's memory latency.
+  static constexpr int RW0 = 64 / TP;
   static constexpr int RW = RW0 > N * N ? N * N : RW0;
   static constexpr int THREADS = RW * TP;
   static constexpr int LP = L + L / 8;  // padded row length in LDS
@@ -105,8 +107,7 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
   if (prog.skip && *prog.skip) return;
   using Cfg = ColCfg<N, R>;
   constexpr int TP = Cfg::TP, TC = Cfg::TC;
-  __shared__ R sre[Cfg::LDS];
-  __shared__ R sim[Cfg::LDS];
+  __shared__ cplx<R> sbuf[Cfg::LDS];
   __shared__ cplx<R> stw[N];
   stage_twiddles<R, N>(stw, twg);
   const cplx<R>* tw = stw;
@@ -114,7 +115,7 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
   const int col = tid % TC;
   const int t = tid / TC;
   const long long base = (long long)blockIdx.y * fstride + (long long)blockIdx.x * TC + col;
-  const LdsView<R> lds{sre + col, sim + col, TC, 1};
+  const LdsView<R> lds{sbuf + col, TC, 1};
   double dotacc = 0.0;
   // Software pipelining: the input column of the next FFT job is loaded into
   // `nxt` before the current job's FFT, whose barriers wait on LDS only.
@@ -204,8 +205,7 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
   constexpr long long C = N / 2;
   constexpr long long S = (long long)N * N * C;
   constexpr long long astride = (long long)N * C;
-  __shared__ R sre[Cfg::LDS];
-  __shared__ R sim[Cfg::LDS];
+  __shared__ cplx<R> sbuf[Cfg::LDS];
   __shared__ cplx<R> stw[N];
   stage_twiddles<R, N>(stw, twg);
   const cplx<R>* tw = stw;
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
   const int kx = blockIdx.x * TC + col;
   const int ky = wavenum<N>(blockIdx.y);
   const long long base = (long long)blockIdx.y * C + kx;
-  const LdsView<R> lds{sre + col, sim + col, TC, 1};
+  const LdsView<R> lds{sbuf + col, TC, 1};
   const R beta = R(a.sv->beta);
   const cplx<R>* __restrict__ r = static_cast<const cplx<R>*>(a.r);
   cplx<R>* __restrict__ p = static_cast<cplx<R>*>(a.p);
@@ -361,15 +361,16 @@ __device__ __forceinline__ cplx<R> iwx(cplx<R> a, int k) {
 #define TUMOR_ROW_SETUP(N)                                           \
   using RC = RowCfg<N>;                                              \
   constexpr int L = RC::L, TP = RC::TP;                              \
-  __shared__ R sre[RC::RW * RC::LP];                                 \
-  __shared__ R sim[RC::RW * RC::LP];                                 \
+  /* rows of a wave start 8 LDS banks apart (bank = 4 bytes, 32 banks) */ \
+  constexpr int LPR = RC::LP + 32 / (int)sizeof(cplx<R>);             \
+  __shared__ cplx<R> sbuf[RC::RW * LPR];                             \
   __shared__ cplx<R> stw[N];                                         \
   stage_twiddles<R, N>(stw, twg);                                    \
   const cplx<R>* tw = stw;                                           \
   const int t = threadIdx.x % TP;                                    \
   const int rl = threadIdx.x / TP;                                   \
   const long long row = (long long)blockIdx.x * RC::RW + rl;         \
-  const LdsView<R> lds{sre + rl * RC::LP, sim + rl * RC::LP, 1, 1};  \
+  const LdsView<R> lds{sbuf + rl * LPR, 1, 1};                      \
   const long long soff = row * L;                                    \
   const long long poff = row * N;                                    \
   (void)soff;                                                        \
@@ -416,7 +417,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xfwd(XProg prog, const c
 }
 
 template <typename R, int N>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xelast(XElastArgs a, const cplx<R>* __restrict__ twg) {
+__global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2)) k_xelast(XElastArgs a, const cplx<R>* __restrict__ twg) {
   if (a.skip && *a.skip) return;
   TUMOR_ROW_SETUP(N)
   const R invV = R(1.0) / (R(N) * R(N) * R(N));
@@ -430,33 +431,46 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xelast(XElastArgs a, con
 #pragma unroll
   for (int f = 0; f < 8; ++f) out[f] = static_cast<cplx<R>*>(a.out[f]) + soff;
 
-  // Group A: diagonal stresses and eta u_x.
   {
-    cplx<R> ux[8], exx[8], eyy[8], ezz[8];
-    row_c2r<R, N>(ux, in[0], false, nullptr, lds, t, tw);
-    row_c2r<R, N>(exx, in[0], true, nullptr, lds, t, tw);
-    row_c2r<R, N>(eyy, in[4], false, nullptr, lds, t, tw);
-    row_c2r<R, N>(ezz, in[7], false, nullptr, lds, t, tw);
+    const ColTerm trace_terms[3] = {{0, SYM_IW, 1.0}, {4, SYM_ONE, 1.0}, {7, SYM_ONE, 1.0}};
+    cplx<R> tr[8];
+    row_c2r_terms<R, N>(tr, 3, trace_terms, a.in, soff, lds, t, tw);
+    cplx<R> sx[8];
+    row_c2r<R, N>(sx, in[0], true, nullptr, lds, t, tw);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int p = t + TP * j;
-      const cplx<R> m = mu[p], l = lam[p], e = eta[p];
-      const R trx = (exx[j].x + eyy[j].x + ezz[j].x) * invV;
-      const R try_ = (exx[j].y + eyy[j].y + ezz[j].y) * invV;
-      exx[j] = {R(2) * m.x * exx[j].x * invV + l.x * trx, R(2) * m.y * exx[j].y * invV + l.y * try_};
-      eyy[j] = {R(2) * m.x * eyy[j].x * invV + l.x * trx, R(2) * m.y * eyy[j].y * invV + l.y * try_};
-      ezz[j] = {R(2) * m.x * ezz[j].x * invV + l.x * trx, R(2) * m.y * ezz[j].y * invV + l.y * try_};
-      ux[j] = {e.x * ux[j].x * invV, e.y * ux[j].y * invV};
+      const cplx<R> m = mu[p], l = lam[p];
+      tr[j] = {tr[j].x * invV, tr[j].y * invV};
+      sx[j] = {R(2) * m.x * sx[j].x * invV + l.x * tr[j].x, R(2) * m.y * sx[j].y * invV + l.y * tr[j].y};
     }
-    row_r2c<R, N>(ux, lds, t, tw);
-    row_r2c<R, N>(exx, lds, t, tw);
+    row_r2c<R, N>(sx, lds, t, tw);
+    {
+      cplx<R> ux[8];
+      row_c2r<R, N>(ux, in[0], false, nullptr, lds, t, tw);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) ux[j] = csub(ux[j], iwx<R, N>(exx[j], t + TP * j));
-    store_row<R, N>(out[0], ux, t);
-    row_r2c<R, N>(eyy, lds, t, tw);
-    store_row<R, N>(out[4], eyy, t);
-    row_r2c<R, N>(ezz, lds, t, tw);
-    store_row<R, N>(out[7], ezz, t);
+      for (int j = 0; j < 8; ++j) {
+        const cplx<R> e = eta[t + TP * j];
+        ux[j] = {e.x * ux[j].x * invV, e.y * ux[j].y * invV};
+      }
+      row_r2c<R, N>(ux, lds, t, tw);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ux[j] = csub(ux[j], iwx<R, N>(sx[j], t + TP * j));
+      store_row<R, N>(out[0], ux, t);
+    }
+#pragma unroll 1
+    for (int d = 0; d < 2; ++d) {
+      cplx<R> sd[8];
+      row_c2r<R, N>(sd, d == 0 ? in[4] : in[7], false, nullptr, lds, t, tw);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int p = t + TP * j;
+        const cplx<R> m = mu[p], l = lam[p];
+        sd[j] = {R(2) * m.x * sd[j].x * invV + l.x * tr[j].x, R(2) * m.y * sd[j].y * invV + l.y * tr[j].y};
+      }
+      row_r2c<R, N>(sd, lds, t, tw);
+      store_row<R, N>(d == 0 ? out[4] : out[7], sd, t);
+    }
   }
   // Groups B and C: shear in the xy and xz planes with eta u_y, eta u_z.
 #pragma unroll 1
