@@ -145,6 +145,9 @@ void launch_pcg_pupdate(const KrylovArgs& a, hipStream_t st);
 template <typename R>
 void launch_precond(const KrylovArgs& a, const void* in, void* out, hipStream_t st);
 // x64 += x32 over ncomp blocks
+// alpha = rho / sum of nb partials of <p, q> (stride apart); nothing once done.
+void launch_fin_alpha(SolveScalars* sv, const double* part, int nb, int stride, hipStream_t st);
+
 // x64 += s * double(x32)
 void launch_add32to64(void* x64, const void* x32, double s, long long count, hipStream_t st);
 // physical float -> double

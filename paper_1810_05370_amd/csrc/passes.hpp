@@ -47,8 +47,9 @@ struct ColProg {
   ColTerm term[kMaxCol][kMaxTerms];
   const int* skip;  // if non-null and *skip != 0 the launch does nothing
   // Optional fused Krylov inner product of a forward z pass: with dsv set,
-  // alpha = rho / sum_o <dotp[o], out[o]> (Parseval-weighted) is published
-  // to dsv by the last block.
+  // each block stores its partial of sum_o <dotp[o], out[o]> (Parseval-
+  // weighted) in dpart[block], and the launcher queues the one-block kernel
+  // that publishes alpha = rho / total to dsv.
   const void* dotp[kMaxCol];
   SolveScalars* dsv;
   double* dpart;

@@ -52,51 +52,24 @@ __device__ __forceinline__ int xwave(int k) {  // x wave number of packed index 
   return k;                                    // k = 0 carries both kx = 0 and kx = N/2: w = 0
 }
 
-// Block sum of v, then the last block of the grid totals the partials in a
-// fixed order and sets alpha = rho / total (or flags a breakdown).
+// Block sum of v stored as this block's partial of an inner product (plain
+// store; launch_fin_alpha, queued right after the pass, totals the partials).
 __device__ __forceinline__ double wave_sum_f(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-__device__ void fused_alpha(double v, SolveScalars* sv, double* part) {
+__device__ void store_dot_partial(double v, double* part) {
   __shared__ double sh[16];
-  __shared__ int last;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  const int nb = gridDim.x * gridDim.y;
-  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   v = wave_sum_f(v);
   if (lane == 0) sh[wv] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += sh[w];
-    part[bid] = s;
-    __threadfence();
-    last = (atomicAdd(&sv->counter, 1u) == (unsigned)nb - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const volatile double* vp = part;
-  double t = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) t += vp[b];
-  t = wave_sum_f(t);
-  __syncthreads();
-  if (lane == 0) sh[wv] = t;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += sh[w];
-    sv->pq = s;
-    if (!(isfinite(s) && s > 0.0)) {
-      sv->bad = 1;
-      sv->done = 1;
-    } else {
-      sv->alpha = sv->rho / s;
-    }
-    sv->counter = 0u;
+    part[blockIdx.y * gridDim.x + blockIdx.x] = s;
   }
 }
 
@@ -125,6 +98,8 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
     for (int j = 0; j < 8; ++j) dst[j] = sp[base + (long long)(t + TP * j) * astride];
   };
   cplx<R> nxt[8];
+  cplx<R> pdot[8];
+  (void)pdot;
   load_col(nxt, prog.term[0][0].src);
   for (int o = 0; o < prog.nout; ++o) {
     cplx<R> acc[8];
@@ -158,6 +133,13 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
     } else {
 #pragma unroll
       for (int j = 0; j < 8; ++j) acc[j] = czero<R>();
+      if constexpr (DOT) {
+        // the inner-product operand at the output positions, loaded before the
+        // transforms so that its latency overlaps them
+        const cplx<R>* __restrict__ pp = static_cast<const cplx<R>*>(prog.dotp[o]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) pdot[j] = pp[base + (long long)(t + TP * j) * astride];
+      }
       for (int q = 0; q < nt; ++q) {
         const ColTerm tm = prog.term[o][q];
         const R cf = R(tm.coef);
@@ -180,19 +162,17 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
 #pragma unroll
     for (int j = 0; j < 8; ++j) dst[base + (long long)(t + TP * j) * astride] = acc[j];
     if constexpr (DOT) {
-      const cplx<R>* __restrict__ pp = static_cast<const cplx<R>*>(prog.dotp[o]);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const cplx<R> pv = pp[base + (long long)(t + TP * j) * astride];
-        dotacc += (double)pv.x * (double)acc[j].x + (double)pv.y * (double)acc[j].y;
-      }
+      for (int j = 0; j < 8; ++j) dotacc += (double)pdot[j].x * (double)acc[j].x + (double)pdot[j].y * (double)acc[j].y;
     }
   }
   if constexpr (DOT) {
+    static_assert((N / 2 / TC) * N <= kRedBlocksMax * kPartialsPerBlock,
+                  "one inner-product partial per block must fit the partials buffer");
     // Parseval weight: the packed kx = 0 column counts once, the others twice
     const int kxp = blockIdx.x * TC + col;
     dotacc *= (kxp == 0) ? 1.0 : 2.0;
-    fused_alpha(dotacc, prog.dsv, prog.dpart);
+    store_dot_partial(dotacc, prog.dpart);
   }
 }
 
@@ -584,9 +564,11 @@ void launch_col_pass(int n, int axis, bool inverse, const ColProg& prog, const v
     dim3 grid(C / Cfg::TC, NN);
     if (inverse)
       hipLaunchKernelGGL((k_col_pass<R, NN, true>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride, astride, twp);
-    else if (prog.dsv)
+    else if (prog.dsv) {
       hipLaunchKernelGGL((k_col_pass<R, NN, false, true>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride, astride,
                          twp);
+      launch_fin_alpha(prog.dsv, prog.dpart, (int)(grid.x * grid.y), 1, st);
+    }
     else
       hipLaunchKernelGGL((k_col_pass<R, NN, false>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride, astride, twp);
   });

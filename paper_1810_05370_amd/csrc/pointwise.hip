@@ -76,6 +76,56 @@ __device__ void final_sums(double (&tot)[NV], const double* part, uint32_t* coun
   if (threadIdx.x == 0) *counter = 0u;
 }
 
+// Block-reduce v[] and store this block's partials (plain stores, no fence):
+// a one-block finishing kernel launched next totals them, the kernel boundary
+// making them visible.  A device-scope fence per block would instead push the
+// block's whole output out of its XCD's L2.
+template <int NV>
+__device__ void block_store_partials(double (&v)[NV], double* part) {
+  __shared__ double sh[NV][kRedThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double s = wave_sum(v[i]);
+    if (lane == 0) sh[i][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < kRedThreads / 64; ++w) s += sh[i][w];
+      part[(long long)blockIdx.x * kPartialsPerBlock + i] = s;
+    }
+  }
+}
+
+// Fixed-order totals of NV partials of nb blocks (one block of kRedThreads).
+template <int NV>
+__device__ void total_partials(double (&tot)[NV], const double* part, int nb, int stride) {
+  __shared__ double sh[NV][kRedThreads / 64];
+  double v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kRedThreads) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += part[(long long)b * stride + i];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double s = wave_sum(v[i]);
+    if (lane == 0) sh[i][wv] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[i][w];
+    tot[i] = s;
+  }
+}
+
 static inline int red_blocks(long long count) {
   long long b = (count + kRedThreads - 1) / kRedThreads;
   if (b > kRedBlocksMax) b = kRedBlocksMax;
@@ -634,17 +684,22 @@ __global__ void __launch_bounds__(kRedThreads) k_pcg_pq(KrylovArgs a, SpecIdx ix
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[0] += wdot(p[e + c * S], q[e + c * S], kx);
   }
-  if (block_partials<1>(acc, a.partials, &a.sv->counter)) {
-    double tot[1];
-    final_sums<1>(tot, a.partials, &a.sv->counter);
-    if (threadIdx.x == 0) {
-      a.sv->pq = tot[0];
-      if (!(isfinite(tot[0]) && tot[0] > 0.0)) {
-        a.sv->bad = 1;
-        a.sv->done = 1;
-      } else {
-        a.sv->alpha = a.sv->rho / tot[0];
-      }
+  block_store_partials<1>(acc, a.partials);
+}
+
+// alpha = rho / <p, q> from the partials of <p, q> (nb blocks, given stride).
+__global__ void __launch_bounds__(kRedThreads) k_fin_alpha(SolveScalars* sv, const double* part, int nb,
+                                                            int stride) {
+  if (sv->done) return;
+  double tot[1];
+  total_partials<1>(tot, part, nb, stride);
+  if (threadIdx.x == 0) {
+    sv->pq = tot[0];
+    if (!(isfinite(tot[0]) && tot[0] > 0.0)) {
+      sv->bad = 1;
+      sv->done = 1;
+    } else {
+      sv->alpha = sv->rho / tot[0];
     }
   }
 }
@@ -685,26 +740,30 @@ __global__ void __launch_bounds__(kRedThreads) k_pcg_update(KrylovArgs a, SpecId
       acc[1] += wdot(rv[c], zv[c], kx);
     }
   }
-  if (block_partials<2>(acc, a.partials, &a.sv->counter)) {
-    double tot[2];
-    final_sums<2>(tot, a.partials, &a.sv->counter);
-    if (threadIdx.x == 0) {
-      SolveScalars* sv = a.sv;
-      sv->it += 1;
-      sv->rr = tot[0];
-      if (!(isfinite(tot[0]) && isfinite(tot[1]))) {
-        sv->bad = 1;
-        sv->done = 1;
-      } else if (!a.fixed && tot[0] <= a.thr2) {
-        sv->conv = 1;
-        sv->done = 1;
-      } else if (sv->it >= a.limit) {
-        sv->conv = a.fixed ? 1 : 0;
-        sv->done = 1;
-      } else {
-        sv->beta = tot[1] / sv->rho;
-        sv->rho = tot[1];
-      }
+  block_store_partials<2>(acc, a.partials);
+}
+
+// After an update: iteration count, ||r||^2, convergence, beta and rho.
+__global__ void __launch_bounds__(kRedThreads) k_fin_update(KrylovArgs a, int nb) {
+  SolveScalars* sv = a.sv;
+  if (sv->done) return;
+  double tot[2];
+  total_partials<2>(tot, a.partials, nb, kPartialsPerBlock);
+  if (threadIdx.x == 0) {
+    sv->it += 1;
+    sv->rr = tot[0];
+    if (!(isfinite(tot[0]) && isfinite(tot[1]))) {
+      sv->bad = 1;
+      sv->done = 1;
+    } else if (!a.fixed && tot[0] <= a.thr2) {
+      sv->conv = 1;
+      sv->done = 1;
+    } else if (sv->it >= a.limit) {
+      sv->conv = a.fixed ? 1 : 0;
+      sv->done = 1;
+    } else {
+      sv->beta = tot[1] / sv->rho;
+      sv->rho = tot[1];
     }
   }
 }
@@ -777,15 +836,21 @@ void launch_pcg_start(const KrylovArgs& a, int zero_x, hipStream_t st) {
 template <typename R>
 void launch_pcg_pq(const KrylovArgs& a, hipStream_t st) {
   const SpecIdx ix = make_idx(a.n);
-  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_pq<R, NCC>), dim3(red_blocks(spec_count(a.n))),
-                                                 dim3(kRedThreads), 0, st, a, ix));
+  const int nb = red_blocks(spec_count(a.n));
+  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_pq<R, NCC>), dim3(nb), dim3(kRedThreads), 0, st, a, ix));
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kRedThreads), 0, st, a.sv, a.partials, nb, kPartialsPerBlock);
+}
+
+void launch_fin_alpha(SolveScalars* sv, const double* part, int nb, int stride, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kRedThreads), 0, st, sv, part, nb, stride);
 }
 
 template <typename R>
 void launch_pcg_update(const KrylovArgs& a, hipStream_t st) {
   const SpecIdx ix = make_idx(a.n);
-  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_update<R, NCC>), dim3(red_blocks(spec_count(a.n))),
-                                                 dim3(kRedThreads), 0, st, a, ix));
+  const int nb = red_blocks(spec_count(a.n));
+  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_update<R, NCC>), dim3(nb), dim3(kRedThreads), 0, st, a, ix));
+  hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(kRedThreads), 0, st, a, nb);
 }
 
 template <typename R>
