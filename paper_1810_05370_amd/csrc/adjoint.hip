@@ -8,7 +8,7 @@
 //   k_sl_adj    : semi-Lagrangian transport (interpolation transpose by FP64
 //                 atomic scatter, velocity sensitivity through X and X*)
 //   k_ic_adj    : projections onto the Gaussian initial-condition basis
-// Parameter sums use deterministic block partials + last-block totals.
+// Parameter sums use deterministic block partials totalled by a one-block kernel.
 #include <cmath>
 
 #include "adjoint.hpp"
@@ -21,11 +21,11 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// Block partials + last block: adds the grid totals of v[] to gs->g[slot0 + k].
+// Block partials of v[] (plain stores); k_fin_grad, queued right after the
+// kernel, adds their fixed-order totals to gs->g[slot0 + k].
 template <int NV>
-__device__ void reduce_into(double (&v)[NV], double* part, GradScalars* gs, int slot0) {
+__device__ void store_grad_partials(double (&v)[NV], double* part) {
   __shared__ double sh[NV][4];
-  __shared__ int last;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -36,21 +36,20 @@ __device__ void reduce_into(double (&v)[NV], double* part, GradScalars* gs, int 
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) part[(long long)blockIdx.x * NV + k] = sh[k][0] + sh[k][1] + sh[k][2] + sh[k][3];
-    __threadfence();
-    last = (atomicAdd(&gs->counter, 1u) == gridDim.x - 1) ? 1 : 0;
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const volatile double* vp = part;
+}
+
+template <int NV>
+__global__ void __launch_bounds__(256) k_fin_grad(GradScalars* gs, const double* part, int nb, int slot0) {
+  __shared__ double sh[NV][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double t[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) t[k] = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) t[k] += vp[(long long)b * NV + k];
+    for (int k = 0; k < NV; ++k) t[k] += part[(long long)b * NV + k];
   }
-  __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const double s = wave_sum_d(t[k]);
@@ -60,7 +59,6 @@ __device__ void reduce_into(double (&v)[NV], double* part, GradScalars* gs, int 
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) gs->g[slot0 + k] += sh[k][0] + sh[k][1] + sh[k][2] + sh[k][3];
-    gs->counter = 0u;
   }
 }
 
@@ -185,7 +183,7 @@ __global__ void __launch_bounds__(256) k_coef_adj(CoefAdjArgs a) {
     const double la = fc.la_w * w + fc.la_g * g + fc.la_f * f + fc.la_t * tau;
     acc[0] += (mu * mb + la * lb) * a.inv_scale;
   }
-  reduce_into<1>(acc, a.partials, a.gs, 4);
+  store_grad_partials<1>(acc, a.partials);
 }
 
 // Step coefficients (S0) transposed: K = k_w w + k_g g + k_f f, rho_p = rho_w w + rho_g g.
@@ -203,7 +201,7 @@ __global__ void __launch_bounds__(256) k_s0_adj(S0AdjArgs a) {
     acc[2] += g0 * kb;
     acc[3] += f0 * kb;
   }
-  reduce_into<4>(acc, a.partials, a.gs, 0);
+  store_grad_partials<4>(acc, a.partials);
 }
 
 // Force b = zeta tanh(tau) G tau, tau = p + n, with b_bar_a = -y_a:
@@ -414,10 +412,14 @@ void launch_react_adj(const ReactAdjArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_react_adj, dim3(rblocks(a.V)), dim3(256), 0, st, a);
 }
 void launch_coef_adj(const CoefAdjArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_coef_adj, dim3(rblocks(a.V)), dim3(256), 0, st, a);
+  const int nb = rblocks(a.V);
+  hipLaunchKernelGGL(k_coef_adj, dim3(nb), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_fin_grad<1>, dim3(1), dim3(256), 0, st, a.gs, a.partials, nb, 4);
 }
 void launch_s0_adj(const S0AdjArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_s0_adj, dim3(rblocks(a.V)), dim3(256), 0, st, a);
+  const int nb = rblocks(a.V);
+  hipLaunchKernelGGL(k_s0_adj, dim3(nb), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_fin_grad<4>, dim3(1), dim3(256), 0, st, a.gs, a.partials, nb, 0);
 }
 void launch_force_adj(long long V, double zeta, const double* p, const double* n, const double* gtau,
                       const double* y, double* taub, double* W, hipStream_t st) {

@@ -11,8 +11,7 @@ namespace tumor {
 // Parameter-gradient accumulators: g[0] rho, g[1] k_w, g[2] k_g, g[3] k_f, g[4] lame_scale.
 struct GradScalars {
   double g[8];
-  uint32_t counter;
-  int32_t pad[3];
+  int32_t pad[4];
 };
 
 struct ReactAdjArgs {

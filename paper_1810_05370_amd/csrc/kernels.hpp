@@ -25,17 +25,15 @@ struct SolveScalars {
   int32_t done;   // 1: no further iteration (converged, limit, breakdown)
   int32_t conv;   // 1: converged
   int32_t bad;    // 1: non-finite or non-positive curvature encountered
-  uint32_t counter;  // last-block counter of the reductions
-  int32_t pad[3];
+  int32_t pad[4];
 };
 
 // Voxel means of the coefficient fields and species masses.
 struct CoefScalars {
   double Kbar, mubar, lambar, etabar;
   double mass[8];
-  uint32_t counter;
   int32_t bad;
-  int32_t pad[2];
+  int32_t pad[3];
   // Written by the transport (reset before it): bits of non-negative doubles,
   // which order like unsigned integers, so blocks combine them by atomic max.
   unsigned long long cfl_bits;      // max |dt v| / h

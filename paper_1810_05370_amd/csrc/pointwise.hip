@@ -1,10 +1,10 @@
 // Pointwise, semi-Lagrangian and Krylov-vector kernels for gfx950.
 //
 // Reductions are deterministic: each block writes one partial per quantity,
-// the last block to finish (detected with a device-scope counter) sums the
-// partials in a fixed order and publishes the result to device scalars that
-// later kernels and the host read.  The grid size of a reduction kernel is a
-// fixed function of the problem size, so results do not depend on timing.
+// and a one-block kernel queued right after sums the partials in a fixed order
+// and publishes the result to device scalars that later kernels and the host
+// read.  The grid size of a reduction kernel is a fixed function of the
+// problem size, so results do not depend on timing.
 #include <algorithm>
 #include <cmath>
 
@@ -18,62 +18,6 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
-}
-
-// Block-reduce v[], store this block's partials, return true in the last block.
-template <int NV>
-__device__ bool block_partials(double (&v)[NV], double* part, uint32_t* counter) {
-  __shared__ double sh[NV][kRedThreads / 64];
-  __shared__ int last;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const double s = wave_sum(v[i]);
-    if (lane == 0) sh[i][wv] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double s = 0.0;
-      for (int w = 0; w < kRedThreads / 64; ++w) s += sh[i][w];
-      part[(long long)blockIdx.x * kPartialsPerBlock + i] = s;
-    }
-    __threadfence();
-    const uint32_t prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  return last != 0;
-}
-
-// Called by every thread of the last block: fixed-order total of all partials.
-template <int NV>
-__device__ void final_sums(double (&tot)[NV], const double* part, uint32_t* counter) {
-  __threadfence();
-  __shared__ double sh[NV][kRedThreads / 64];
-  double v[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = 0.0;
-  const volatile double* vp = part;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] += vp[(long long)b * kPartialsPerBlock + i];
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const double s = wave_sum(v[i]);
-    if (lane == 0) sh[i][wv] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double s = 0.0;
-    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[i][w];
-    tot[i] = s;
-  }
-  if (threadIdx.x == 0) *counter = 0u;
 }
 
 // Block-reduce v[] and store this block's partials (plain stores, no fence):
@@ -197,27 +141,62 @@ __global__ void __launch_bounds__(kRedThreads) k_react(ReactArgs a) {
     acc[4] += p; acc[5] += i; acc[6] += n; acc[7] += o; acc[8] += l; acc[9] += g; acc[10] += w;
     acc[11] += f;
   }
-  if (block_partials<12>(acc, a.partials, &a.cs->counter)) {
-    double tot[12];
-    final_sums<12>(tot, a.partials, &a.cs->counter);
-    if (threadIdx.x == 0) {
-      const double iv = 1.0 / (double)a.V;
-      a.cs->Kbar = tot[0] * iv;
-      a.cs->mubar = tot[1] * iv;
-      a.cs->lambar = tot[2] * iv;
-      a.cs->etabar = tot[3] * iv;
-      int bad = 0;
-      for (int k = 0; k < 8; ++k) {
-        a.cs->mass[k] = tot[4 + k];
-        if (!isfinite(tot[4 + k])) bad = 1;
-      }
-      a.cs->bad = bad;
+  block_store_partials<12>(acc, a.partials);
+}
+
+// ------------------------------------------------- one-block finishing kernels
+// Each totals the block partials of the kernel queued just before it (fixed
+// order) and publishes the scalars.
+__global__ void __launch_bounds__(kRedThreads) k_fin_react(CoefScalars* cs, const double* part, int nb, long long V) {
+  double tot[12];
+  total_partials<12>(tot, part, nb, kPartialsPerBlock);
+  if (threadIdx.x == 0) {
+    const double iv = 1.0 / (double)V;
+    cs->Kbar = tot[0] * iv;
+    cs->mubar = tot[1] * iv;
+    cs->lambar = tot[2] * iv;
+    cs->etabar = tot[3] * iv;
+    int bad = 0;
+    for (int k = 0; k < 8; ++k) {
+      cs->mass[k] = tot[4 + k];
+      if (!isfinite(tot[4 + k])) bad = 1;
     }
+    cs->bad = bad;
+  }
+}
+
+// ||b||^2 and ||r||^2 of a fresh residual; resets the solve state.
+__global__ void __launch_bounds__(kRedThreads) k_fin_resid(SolveScalars* sv, const double* part, int nb) {
+  double tot[2];
+  total_partials<2>(tot, part, nb, kPartialsPerBlock);
+  if (threadIdx.x == 0) {
+    sv->bb = tot[0];
+    sv->rr = tot[1];
+    sv->it = 0;
+    sv->done = 0;
+    sv->conv = 0;
+    sv->bad = (isfinite(tot[0]) && isfinite(tot[1])) ? 0 : 1;
+  }
+}
+
+// rho = <r, M^-1 r> at the start of a PCG solve.
+__global__ void __launch_bounds__(kRedThreads) k_fin_start(SolveScalars* sv, const double* part, int nb) {
+  double tot[1];
+  total_partials<1>(tot, part, nb, kPartialsPerBlock);
+  if (threadIdx.x == 0) {
+    sv->rho = tot[0];
+    sv->it = 0;
+    sv->conv = 0;
+    const bool ok = isfinite(tot[0]) && tot[0] > 0.0;
+    sv->bad = ok ? 0 : 1;
+    sv->done = ok ? 0 : 1;
   }
 }
 
 void launch_react(const ReactArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_react, dim3(red_blocks(a.V)), dim3(kRedThreads), 0, st, a);
+  const int nb = red_blocks(a.V);
+  hipLaunchKernelGGL(k_react, dim3(nb), dim3(kRedThreads), 0, st, a);
+  hipLaunchKernelGGL(k_fin_react, dim3(1), dim3(kRedThreads), 0, st, a.cs, a.partials, nb, a.V);
 }
 
 // ------------------------------------------------------- initial condition
@@ -585,18 +564,7 @@ __global__ void __launch_bounds__(kRedThreads) k_residual(KrylovArgs a, SpecIdx 
       acc[1] += wdot(rv, rv, kx);
     }
   }
-  if (block_partials<2>(acc, a.partials, &a.sv->counter)) {
-    double tot[2];
-    final_sums<2>(tot, a.partials, &a.sv->counter);
-    if (threadIdx.x == 0) {
-      a.sv->bb = tot[0];
-      a.sv->rr = tot[1];
-      a.sv->it = 0;
-      a.sv->done = 0;
-      a.sv->conv = 0;
-      a.sv->bad = (isfinite(tot[0]) && isfinite(tot[1])) ? 0 : 1;
-    }
-  }
+  block_store_partials<2>(acc, a.partials);
 }
 
 // Crank-Nicolson start: x0 = c, b = c + h Dc, r = b - (c - h Dc).
@@ -621,18 +589,7 @@ __global__ void __launch_bounds__(kRedThreads) k_cn_residual(KrylovArgs a, SpecI
     acc[0] += wdot(bv, bv, kx);
     acc[1] += wdot(rv, rv, kx);
   }
-  if (block_partials<2>(acc, a.partials, &a.sv->counter)) {
-    double tot[2];
-    final_sums<2>(tot, a.partials, &a.sv->counter);
-    if (threadIdx.x == 0) {
-      a.sv->bb = tot[0];
-      a.sv->rr = tot[1];
-      a.sv->it = 0;
-      a.sv->done = 0;
-      a.sv->conv = 0;
-      a.sv->bad = (isfinite(tot[0]) && isfinite(tot[1])) ? 0 : 1;
-    }
-  }
+  block_store_partials<2>(acc, a.partials);
 }
 
 template <typename R, int NC>
@@ -657,18 +614,7 @@ __global__ void __launch_bounds__(kRedThreads) k_pcg_start(KrylovArgs a, SpecIdx
       acc[0] += wdot(rv[c], zv[c], kx);
     }
   }
-  if (block_partials<1>(acc, a.partials, &a.sv->counter)) {
-    double tot[1];
-    final_sums<1>(tot, a.partials, &a.sv->counter);
-    if (threadIdx.x == 0) {
-      a.sv->rho = tot[0];
-      a.sv->it = 0;
-      a.sv->conv = 0;
-      const bool ok = isfinite(tot[0]) && tot[0] > 0.0;
-      a.sv->bad = ok ? 0 : 1;
-      a.sv->done = ok ? 0 : 1;
-    }
-  }
+  block_store_partials<1>(acc, a.partials);
 }
 
 template <typename R, int NC>
@@ -814,23 +760,28 @@ static inline long long spec_count(int n) { return (long long)n * n * (n / 2); }
 template <typename R>
 void launch_residual(const KrylovArgs& a, void* r32, hipStream_t st) {
   const SpecIdx ix = make_idx(a.n);
-  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_residual<R, NCC>), dim3(red_blocks(spec_count(a.n))),
-                                                 dim3(kRedThreads), 0, st, a, ix,
+  const int nb = red_blocks(spec_count(a.n));
+  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_residual<R, NCC>), dim3(nb), dim3(kRedThreads), 0, st, a, ix,
                                                  static_cast<cplx<float>*>(r32)));
+  hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kRedThreads), 0, st, a.sv, a.partials, nb);
 }
 
 template <typename R>
 void launch_cn_residual(const KrylovArgs& a, const void* c, const void* dc, hipStream_t st) {
   const SpecIdx ix = make_idx(a.n);
-  hipLaunchKernelGGL((k_cn_residual<R>), dim3(red_blocks(spec_count(a.n))), dim3(kRedThreads), 0, st, a, ix,
+  const int nb = red_blocks(spec_count(a.n));
+  hipLaunchKernelGGL((k_cn_residual<R>), dim3(nb), dim3(kRedThreads), 0, st, a, ix,
                      static_cast<const cplx<R>*>(c), static_cast<const cplx<R>*>(dc));
+  hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kRedThreads), 0, st, a.sv, a.partials, nb);
 }
 
 template <typename R>
 void launch_pcg_start(const KrylovArgs& a, int zero_x, hipStream_t st) {
   const SpecIdx ix = make_idx(a.n);
-  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_start<R, NCC>), dim3(red_blocks(spec_count(a.n))),
-                                                 dim3(kRedThreads), 0, st, a, ix, zero_x));
+  const int nb = red_blocks(spec_count(a.n));
+  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_start<R, NCC>), dim3(nb), dim3(kRedThreads), 0, st, a, ix,
+                                                 zero_x));
+  hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kRedThreads), 0, st, a.sv, a.partials, nb);
 }
 
 template <typename R>
