@@ -924,10 +924,10 @@ void transport(Ctx& c, double* const (&outs)[6]) {
   s.n_grid = c.n;
   s.dt = c.cfg.dt;
   s.s = c.cfg.dt / (2.0 * M_PI / c.n);
-  // FP32: scan 6 + pack 10 FP64 reads, 12 FP32 writes; gather 4 FP64 + 12 FP32
-  // reads, 6 FP64 writes.  FP64: CFL 3 reads; gather 10 reads, 6 writes.
+  // pack: 10 FP64 reads, 12 RC writes; gather: 4 FP64 + 12 RC reads, 6 FP64
+  // writes; FP32 adds the scan for the scales (6 FP64 reads).
   HIPCHECK(hipMemsetAsync(&c.cs->cfl_bits, 0, 7 * sizeof(unsigned long long), c.st));  // cfl + qmax[6]
-  timed(c, TUMOR_K_SL, (c.mixed ? 26.0 * 8.0 + 24.0 * 4.0 : 19.0 * 8.0) * c.V, [&] {
+  timed(c, TUMOR_K_SL, (c.mixed ? 26.0 * 8.0 + 24.0 * 4.0 : 44.0 * 8.0) * c.V, [&] {
     if (c.mixed) tumor::launch_sl<float>(s, c.p64.A[0], c.cs, c.st);
     else tumor::launch_sl<double>(s, c.p64.A[0], c.cs, c.st);
   });

@@ -126,8 +126,20 @@ struct LdsView {
   __device__ __forceinline__ cplx<R> get(int pos) const { return buf[addr(pos)]; }
 };
 
-template <typename R, int L, bool INV, int TWS, int r, int p, bool LAST>
-__device__ __forceinline__ void fft_stage(cplx<R> (&v)[8], const LdsView<R>& lds, int t,
+// LDS view of one row transform (16 or fewer lanes per row): element `pos`
+// lives at buf[pos + pos/8].  (A bijective XOR swizzle of each 16-element
+// block halves the measured bank conflicts of FP32 rows but costs registers
+// and no time: the row kernels wait on global memory, not on LDS.)
+template <typename R>
+struct LdsRowView {
+  cplx<R>* buf;
+  __device__ __forceinline__ int addr(int pos) const { return pos + (pos >> 3); }
+  __device__ __forceinline__ void put(int pos, cplx<R> v) const { buf[addr(pos)] = v; }
+  __device__ __forceinline__ cplx<R> get(int pos) const { return buf[addr(pos)]; }
+};
+
+template <typename R, int L, bool INV, int TWS, int r, int p, bool LAST, typename View>
+__device__ __forceinline__ void fft_stage(cplx<R> (&v)[8], const View& lds, int t,
                                           const cplx<R>* __restrict__ tw) {
   constexpr int TP = L / 8;
   constexpr int NB = 8 / r;
@@ -163,8 +175,8 @@ __device__ __forceinline__ void fft_stage(cplx<R> (&v)[8], const LdsView<R>& lds
 
 // In-place transform of the 8 register elements (positions t + TP*j).
 // All threads of the block must call it (it synchronises the block).
-template <typename R, int L, bool INV, int TWS>
-__device__ __forceinline__ void fft_block(cplx<R> (&v)[8], const LdsView<R>& lds, int t,
+template <typename R, int L, bool INV, int TWS, typename View>
+__device__ __forceinline__ void fft_block(cplx<R> (&v)[8], const View& lds, int t,
                                           const cplx<R>* __restrict__ tw) {
   dft8<R, INV>(v);
   if constexpr (Radix<L>::S > 1) {

@@ -244,7 +244,7 @@ __device__ __forceinline__ cplx<R> c2r_pre(cplx<R> A, cplx<R> B, int k, const cp
 
 // Packed R2C of the row held as v[j] = (x[2p], x[2p+1]), p = t + TP*j.
 template <typename R, int N>
-__device__ __forceinline__ void row_r2c(cplx<R> (&v)[8], const LdsView<R>& lds, int t,
+__device__ __forceinline__ void row_r2c(cplx<R> (&v)[8], const LdsRowView<R>& lds, int t,
                                         const cplx<R>* __restrict__ tw) {
   constexpr int L = N / 2, TP = L / 8;
   fft_block<R, L, false, 2>(v, lds, t, tw);
@@ -274,7 +274,7 @@ __device__ __forceinline__ void row_r2c(cplx<R> (&v)[8], const LdsView<R>& lds, 
 template <typename R, int N>
 __device__ __forceinline__ void row_c2r_terms(cplx<R> (&v)[8], int nt, const ColTerm* terms,
                                               const void* const* in, long long rowoff,
-                                              const LdsView<R>& lds, int t,
+                                              const LdsRowView<R>& lds, int t,
                                               const cplx<R>* __restrict__ tw) {
   constexpr int L = N / 2, TP = L / 8;
 #pragma unroll
@@ -304,7 +304,7 @@ __device__ __forceinline__ void row_c2r_terms(cplx<R> (&v)[8], int nt, const Col
 // Single-input C2R with an optional x-derivative and an optional added input.
 template <typename R, int N>
 __device__ __forceinline__ void row_c2r(cplx<R> (&v)[8], const cplx<R>* __restrict__ a, bool iw_a,
-                                        const cplx<R>* __restrict__ b, const LdsView<R>& lds, int t,
+                                        const cplx<R>* __restrict__ b, const LdsRowView<R>& lds, int t,
                                         const cplx<R>* __restrict__ tw) {
   constexpr int L = N / 2, TP = L / 8;
 #pragma unroll
@@ -350,7 +350,7 @@ __device__ __forceinline__ cplx<R> iwx(cplx<R> a, int k) {
   const int t = threadIdx.x % TP;                                    \
   const int rl = threadIdx.x / TP;                                   \
   const long long row = (long long)blockIdx.x * RC::RW + rl;         \
-  const LdsView<R> lds{sbuf + rl * LPR, 1, 1};                      \
+  const LdsRowView<R> lds{sbuf + rl * LPR};                         \
   const long long soff = row * L;                                    \
   const long long poff = row * N;                                    \
   (void)soff;                                                        \

@@ -321,7 +321,7 @@ __device__ __forceinline__ void block_max_cfl(double c, CoefScalars* cs) {
 // Node-interleaved copies of the gathered fields (the interpolation type RC):
 //   v4[node] = (v_x, v_y, v_z, 0)                       gathered at X*
 //   q8[node] = (s_p p, s_i i, s_n n, s_g g, s_w w, s_f f, div v, 0)   at X
-// with s_q the power-of-two scale of max |q| (used for FP32 only).
+// with s_q = 1 in FP64 and the power-of-two scale of max |q| in FP32.
 // Scaling by a power of two and rounding commute, and the interpolation and
 // the Heun update are linear in q, so the packed copies change no result
 // while FP32 values stay in range; fields far below it (the necrotic cells
@@ -351,12 +351,6 @@ __global__ void __launch_bounds__(256) k_sl_pack(SLArgs a, RC* __restrict__ v4, 
   block_max_cfl(a.s * sqrt(vx * vx + vy * vy + vz * vz), cs);
 }
 
-// FP64 transport: only the CFL number (the gather reads the fields in place).
-__global__ void __launch_bounds__(256) k_sl_cfl(SLArgs a, CoefScalars* cs) {
-  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;  // the grid covers V exactly
-  const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v];
-  block_max_cfl(a.s * sqrt(vx * vx + vy * vy + vz * vz), cs);
-}
 
 // W consecutive RC values of one stencil node (16-byte vector loads; q is
 // 16-byte aligned because W * sizeof(RC) is a multiple of 16).
@@ -412,50 +406,39 @@ __device__ __forceinline__ void interp_packed(const RC* __restrict__ q, double j
 // values at X, and Heun's method for the conservative source
 // g(nu, x) = -nu div v(x) of p, i, n, g, w; f is transported without source.
 //
-// One block per 16 x 4 x 4 brick of voxels (x fastest).  Blocks are handed
-// to the eight XCDs in turn, so block b is mapped to brick
-// (b mod 8) * (bricks / 8) + b / 8: each XCD sweeps one contiguous z slab,
-// and consecutive bricks of a slab form 256 x 16 x 16 groups (x, then 4
-// bricks in z, then y), so that the stencils of the bricks an XCD runs at
-// once overlap in its L2.
-template <typename RC>
+// One block per BX x BY x BZ brick of voxels (x fastest, 256 voxels).
+// Blocks are handed to the eight XCDs in turn, so block b is mapped to
+// brick (b mod 8) * (bricks / 8) + b / 8: each XCD sweeps one contiguous z
+// slab, and consecutive bricks of a slab form groups of 4 bricks in z (x,
+// then z, then y), so that the stencils of the bricks an XCD runs at once
+// overlap in its L2 (XCD_SLABS; otherwise bricks follow the block index).
+template <typename RC, int BX, int BY, int BZ, bool XCD_SLABS>
 __global__ void __launch_bounds__(256) k_sl_gather(SLArgs a, const RC* __restrict__ v4, const RC* __restrict__ q8,
                                                    const CoefScalars* cs) {
+  static_assert(BX * BY * BZ == 256, "one voxel per thread");
   const int n = a.n_grid;
   const unsigned nb = gridDim.x;
-  const unsigned id = (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3);
-  const unsigned nbx = (unsigned)n >> 4, nby = (unsigned)n >> 2;
+  const unsigned id = XCD_SLABS ? (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+  const unsigned nbx = (unsigned)n / BX, nby = (unsigned)n / BY;
   const unsigned bx = id % nbx;
   unsigned r = id / nbx;
   const unsigned zl = r & 3u;
   r >>= 2;
   const unsigned by = r % nby, zg = r / nby;
   const int t = threadIdx.x;
-  const int jx = (int)(bx * 16) + (t & 15);
-  const int jy = (int)(by * 4) + ((t >> 4) & 3);
-  const int jz = (int)((zg * 4 + zl) * 4) + (t >> 6);
+  const int jx = (int)(bx * BX) + (t % BX);
+  const int jy = (int)(by * BY) + ((t / BX) % BY);
+  const int jz = (int)((zg * 4 + zl) * BZ) + (t / (BX * BY));
   const long long v = ((long long)jz * n + jy) * n + jx;
   const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v];
   const double s = a.s;
   RC vs[3];
   RC qx[7];
-  if constexpr (sizeof(RC) == sizeof(double)) {
-    // FP64: the fields are gathered where they are (a packed copy would only
-    // add its padding to the bytes every stencil node moves).
-    const double* const vel[3] = {a.vx, a.vy, a.vz};
-    interp_pt<RC, 3>(vel, jx - s * vx, jy - s * vy, jz - s * vz, n, vs);
-  } else {
-    interp_packed<RC, 4, 3>(v4, jx - s * vx, jy - s * vy, jz - s * vz, n, vs);
-  }
+  interp_packed<RC, 4, 3>(v4, jx - s * vx, jy - s * vy, jz - s * vz, n, vs);
   const double Xx = jx - 0.5 * s * (vx + (double)vs[0]);
   const double Xy = jy - 0.5 * s * (vy + (double)vs[1]);
   const double Xz = jz - 0.5 * s * (vz + (double)vs[2]);
-  if constexpr (sizeof(RC) == sizeof(double)) {
-    const double* const fl[7] = {a.p, a.i, a.n, a.g, a.w, a.f, a.div};
-    interp_pt<RC, 7>(fl, Xx, Xy, Xz, n, qx);
-  } else {
-    interp_packed<RC, 8, 7>(q8, Xx, Xy, Xz, n, qx);
-  }
+  interp_packed<RC, 8, 7>(q8, Xx, Xy, Xz, n, qx);
   const RC dt = RC(a.dt);
   const RC dX = qx[6];
   const RC d0 = RC(a.div[v]);
@@ -477,8 +460,8 @@ __global__ void __launch_bounds__(256) k_sl_gather(SLArgs a, const RC* __restric
 }
 
 // n is a power of two >= 16 (checked at init): V = n^3 is a multiple of 256,
-// the number of bricks n^3 / 256 is a multiple of 8, and n / 4 (bricks
-// along z) a multiple of 4, as k_sl_gather's brick map needs.
+// the number of bricks n^3 / 256 is a multiple of 8, and the bricks along z
+// (n / BZ) a multiple of 4, as k_sl_gather's brick map needs.
 template <typename RC>
 void launch_sl(const SLArgs& a, void* packed, CoefScalars* cs, hipStream_t st) {
   const long long V = (long long)a.n_grid * a.n_grid * a.n_grid;
@@ -487,11 +470,14 @@ void launch_sl(const SLArgs& a, void* packed, CoefScalars* cs, hipStream_t st) {
   if (sizeof(RC) != sizeof(double)) {
     const long long blocks = std::min<long long>(V / 256, 4096);
     hipLaunchKernelGGL(k_sl_scan, dim3((unsigned)blocks), dim3(256), 0, st, a, cs);
-    hipLaunchKernelGGL(k_sl_pack<RC>, dim3((unsigned)(V / 256)), dim3(256), 0, st, a, v4, q8, cs);
-  } else {
-    hipLaunchKernelGGL(k_sl_cfl, dim3((unsigned)(V / 256)), dim3(256), 0, st, a, cs);
   }
-  hipLaunchKernelGGL(k_sl_gather<RC>, dim3((unsigned)(V / 256)), dim3(256), 0, st, a, v4, q8, cs);
+  hipLaunchKernelGGL(k_sl_pack<RC>, dim3((unsigned)(V / 256)), dim3(256), 0, st, a, v4, q8, cs);
+  // 64-voxel rows per wave (measured best for both types at 256^3); grids
+  // below 64 use 16 x 4 x 4 bricks.
+  if (a.n_grid >= 64)
+    hipLaunchKernelGGL((k_sl_gather<RC, 64, 2, 2, true>), dim3((unsigned)(V / 256)), dim3(256), 0, st, a, v4, q8, cs);
+  else
+    hipLaunchKernelGGL((k_sl_gather<RC, 16, 4, 4, true>), dim3((unsigned)(V / 256)), dim3(256), 0, st, a, v4, q8, cs);
 }
 template void launch_sl<double>(const SLArgs&, void*, CoefScalars*, hipStream_t);
 template void launch_sl<float>(const SLArgs&, void*, CoefScalars*, hipStream_t);
