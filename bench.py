@@ -70,8 +70,18 @@ def run_form(tm, torch, inp, P, precision, steps, warmup):
     dom = sim.kernel_timer_read(dominant)
     log(f"[{precision}] {steps} steps: wall {wall:.3f} s, events {gpu_ms / 1e3:.3f} s;"
         f" dominant {dominant}: {dom['launches']} launches, {dom['ms']:.1f} ms")
+    # mass-effect diagnostics (scalars) of the final displacement
+    sim.diagnose(0.1)                                    # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        diag = sim.diagnose(0.1)
+    torch.cuda.synchronize()
+    diag_ms = (time.perf_counter() - t0) / reps * 1e3
     sim.close()
-    return dict(wall=wall, gpu_ms=gpu_ms, stats=stats, warm_profile=prof, dominant=dominant, dom=dom)
+    return dict(wall=wall, gpu_ms=gpu_ms, stats=stats, warm_profile=prof, dominant=dominant, dom=dom,
+                diag=diag, diag_ms=diag_ms)
 
 
 def run_adjoint(tm, torch, inp, P, precision, steps, warmup, ckpt):
@@ -345,6 +355,8 @@ def main():
     extra["diffusion_iterations_last_step"] = main_run["stats"][-1]["it_diff"]
     extra["warmup_kernel_ms"] = {c: round(v["ms"], 2) for c, v in main_run["warm_profile"].items() if v["ms"] > 0}
     extra["wall_s"] = round(main_run["wall"], 4)
+    extra["diagnostics"] = dict(ms=round(main_run["diag_ms"], 3), threshold_voxels=0.1,
+                                **{k: round(v, 6) for k, v in main_run["diag"].items()})
     rl = roofline(main_run["dom"], main_run["dominant"], n)
 
     if not args.no_adjoint:

@@ -172,6 +172,29 @@ int tumor_solve_elasticity(tumor_ctx* ctx, const double* force, double* u_out,
  * max |dt u_t^n| / h.  The state is unchanged. */
 int tumor_transport(tumor_ctx* ctx, double* out, double* max_cfl);
 
+/* Mass-effect diagnostics of the current displacement u^n (Sec. 3: stress by
+ * Hooke's law e:hook, principal stresses shown by the stress trace, maximum
+ * shear from Mohr's circle e:princ_stress, Jacobian e:jacobian; Sec. 4: the
+ * grid-search scalars).  With F_ab = G_b u_a (spectral derivatives) and the
+ * context's current Lame fields:
+ *   trace     = tr T,  T = lambda tr(F) I + mu (F + F^T)
+ *   shear     = sqrt(((T_xx - T_yy)/2)^2 + T_xy^2)   (x-y plane, as printed)
+ *   J         = det(I + F)
+ * fields: device, 3 N^3 values (trace, shear, J), or NULL for the scalars
+ * only.  threshold: displacement (voxels) whose contour defines d_max.
+ * Runs in FP64 in both precisions; the state is unchanged. */
+typedef struct {
+  double max_disp;             /* max |u| / h (voxels)                            */
+  double trace_min, trace_max; /* extremes of the stress trace                    */
+  double shear_max;            /* max of the Mohr shear stress                    */
+  double jac_min, jac_max;     /* extremes of J                                   */
+  double jac_l2;               /* sqrt(h^3 sum (J - 1)^2)                         */
+  double d_max;                /* max distance (voxels, periodic) from the nearest
+                                  initial seed of the points with |u| >= threshold
+                                  voxels; 0 without seeds or such points          */
+} tumor_diagnostics;
+int tumor_diagnose(tumor_ctx* ctx, double threshold, double* fields, tumor_diagnostics* out);
+
 /* Discrete adjoint (the exact transpose of the linearised split step, every
  * PCG solve taken as exact; the paper leaves adjoint-based inversion to
  * future work, Sec. 5).  Requires a context created with TUMOR_F_ADJOINT.

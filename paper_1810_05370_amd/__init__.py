@@ -62,6 +62,12 @@ class TumorConfig(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 4)]
 
 
+class TumorDiagnostics(ctypes.Structure):
+    _fields_ = [("max_disp", ctypes.c_double), ("trace_min", ctypes.c_double), ("trace_max", ctypes.c_double),
+                ("shear_max", ctypes.c_double), ("jac_min", ctypes.c_double), ("jac_max", ctypes.c_double),
+                ("jac_l2", ctypes.c_double), ("d_max", ctypes.c_double)]
+
+
 class TumorStepStats(ctypes.Structure):
     _fields_ = [("it_diff", ctypes.c_int32 * 3), ("it_elast", ctypes.c_int32),
                 ("outer_elast", ctypes.c_int32), ("outer_diff", ctypes.c_int32 * 3),
@@ -104,6 +110,7 @@ def load_library(path: Optional[str] = None):
         "tumor_solve_elasticity": (ctypes.c_int, [P, P, P, ctypes.POINTER(ctypes.c_int32),
                                                   ctypes.POINTER(ctypes.c_double)]),
         "tumor_transport": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_double)]),
+        "tumor_diagnose": (ctypes.c_int, [P, ctypes.c_double, P, ctypes.POINTER(TumorDiagnostics)]),
         "tumor_adjoint_step": (ctypes.c_int, [P, P, P]),
         "tumor_tape_bytes": (ctypes.c_int, [ctypes.POINTER(TumorConfig), ctypes.c_int32, ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_size_t)]),
@@ -257,6 +264,18 @@ class Tumor:
         cfl = ctypes.c_double(0)
         _check(self.lib.tumor_transport(self.ctx, _ptr(out), ctypes.byref(cfl)))
         return out, cfl.value
+
+    def diagnose(self, threshold=0.1, fields=False):
+        """Mass-effect diagnostics of the current displacement: a dict of the
+        scalars, plus a (3, N, N, N) tensor (stress trace, Mohr shear,
+        Jacobian) when fields is true."""
+        torch = self._torch
+        n = self.n
+        out = TumorDiagnostics()
+        f = torch.empty((3, n, n, n), dtype=torch.float64, device=self.device) if fields else None
+        _check(self.lib.tumor_diagnose(self.ctx, float(threshold), _ptr(f) if fields else None, ctypes.byref(out)))
+        d = {k: getattr(out, k) for k, _ in TumorDiagnostics._fields_}
+        return (d, f) if fields else d
 
     def get(self, name):
         torch = self._torch

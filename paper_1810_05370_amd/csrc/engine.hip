@@ -1552,6 +1552,96 @@ int tumor_transport(tumor_ctx* ctx, double* out, double* max_cfl) {
   });
 }
 
+int tumor_diagnose(tumor_ctx* ctx, double threshold, double* fields, tumor_diagnostics* out) {
+  if (!ctx) return einval("ctx is NULL");
+  if (!out) return einval("out is NULL");
+  if (!(threshold >= 0.0) || !std::isfinite(threshold)) return einval("threshold must be finite and >= 0");
+  return guarded([&]() -> int {
+    Ctx& c = *ctx;
+    PrecBufs<double>& P = c.p64;
+    auto** A = P.A;
+    auto** B = P.B;
+    const long long S = c.S;
+    // u_a and F_ab = G_b u_a in physical space (FP64 in both precisions).
+    // Scratch: the pass buffers, the post-transport species G and the velocity
+    // buffers, none of which carries state between calls.
+    colp<double>(c, 2, true,
+                 Prog()
+                     .in(0, c.U)
+                     .in(1, c.U + S)
+                     .in(2, c.U + 2 * S)
+                     .out(A[0], {T1(0)})
+                     .out(A[1], {T1(1)})
+                     .out(A[2], {T1(2)})
+                     .out(A[3], {TW(0)})
+                     .out(A[4], {TW(1)})
+                     .out(A[5], {TW(2)}));
+    colp<double>(c, 1, true,
+                 Prog()
+                     .in(0, A[0])
+                     .in(1, A[1])
+                     .in(2, A[2])
+                     .in(3, A[3])
+                     .in(4, A[4])
+                     .out(B[0], {T1(0)})
+                     .out(B[1], {T1(1)})
+                     .out(B[2], {T1(2)})
+                     .out(B[3], {TW(0)})
+                     .out(B[4], {TW(1)})
+                     .out(B[5], {TW(2)})
+                     .out(B[6], {T1(3)})
+                     .out(B[7], {T1(4)}));
+    colp<double>(c, 1, true, Prog().in(0, A[5]).out(A[0], {T1(0)}));
+    double* ph[12] = {c.G[0], c.G[1], c.G[2], c.G[3], c.G[4], c.G[5], c.G[6], c.G[7],
+                      c.vel[0], c.vel[1], c.vel[2], c.vel[3]};
+    Prog x1;
+    for (int k = 0; k < 6; ++k) x1.in(k, B[k]);
+    x1.out(ph[0], {T1(0)}).out(ph[1], {T1(1)}).out(ph[2], {T1(2)});
+    x1.out(ph[3], {TW(0)}).out(ph[4], {TW(1)}).out(ph[5], {TW(2)});
+    x1.out(ph[6], {T1(3)}).out(ph[7], {T1(4)});
+    Prog x2;
+    x2.in(0, B[5]).in(1, B[6]).in(2, B[7]).in(3, A[0]);
+    x2.out(ph[8], {T1(0)}).out(ph[9], {T1(1)}).out(ph[10], {T1(2)}).out(ph[11], {T1(3)});
+    const double inv = 1.0 / (double)c.V;
+    tumor::launch_xinv<double>(c.n, to_x(x1.p, inv), P.tw, c.st);
+    tumor::launch_xinv<double>(c.n, to_x(x2.p, inv), P.tw, c.st);
+    tumor::DiagArgs d;
+    std::memset(&d, 0, sizeof(d));
+    for (int k = 0; k < 12; ++k) d.f[k] = ph[k];
+    d.mu = c.mu;
+    d.lam = c.lam;
+    double* icd = reinterpret_cast<double*>(A[6]);
+    double* res = reinterpret_cast<double*>(A[7]);
+    if (c.n_ic > 0)
+      HIPCHECK(hipMemcpyAsync(icd, c.ic_host, 5 * (size_t)c.n_ic * sizeof(double), hipMemcpyHostToDevice, c.st));
+    d.ic = icd;
+    d.n_ic = c.n_ic;
+    d.n = c.n;
+    d.h = 2.0 * M_PI / c.n;
+    d.thr = threshold;
+    if (fields) {
+      d.trace = fields;
+      d.shear = fields + c.V;
+      d.jac = fields + 2 * c.V;
+    }
+    d.partials = c.partials;
+    tumor::launch_diag(d, res, c.st);
+    HIPCHECK(hipGetLastError());
+    double r[8];
+    HIPCHECK(hipMemcpyAsync(r, res, sizeof(r), hipMemcpyDeviceToHost, c.st));
+    HIPCHECK(hipStreamSynchronize(c.st));
+    out->max_disp = r[0];
+    out->trace_min = r[1];
+    out->trace_max = r[2];
+    out->shear_max = r[3];
+    out->jac_min = r[4];
+    out->jac_max = r[5];
+    out->jac_l2 = r[6];
+    out->d_max = r[7];
+    return TUMOR_OK;
+  });
+}
+
 int tumor_get_field(tumor_ctx* ctx, int32_t id, double* dst) {
   if (!ctx) return einval("ctx is NULL");
   if (!dst) return einval("dst is NULL");

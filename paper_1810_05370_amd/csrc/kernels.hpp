@@ -143,6 +143,24 @@ void launch_pcg_pupdate(const KrylovArgs& a, hipStream_t st);
 template <typename R>
 void launch_precond(const KrylovArgs& a, const void* in, void* out, hipStream_t st);
 // x64 += x32 over ncomp blocks
+// Mass-effect diagnostics of a displacement (Sec. 3, e:hook, e:princ_stress,
+// e:jacobian; Sec. 4 grid search).  f[3a + b'] are physical fields: f[0..2]
+// = u_a, then F_ab = G_b u_a stored at f[3 + 3b + a] (derivative b of u_a).
+struct DiagArgs {
+  const double* f[12];
+  const double *mu, *lam;
+  const double* ic;  // n_ic x (cx, cy, cz, sigma, weight), device
+  int n_ic;
+  int n;
+  double h;
+  double thr;        // displacement threshold, voxels
+  double *trace, *shear, *jac;  // nullable outputs
+  double* partials;
+};
+// results[8] = max |u|/h, min tr T, max tr T, max tau, min J, max J,
+// sqrt(h^3 sum (J-1)^2), d_max (voxels; 0 without seeds or displacement)
+void launch_diag(const DiagArgs& a, double* results, hipStream_t st);
+
 // alpha = rho / sum of nb partials of <p, q> (stride apart); nothing once done.
 void launch_fin_alpha(SolveScalars* sv, const double* part, int nb, int stride, hipStream_t st);
 

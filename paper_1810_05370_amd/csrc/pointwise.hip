@@ -193,6 +193,123 @@ __global__ void __launch_bounds__(kRedThreads) k_fin_start(SolveScalars* sv, con
   }
 }
 
+// ----------------------------------------------------------- diagnostics
+// Per-block slots: 0 max |u|^2 / h^2, 1 max(-tr T), 2 max tr T, 3 max tau,
+// 4 max(-J), 5 max J, 6 sum (J - 1)^2, 7 max squared seed distance of the
+// points displaced by >= thr voxels (-1: none).  Slot 6 sums, the others take
+// maxima.
+constexpr int kDiagSlots = 8;
+
+__device__ __forceinline__ double diag_combine(int k, double a, double b) { return k == 6 ? a + b : fmax(a, b); }
+
+__global__ void __launch_bounds__(kRedThreads) k_diag(DiagArgs a) {
+  const int n = a.n;
+  const long long V = (long long)n * n * n;
+  const double L = 2.0 * M_PI;
+  double acc[kDiagSlots];
+#pragma unroll
+  for (int k = 0; k < kDiagSlots; ++k) acc[k] = (k == 6) ? 0.0 : -INFINITY;
+  for (long long v = (long long)blockIdx.x * kRedThreads + threadIdx.x; v < V;
+       v += (long long)gridDim.x * kRedThreads) {
+    double F[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) F[i][j] = a.f[3 + 3 * j + i][v];
+    const double mu = a.mu[v], lam = a.lam[v];
+    const double tr = F[0][0] + F[1][1] + F[2][2];
+    const double Txx = mu * (F[0][0] + F[0][0]) + lam * tr;
+    const double Tyy = mu * (F[1][1] + F[1][1]) + lam * tr;
+    const double Tzz = mu * (F[2][2] + F[2][2]) + lam * tr;
+    const double Txy = mu * (F[0][1] + F[1][0]);
+    const double trace = Txx + Tyy + Tzz;
+    const double hx = 0.5 * (Txx - Tyy);
+    const double tau = sqrt(hx * hx + Txy * Txy);
+    const double a00 = F[0][0] + 1.0, a11 = F[1][1] + 1.0, a22 = F[2][2] + 1.0;
+    const double J = a00 * (a11 * a22 - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * a22 - F[1][2] * F[2][0]) +
+                     F[0][2] * (F[1][0] * F[2][1] - a11 * F[2][0]);
+    if (a.trace) a.trace[v] = trace;
+    if (a.shear) a.shear[v] = tau;
+    if (a.jac) a.jac[v] = J;
+    const double ux = a.f[0][v], uy = a.f[1][v], uz = a.f[2][v];
+    const double umag = sqrt(ux * ux + uy * uy + uz * uz) / a.h;
+    acc[0] = fmax(acc[0], umag);
+    acc[1] = fmax(acc[1], -trace);
+    acc[2] = fmax(acc[2], trace);
+    acc[3] = fmax(acc[3], tau);
+    acc[4] = fmax(acc[4], -J);
+    acc[5] = fmax(acc[5], J);
+    acc[6] += (J - 1.0) * (J - 1.0);
+    if (a.n_ic > 0 && umag >= a.thr) {
+      const int jx = (int)(v % n), jy = (int)((v / n) % n), jz = (int)(v / ((long long)n * n));
+      const double q[3] = {a.h * jx, a.h * jy, a.h * jz};
+      double best = INFINITY;
+      for (int k = 0; k < a.n_ic; ++k) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double d = q[c] - a.ic[5 * k + c];
+          d = d - L * rint(d / L);
+          d2 = d2 + d * d;
+        }
+        best = fmin(best, d2);
+      }
+      acc[7] = fmax(acc[7], best);
+    }
+  }
+  __shared__ double sh[kDiagSlots][kRedThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kDiagSlots; ++k) {
+    double t = acc[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t = diag_combine(k, t, __shfl_xor(t, off, 64));
+    if (lane == 0) sh[k][wv] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < kDiagSlots) {
+    const int k = threadIdx.x;
+    double t = sh[k][0];
+    for (int w = 1; w < kRedThreads / 64; ++w) t = diag_combine(k, t, sh[k][w]);
+    a.partials[(long long)blockIdx.x * kPartialsPerBlock + k] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_fin_diag(const double* part, int nb, double h, double* res) {
+  __shared__ double sh[kDiagSlots][kRedThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kDiagSlots; ++k) {
+    double t = (k == 6) ? 0.0 : -INFINITY;
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) t = diag_combine(k, t, part[(long long)b * kPartialsPerBlock + k]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t = diag_combine(k, t, __shfl_xor(t, off, 64));
+    if (lane == 0) sh[k][wv] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[kDiagSlots];
+    for (int k = 0; k < kDiagSlots; ++k) {
+      t[k] = sh[k][0];
+      for (int w = 1; w < kRedThreads / 64; ++w) t[k] = diag_combine(k, t[k], sh[k][w]);
+    }
+    res[0] = t[0];
+    res[1] = -t[1];
+    res[2] = t[2];
+    res[3] = t[3];
+    res[4] = -t[4];
+    res[5] = t[5];
+    res[6] = sqrt(h * h * h * t[6]);
+    res[7] = t[7] >= 0.0 ? sqrt(t[7]) / h : 0.0;
+  }
+}
+
+void launch_diag(const DiagArgs& a, double* results, hipStream_t st) {
+  const int nb = red_blocks((long long)a.n * a.n * a.n);
+  hipLaunchKernelGGL(k_diag, dim3(nb), dim3(kRedThreads), 0, st, a);
+  hipLaunchKernelGGL(k_fin_diag, dim3(1), dim3(kRedThreads), 0, st, a.partials, nb, a.h, results);
+}
+
 void launch_react(const ReactArgs& a, hipStream_t st) {
   const int nb = red_blocks(a.V);
   hipLaunchKernelGGL(k_react, dim3(nb), dim3(kRedThreads), 0, st, a);

@@ -48,6 +48,8 @@ int main(void) {
          offsetof(tumor_config, reserved), offsetof(tumor_params, heaviside_eps));
   printf("%zu %zu %zu\n", offsetof(tumor_step_stats, relres_diff), offsetof(tumor_step_stats, mass),
          offsetof(tumor_step_stats, max_cfl));
+  printf("%zu %zu %zu\n", sizeof(tumor_diagnostics), offsetof(tumor_diagnostics, jac_l2),
+         offsetof(tumor_diagnostics, d_max));
   return 0;
 }
 ''')
@@ -59,7 +61,8 @@ int main(void) {
     want = [c.sizeof(tm.TumorParams), c.sizeof(tm.TumorConfig), c.sizeof(tm.TumorStepStats),
             tm.TumorConfig.dt.offset, tm.TumorConfig.max_it.offset, tm.TumorConfig.reserved.offset,
             tm.TumorParams.heaviside_eps.offset, tm.TumorStepStats.relres_diff.offset,
-            tm.TumorStepStats.mass.offset, tm.TumorStepStats.max_cfl.offset]
+            tm.TumorStepStats.mass.offset, tm.TumorStepStats.max_cfl.offset,
+            c.sizeof(tm.TumorDiagnostics), tm.TumorDiagnostics.jac_l2.offset, tm.TumorDiagnostics.d_max.offset]
     assert got == want
 
 

@@ -180,3 +180,25 @@ def test_adjoint_gradient_matches_central_differences(precision):
         err = abs(grad[idx] - fd) / abs(fd)
         say(f"adjoint {precision} {name}: {grad[idx]:.9e} vs central difference {fd:.9e} (rel {err:.1e})")
         assert err < tol, name
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_mass_effect_diagnostics_element_by_element(inputs, precision):
+    from oracle import diagnostics as dg
+    sim, P = _warm_sim(inputs, precision)
+    s, f = sim.diagnose(0.1, fields=True)
+    f = f.cpu().numpy()
+    u = _host(sim, "u")
+    mu, lam = _host(sim, "mu"), _host(sim, "lambda")
+    sim.close()
+    g = Grid(N)
+    ref_f, ref_s = dg.diagnose(g, mu, lam, u, inputs["centers"], 0.1)
+    for k, name in enumerate(("trace", "shear", "jac")):
+        off = 1.0 if name == "jac" else 0.0
+        err = rel_l2(f[k] - off, ref_f[name] - off)
+        say(f"diagnostics {precision} {name}: relL2 {err:.2e}")
+        assert err < 1e-10, name
+    say(f"  scalars {s}")
+    for key in ("max_disp", "trace_min", "trace_max", "shear_max", "jac_l2"):
+        assert abs(s[key] - ref_s[key]) <= 1e-10 * abs(ref_s[key]), key
+    assert abs(s["d_max"] - ref_s["d_max"]) <= 1e-9 * max(1.0, ref_s["d_max"])
