@@ -23,11 +23,13 @@ using a 3D multispecies tumor model with mass effect" (arXiv 1810.05370):
 * ``adjoint``   -- the discrete adjoint of the split step (the paper lists
   adjoint-based inversion as future work in Sec. 5);
 * ``diagnostics`` -- stress trace, Mohr maximum shear, deformation Jacobian and
-  the grid-search scalars (Sec. 3, e:princ_stress, e:jacobian; Sec. 4).
+  the grid-search scalars (Sec. 3, e:princ_stress, e:jacobian; Sec. 4);
+* ``model_single`` -- the split step of the single-species model with mass
+  effect (Sec. 2.2, e:rd; Sec. 3).
 
 Parity status: every building block is pinned by closed forms, invariants or
 brute force in ``tests/test_oracle_*.py``.  The full coupled step has no
 worked example in the paper; beyond the pinned blocks and the invariants
 (mass balance, residual certificates) it is "parity unpinned".
 """
-from . import spectral, solvers, transport, reaction, model, diagnostics  # noqa: F401
+from . import spectral, solvers, transport, reaction, model, diagnostics, model_single  # noqa: F401

@@ -125,3 +125,27 @@ def elastic_force(grid, zeta, p, n):
     t = np.tanh(tau)
     g = grid.grad(tau)
     return np.stack([zeta * t * g[a] for a in range(3)])
+
+
+def single_species_reaction(P, dt, c_dag, c_dd, g, w, rho):
+    """Reaction sub-step of the single-species model (Sec. 2.2, e:rd; Sec. 3,
+    single-species splitting list).
+
+    The tumour grows logistically, R = rho c (1 - c) (e:reac_op), with the
+    growth rate rho = rho_w w + rho_g g frozen from the last refresh
+    (e:reaction_op), integrated exactly over dt as in the multispecies step.
+    Healthy tissue loses what the tumour gained in this step's diffusion and
+    reaction sub-steps, split by g / (g + w) (e:gm, e:wm), so that c + g + w
+    is conserved pointwise.
+
+    c_dag: tumour after transport; c_dd: after diffusion.  Returns (c', g', w').
+    """
+    dD = c_dd - c_dag
+    dR = logistic_flow(c_dd, rho, dt) - c_dd
+    c1 = c_dd + dR
+    s = dD + dR
+    gw = g + w
+    small = gw < 1e-12
+    phig = np.where(small, 0.5, g / np.where(small, 1.0, gw))
+    phiw = np.where(small, 0.5, w / np.where(small, 1.0, gw))
+    return c1, g - phig * s, w - phiw * s
