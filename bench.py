@@ -84,6 +84,25 @@ def run_form(tm, torch, inp, P, precision, steps, warmup):
                 diag=diag, diag_ms=diag_ms)
 
 
+def run_single(tm, torch, inp, P, precision, steps, warmup):
+    """Split steps/s of the single-species model on the same inputs."""
+    sim = tm.from_inputs(inp, P, precision=precision, model="single")
+    for _ in range(warmup):
+        sim.step(1)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(sim.stream)
+    its = [sim.step(1) for _ in range(steps)]
+    ev1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    sim.close()
+    log(f"[single {precision}] {steps} steps: {ms / steps:.1f} ms/step, elasticity it {[s['it_elast'] for s in its]}")
+    return dict(steps_per_s=round(steps / (ms / 1e3), 4), ms_per_step=round(ms / steps, 3),
+                elasticity_iterations=[s["it_elast"] for s in its], diffusion_iterations=[s["it_diff"][0] for s in its])
+
+
 def run_adjoint(tm, torch, inp, P, precision, steps, warmup, ckpt):
     """Forward + adjoint throughput: `steps` recorded steps then their reverse sweep."""
     import numpy as np
@@ -290,6 +309,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint form")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-species model")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel that calibrates "
                          "the HBM byte counters of a rocprofv3 --pmc run)")
@@ -358,6 +378,10 @@ def main():
     extra["diagnostics"] = dict(ms=round(main_run["diag_ms"], 3), threshold_voxels=0.1,
                                 **{k: round(v, 6) for k, v in main_run["diag"].items()})
     rl = roofline(main_run["dom"], main_run["dominant"], n)
+
+    if not args.no_single:
+        extra["single_species"] = {prec: run_single(tm, torch, inp, P, prec, args.steps, args.warmup)
+                                   for prec in (("mixed", "fp64") if not args.no_fp64 else ("mixed",))}
 
     if not args.no_adjoint:
         ainp = synthetic.workload_inputs(args.adjoint_workload)

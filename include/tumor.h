@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define TUMOR_ABI_VERSION 1
+#define TUMOR_ABI_VERSION 2
 
 typedef enum {
   TUMOR_OK = 0,
@@ -95,6 +95,19 @@ typedef struct {
   double heaviside_eps;
 } tumor_params;
 
+/* Tumour model (tumor_config.model).
+ *   MULTISPECIES: p, i, n, o, l, g, w, f (Sec. 2.3-2.4, Eq. e:gog, e:edema).
+ *   SINGLE: the reaction-diffusion model with mass effect (Sec. 2.2, Eq. e:rd):
+ *     one tumour density c (stored in the p field; i, n, l stay 0 and o stays
+ *     o_heal) that diffuses with K and grows as rho c (1 - c), rho = rho_w w +
+ *     rho_g g (e:reac_op, e:reaction_op); g and w lose the tumour's diffusion
+ *     and growth increments in proportion g : w (e:gm, e:wm); the force is
+ *     zeta tanh(c) grad c (e:force).  Split as in the single-species list of
+ *     Sec. 3: transport, CN diffusion of c, reaction, refresh, elasticity.
+ *     Parameters of the multispecies reaction (alpha0, ..., delta_l) are
+ *     unused; TUMOR_F_EDEMA has no effect and TUMOR_F_ADJOINT is rejected. */
+typedef enum { TUMOR_MODEL_MULTISPECIES = 0, TUMOR_MODEL_SINGLE = 1 } tumor_model;
+
 /* Numerical configuration (Table t:numparams: N, dt, Krylov tolerance). */
 typedef struct {
   int32_t n;            /* grid size per axis: a power of two in [16, 512]     */
@@ -104,7 +117,8 @@ typedef struct {
   double rtol_elast;    /* elasticity PCG relative tolerance, in (0, 1)          */
   int32_t max_it;       /* PCG iteration cap per solve (>= 1)                    */
   int32_t flags;        /* TUMOR_F_* (0 selects TUMOR_F_DEFAULT)                 */
-  int32_t reserved[4];  /* must be zero                                          */
+  int32_t model;        /* tumor_model                                           */
+  int32_t reserved[3];  /* must be zero                                          */
 } tumor_config;
 
 /* Statistics of the last step (or solve). */

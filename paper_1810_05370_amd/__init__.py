@@ -59,7 +59,7 @@ class TumorConfig(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("precision", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("rtol_diff", ctypes.c_double), ("rtol_elast", ctypes.c_double),
                 ("max_it", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("model", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class TumorDiagnostics(ctypes.Structure):
@@ -149,10 +149,14 @@ def make_params(values: dict) -> TumorParams:
     return TumorParams(*[float(values[k]) for k in PARAM_FIELDS])
 
 
+MODELS = {"multispecies": 0, "single": 1}
+
+
 def make_config(n, precision="fp64", dt=0.01, rtol_diff=1e-8, rtol_elast=1e-8, max_it=1000,
-                flags=F_DEFAULT) -> TumorConfig:
+                flags=F_DEFAULT, model="multispecies") -> TumorConfig:
+    """model: "multispecies" or "single" (an unknown name gives an invalid code)."""
     return TumorConfig(int(n), PREC[precision], float(dt), float(rtol_diff), float(rtol_elast),
-                       int(max_it), int(flags), (ctypes.c_int32 * 4)(0, 0, 0, 0))
+                       int(max_it), int(flags), MODELS.get(model, -1), (ctypes.c_int32 * 3)(0, 0, 0))
 
 
 def workspace_bytes(cfg: TumorConfig) -> int:
@@ -180,13 +184,13 @@ class Tumor:
 
     def __init__(self, n, params: dict, wm, gm, csf, centers=(), sigmas=(), weights=(),
                  precision="fp64", dt=0.01, rtol_diff=1e-8, rtol_elast=1e-8, max_it=1000,
-                 flags=F_DEFAULT, stream=None):
+                 flags=F_DEFAULT, stream=None, model="multispecies"):
         import torch
         self._torch = torch
         lib = load_library()
         self.lib = lib
         self.n = int(n)
-        self.cfg = make_config(n, precision, dt, rtol_diff, rtol_elast, max_it, flags)
+        self.cfg = make_config(n, precision, dt, rtol_diff, rtol_elast, max_it, flags, model)
         self.prm = make_params(params)
         nb = workspace_bytes(self.cfg)
         dev = wm.device

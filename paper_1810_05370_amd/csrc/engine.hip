@@ -87,7 +87,9 @@ int check_cfg(const tumor_config* c) {
   if (!(c->rtol_elast > 0.0 && c->rtol_elast < 1.0)) return TUMOR_EINVAL;
   if (c->max_it < 1) return TUMOR_EINVAL;
   if (c->flags & ~(TUMOR_F_DEFAULT | TUMOR_F_ADJOINT)) return TUMOR_EINVAL;
-  for (int k = 0; k < 4; ++k)
+  if (c->model != TUMOR_MODEL_MULTISPECIES && c->model != TUMOR_MODEL_SINGLE) return TUMOR_EINVAL;
+  if (c->model == TUMOR_MODEL_SINGLE && (c->flags & TUMOR_F_ADJOINT)) return TUMOR_EINVAL;
+  for (int k = 0; k < 3; ++k)
     if (c->reserved[k] != 0) return TUMOR_EINVAL;
   return TUMOR_OK;
 }
@@ -115,7 +117,8 @@ struct tumor_ctx {
   int n;
   long long V, S;
   bool mixed;
-  bool adj;  // adjoint scratch present
+  bool adj;     // adjoint scratch present
+  bool single;  // single-species model (tumour c in F[P])
   int flags;
   double* F[8];
   double* G[8];
@@ -818,6 +821,7 @@ void refresh(Ctx& c, int do_reaction, const double* const* in, double* const* ou
   a.partials = c.partials;
   a.V = c.V;
   a.do_reaction = do_reaction;
+  a.single = c.single ? 1 : 0;
   a.rc = c.rc;
   a.fc = c.fc;
   const double rb = do_reaction ? (10.0 + 13.0) * c.V * 8.0 + (c.K32 ? 16.0 * c.V : 0.0) : 12.0 * c.V * 8.0;
@@ -946,8 +950,15 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
     for (int k : ids)
       HIPCHECK(hipMemcpyAsync(c.G[k], c.F[k], c.V * sizeof(double), hipMemcpyDeviceToDevice, c.st));
   }
-  // S2: Crank-Nicolson diffusion of i, o (and l).
   SolveOut sd[3];
+  if (c.single) {
+    // Single-species model: CN diffusion of c, then its reaction and the refresh.
+    sd[0] = cn_solve(c, c.G[P], c.Rdd[0], 0);
+    const double* in[9] = {c.G[P], c.G[P], c.Rdd[0], c.G[N], c.G[G], c.G[W], c.F[O], c.F[L], c.G[F]};
+    double* out[8] = {c.F[P], c.F[I], c.F[N], c.F[G], c.F[W], c.F[O], c.F[L], c.F[F]};
+    refresh(c, 1, in, out);
+  } else {
+  // S2: Crank-Nicolson diffusion of i, o (and l).
   sd[0] = cn_solve(c, c.G[I], c.Rdd[0], 0);
   sd[1] = cn_solve(c, c.F[O], c.Rdd[1], 1);
   if (c.flags & TUMOR_F_EDEMA) sd[2] = cn_solve(c, c.F[L], c.Rdd[2], 2);
@@ -957,6 +968,7 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
     const double* in[9] = {c.G[P], c.G[I], c.Rdd[0], c.G[N], c.G[G], c.G[W], c.Rdd[1], c.Rdd[2], c.G[F]};
     double* out[8] = {c.F[P], c.F[I], c.F[N], c.F[G], c.F[W], c.F[O], c.F[L], c.F[F]};
     refresh(c, 1, in, out);
+  }
   }
   // S6-S7: elasticity and rotation.
   SolveOut se;
@@ -1417,6 +1429,7 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
     c->V = V;
     c->S = V / 2;
     c->mixed = cfg->precision == TUMOR_PREC_MIXED;
+    c->single = cfg->model == TUMOR_MODEL_SINGLE;
     c->adj = (cfg->flags & TUMOR_F_ADJOINT) != 0;
     c->flags = (cfg->flags & TUMOR_F_DEFAULT) == 0 ? TUMOR_F_DEFAULT : (cfg->flags & TUMOR_F_DEFAULT);
     c->win_start = -1;

@@ -70,6 +70,7 @@ struct ReactArgs {
   double* partials;
   long long V;
   int do_reaction;
+  int single;  // single-species model: tumour c in p (i_dag = c after transport, i_dd after diffusion)
   ReactConsts rc;
   RefreshConsts fc;
 };

@@ -97,7 +97,25 @@ __global__ void __launch_bounds__(kRedThreads) k_react(ReactArgs a) {
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.V; v += stride) {
     double p = a.p[v], n = a.n[v], g = a.g[v], w = a.w[v], o = a.o[v], l = a.l[v], f = a.f[v];
     double i = a.i_dd[v];
-    if (a.do_reaction) {
+    if (a.do_reaction && a.single) {
+      // Single-species model (e:rd): logistic growth rho c (1 - c) with the
+      // frozen rho (e:reac_op, e:reaction_op), exact over dt; g and w lose the
+      // diffusion and growth increments in proportion g : w (e:gm, e:wm).
+      const double c_dag = a.i_dag[v], c_dd = i;
+      const double dR = logistic_flow(c_dd, a.rho[v], rc.dt) - c_dd;
+      const double c1 = c_dd + dR;
+      const double s = (c_dd - c_dag) + dR;
+      const double gw = g + w;
+      const bool small = gw < 1e-12;
+      const double phig = small ? 0.5 : g / gw;
+      const double phiw = small ? 0.5 : w / gw;
+      p = c1;
+      i = 0.0;
+      g = g - phig * s;
+      w = w - phiw * s;
+      a.po[v] = p; a.io[v] = i; a.no[v] = n; a.go[v] = g; a.wo[v] = w; a.oo[v] = o; a.lo[v] = l;
+      a.fo[v] = f;
+    } else if (a.do_reaction) {
       const double dt = rc.dt;
       const double dD = i - a.i_dag[v];
       const double rho_p = a.rho[v];

@@ -202,3 +202,21 @@ def test_mass_effect_diagnostics_element_by_element(inputs, precision):
     for key in ("max_disp", "trace_min", "trace_max", "shear_max", "jac_l2"):
         assert abs(s[key] - ref_s[key]) <= 1e-10 * abs(ref_s[key]), key
     assert abs(s["d_max"] - ref_s["d_max"]) <= 1e-9 * max(1.0, ref_s["d_max"])
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_single_species_total_density_is_conserved_without_transport(inputs, precision):
+    P = synthetic.params()
+    sim = tm.from_inputs(inputs, P, precision=precision, flags=tm.F_ELASTICITY, model="single")
+
+    def total():
+        return sum(float(np.sum(_host(sim, k))) for k in ("p", "g", "w"))
+
+    m0 = total()
+    st = sim.step(2)
+    m1 = total()
+    drift = abs(m1 - m0) / m0
+    say(f"single-species mass {precision}: relative drift {drift:.1e}; it {st['it_diff']} {st['it_elast']}")
+    assert drift < (1e-12 if precision == "fp64" else 1e-10)
+    assert st["relres_elast"] <= 1e-8 and st["relres_diff"][0] <= 1e-8 and st["it_elast"] > 0
+    sim.close()
