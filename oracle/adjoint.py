@@ -307,6 +307,10 @@ def adjoint_step(P, grid, tape, lam, grad, cfg=None):
             bar[k] += tb
         mu_base = sum(parts[k][0] * f for k, f in (("w", w1), ("g", g1), ("f", adv["f"]), ("t", tau)))
         la_base = sum(parts[k][1] * f for k, f in (("w", w1), ("g", g1), ("f", adv["f"]), ("t", tau)))
+        if tape.get("bg") is not None:
+            mu_b, la_b = rx.lame_species(P["E_bg"], P["nu_bg"])
+            mu_base = mu_base + mu_b * tape["bg"]
+            la_base = la_base + la_b * tape["bg"]
         grad["lame_scale"] += dot(mu_base, mub) + dot(la_base, lamb)
     else:
         u_bar_prev_slot = u_bar_prev_slot + u_bar_new      # u^{n+1} = u^n
@@ -382,7 +386,7 @@ def gradient(P, inputs, steps, tau_target, cfg=None):
     if cfg:
         c.update(cfg)
     st = model.init_state(P, inputs["n"], inputs["wm"], inputs["gm"], inputs["csf"], inputs["centers"],
-                          inputs["sigmas"], inputs["weights"])
+                          inputs["sigmas"], inputs["weights"], inputs.get("bg"))
     grid = st.grid
     tapes = []
     for k in range(steps):

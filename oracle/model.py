@@ -54,13 +54,14 @@ def gaussian_basis(grid, centers, sigmas, weights):
 class State:
     """Species, displacement history and the coefficients of the last refresh."""
 
-    def __init__(self, grid, P, fields, u, u_prev):
+    def __init__(self, grid, P, fields, u, u_prev, bg=None):
         self.grid = grid
         self.P = P
         self.f = fields
         self.u = u
         self.u_prev = u_prev
-        self.coef = rx.refresh(P, *(fields[k] for k in ("p", "i", "n", "g", "w", "f")))
+        self.bg = bg          # static background-material fraction, or None
+        self.coef = rx.refresh(P, *(fields[k] for k in ("p", "i", "n", "g", "w", "f")), bg=bg)
         self.nstep = 0
 
     def copy(self):
@@ -68,12 +69,13 @@ class State:
         s.grid, s.P = self.grid, self.P
         s.f = {k: v.copy() for k, v in self.f.items()}
         s.u, s.u_prev = self.u.copy(), self.u_prev.copy()
+        s.bg = None if self.bg is None else self.bg.copy()
         s.coef = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in self.coef.items()}
         s.nstep = self.nstep
         return s
 
 
-def init_state(P, n, wm, gm, csf, centers, sigmas, weights):
+def init_state(P, n, wm, gm, csf, centers, sigmas, weights, bg=None):
     grid = Grid(n)
     p0 = gaussian_basis(grid, centers, sigmas, weights)
     z = np.zeros((n, n, n))
@@ -81,7 +83,7 @@ def init_state(P, n, wm, gm, csf, centers, sigmas, weights):
                   l=z.copy(), g=np.array(gm, float), w=np.array(wm, float),
                   f=np.array(csf, float))
     u = np.zeros((3, n, n, n))
-    return State(grid, P, fields, u, u.copy())
+    return State(grid, P, fields, u, u.copy(), None if bg is None else np.array(bg, float))
 
 
 DEFAULT_CFG = dict(dt=0.01, rtol_diff=1e-8, rtol_elast=1e-8, max_it=1000,
@@ -137,7 +139,7 @@ def step(st: State, cfg=None, forced=None, tape=None):
     l1 = rx.edema_reaction(P, dt, l_dag, i1) if c["edema"] else l_dag
     f1 = adv["f"]
     # S5: refresh.
-    coef = rx.refresh(P, p1, i1, n1, g1, w1, f1)
+    coef = rx.refresh(P, p1, i1, n1, g1, w1, f1, bg=st.bg)
     # S6: elasticity.
     ie, re_ = 0, 0.0
     if c["elasticity"]:
@@ -153,7 +155,7 @@ def step(st: State, cfg=None, forced=None, tape=None):
     if tape is not None:
         tape.update(v=v, adv=adv, i_dd=i_dd, o_dag=o_dag, l_dag=l_dag, coef0=F_coef0,
                     p1=p1, i1=i1, n1=n1, g1=g1, w1=w1, o1=o1, l1=l1, coef1=coef,
-                    u_new=u_new, u=st.u, u_prev=st.u_prev, F0={k: F[k] for k in F})
+                    u_new=u_new, u=st.u, u_prev=st.u_prev, F0={k: F[k] for k in F}, bg=st.bg)
     # S7: rotate.
     st.u_prev, st.u = st.u, u_new
     st.f = dict(p=p1, i=i1, n=n1, o=o1, l=l1, g=g1, w=w1, f=f1)
@@ -169,7 +171,7 @@ def step(st: State, cfg=None, forced=None, tape=None):
 def run(P, inputs, steps, cfg=None, forced=None):
     """Initialise from a ``synthetic.workload_inputs`` dict and take ``steps`` steps."""
     st = init_state(P, inputs["n"], inputs["wm"], inputs["gm"], inputs["csf"],
-                    inputs["centers"], inputs["sigmas"], inputs["weights"])
+                    inputs["centers"], inputs["sigmas"], inputs["weights"], inputs.get("bg"))
     stats = []
     for k in range(steps):
         stats.append(step(st, cfg, None if forced is None else forced[k]))

@@ -46,7 +46,7 @@ def step(st: State, cfg=None, forced=None):
     c1, g1, w1 = rx.single_species_reaction(P, dt, adv["p"], c_dd, adv["g"], adv["w"], coef["rho_p"])
     f1 = adv["f"]
     z = np.zeros_like(c1)
-    coef = rx.refresh(P, c1, z, z, g1, w1, f1)
+    coef = rx.refresh(P, c1, z, z, g1, w1, f1, bg=st.bg)
     ie, re_ = 0, 0.0
     if c["elasticity"]:
         force = rx.elastic_force(grid, P["zeta"], c1, z)

@@ -100,8 +100,13 @@ def lame_species(E, nu):
     return E / (2.0 * (1.0 + nu)), nu * E / ((1.0 - 2.0 * nu) * (1.0 + nu))
 
 
-def refresh(P, p, i, n, g, w, f):
-    """Coefficient fields and their voxel means from the current species."""
+def refresh(P, p, i, n, g, w, f, bg=None):
+    """Coefficient fields and their voxel means from the current species.
+
+    bg: optional static background-material fraction (fictitious domain,
+    Sec. 3): it enters the Lame mixture with (E_bg, nu_bg) (e:lame) and the
+    screening with eta_bg (e:screening); it carries no diffusion or growth, so
+    the tumour flux vanishes outside the brain."""
     tau = p + i + n
     K = P["k_w"] * w + P["k_g"] * g + P["k_f"] * f
     rho_p = P["rho_w"] * w + P["rho_g"] * g
@@ -114,6 +119,11 @@ def refresh(P, p, i, n, g, w, f):
     mu = s * (mu_w * w + mu_g * g + mu_f * f + mu_t * tau)
     lam = s * (la_w * w + la_g * g + la_f * f + la_t * tau)
     eta = P["eta_tumor"] * tau + P["eta_healthy"] * (g + w + f)
+    if bg is not None:
+        mu_b, la_b = lame_species(P["E_bg"], P["nu_bg"])
+        mu = mu + s * mu_b * bg
+        lam = lam + s * la_b * bg
+        eta = eta + P["eta_bg"] * bg
     return dict(K=K, rho_p=rho_p, rho_i=rho_i, mu=mu, lam=lam, eta=eta,
                 Kbar=float(K.mean()), mubar=float(mu.mean()),
                 lambar=float(lam.mean()), etabar=float(eta.mean()))

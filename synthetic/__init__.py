@@ -43,6 +43,7 @@ TABLE_SETUP = dict(
     nu_wm=0.3, nu_gm=0.3, nu_csf=0.1, nu_tumor=0.45,
     lame_scale=1.0, zeta=4.0e4,
     heaviside_eps=0.01,
+    E_bg=15000.0, nu_bg=0.48, eta_bg=1.0e6,          # background material (fictitious domain)
 )
 
 # Overrides shared by every synthetic workload.
@@ -121,15 +122,40 @@ def tumor_seeds(kind: str, seed: int):
     raise ValueError(kind)
 
 
-def workload_inputs(name: str, n: int | None = None):
-    """All inputs of a named workload (optionally at another grid size)."""
+BRAIN_SEMI_AXES = (0.80 * math.pi, 0.92 * math.pi, 0.72 * math.pi)   # (x, y, z), centred at (pi, pi, pi)
+
+
+def brain_mask(n: int, width_cells: float = 2.0):
+    """Smooth ellipsoidal brain mask in (0, 1): 1/2 (1 - tanh(d / (width h))),
+    d = (r - 1) min(semi-axes) with r the ellipsoidal radius about the centre."""
+    h = TWO_PI / n
+    c = np.arange(n) * h - math.pi
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    a, b, cz = BRAIN_SEMI_AXES
+    r = np.sqrt((x / a) ** 2 + (y / b) ** 2 + (z / cz) ** 2)
+    d = (r - 1.0) * min(BRAIN_SEMI_AXES)
+    return 0.5 * (1.0 - np.tanh(d / (width_cells * h)))
+
+
+def workload_inputs(name: str, n: int | None = None, masked: bool = False):
+    """All inputs of a named workload (optionally at another grid size).
+
+    masked: fictitious domain with a brain mask m (brain_mask): the tissue
+    maps are multiplied by m, the background fraction bg = 1 - m is returned
+    under "bg", and the tumour seeds are pulled towards the centre
+    (c -> pi + 0.35 (c - pi)) so that they lie inside the brain."""
     wl = WORKLOADS[name]
     nn = wl["n"] if n is None else int(n)
     wm, gm, csf = tissue_maps(nn, wl["sigma_cells"], wl["seed"])
     centers, sigmas, weights = tumor_seeds(wl["seeds"], wl["seed"])
-    return dict(n=nn, wm=wm, gm=gm, csf=csf, centers=centers, sigmas=sigmas,
-                weights=weights, steps=wl["steps"], precision=wl["precision"],
-                dt=0.01, rtol=1e-8)
+    out = dict(n=nn, wm=wm, gm=gm, csf=csf, centers=centers, sigmas=sigmas,
+               weights=weights, steps=wl["steps"], precision=wl["precision"],
+               dt=0.01, rtol=1e-8)
+    if masked:
+        m = brain_mask(nn)
+        out.update(wm=wm * m, gm=gm * m, csf=csf * m, bg=1.0 - m,
+                   centers=math.pi + 0.35 * (np.asarray(centers) - math.pi))
+    return out
 
 
 def random_field(n: int, seed: int, smooth_cells: float = 0.0, ncomp: int | None = None):
