@@ -84,9 +84,10 @@ def run_form(tm, torch, inp, P, precision, steps, warmup):
                 diag=diag, diag_ms=diag_ms)
 
 
-def run_single(tm, torch, inp, P, precision, steps, warmup):
-    """Split steps/s of the single-species model on the same inputs."""
-    sim = tm.from_inputs(inp, P, precision=precision, model="single")
+def run_single(tm, torch, inp, P, precision, steps, warmup, model="single"):
+    """Split steps/s of a model variant (the single-species model, or the
+    multispecies model on masked inputs) on the 256^3 inputs."""
+    sim = tm.from_inputs(inp, P, precision=precision, model=model)
     for _ in range(warmup):
         sim.step(1)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -98,7 +99,7 @@ def run_single(tm, torch, inp, P, precision, steps, warmup):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     sim.close()
-    log(f"[single {precision}] {steps} steps: {ms / steps:.1f} ms/step, elasticity it {[s['it_elast'] for s in its]}")
+    log(f"[{model} {precision}] {steps} steps: {ms / steps:.1f} ms/step, elasticity it {[s['it_elast'] for s in its]}")
     return dict(steps_per_s=round(steps / (ms / 1e3), 4), ms_per_step=round(ms / steps, 3),
                 elasticity_iterations=[s["it_elast"] for s in its], diffusion_iterations=[s["it_diff"][0] for s in its])
 
@@ -310,6 +311,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint form")
     ap.add_argument("--no-single", action="store_true", help="skip the single-species model")
+    ap.add_argument("--no-masked", action="store_true",
+                    help="skip the fictitious-domain form (brain mask and background material)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel that calibrates "
                          "the HBM byte counters of a rocprofv3 --pmc run)")
@@ -382,6 +385,11 @@ def main():
     if not args.no_single:
         extra["single_species"] = {prec: run_single(tm, torch, inp, P, prec, args.steps, args.warmup)
                                    for prec in (("mixed", "fp64") if not args.no_fp64 else ("mixed",))}
+
+    if not args.no_masked:
+        minp = synthetic.workload_inputs(args.workload, masked=True)
+        extra["masked"] = dict(workload=f"{args.workload} with the brain mask and background material",
+                               **run_single(tm, torch, minp, P, precision, args.steps, args.warmup, "multispecies"))
 
     if not args.no_adjoint:
         ainp = synthetic.workload_inputs(args.adjoint_workload)

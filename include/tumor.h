@@ -78,9 +78,9 @@ typedef enum {
  *                                  (e:alpha, e:beta, e:death, e:gog_reac_op)
  *   oxygen: -delta_p p + delta_s (o_heal - o)(g + w)                    (e:ox)
  *   edema:  delta_e i/(i + delta_half)(1 - i) - delta_l l             (e:edema)
- *   eta    = eta_tumor (p+i+n) + eta_healthy (g+w+f)             (e:screening)
- *   mu, lambda from (E_s, nu_s) of w, g, f and the tumour p+i+n (e:lame),
- *           both multiplied by lame_scale
+ *   eta    = eta_tumor (p+i+n) + eta_healthy (g+w+f) + eta_bg bg  (e:screening)
+ *   mu, lambda from (E_s, nu_s) of w, g, f, the tumour p+i+n and the
+ *           background bg (e:lame), both multiplied by lame_scale
  *   force  b = zeta tanh(p+n) grad(p+n)                   (e:forcingfunction)
  *   H(x)   = (1 + tanh(x / heaviside_eps)) / 2  (the smoothed Heaviside)
  */
@@ -93,6 +93,12 @@ typedef struct {
   double E_wm, E_gm, E_csf, E_tumor, nu_wm, nu_gm, nu_csf, nu_tumor;
   double lame_scale, zeta;
   double heaviside_eps;
+  double E_bg, nu_bg, eta_bg;  /* background material (fictitious domain, Sec. 3;
+                                  Table t:setup): with the background fraction
+                                  TUMOR_FIELD_BG it adds to the Lame mixture and
+                                  the screening, penalising displacement outside
+                                  the brain; it has no diffusion or growth, so
+                                  the tumour flux vanishes there               */
 } tumor_params;
 
 /* Tumour model (tumor_config.model).
@@ -143,7 +149,9 @@ enum {
   TUMOR_FIELD_UPREV = 9,    /* displacement u^{n-1}, 3 N^3 values             */
   TUMOR_FIELD_K = 10, TUMOR_FIELD_RHO = 11, TUMOR_FIELD_MU = 12,
   TUMOR_FIELD_LAMBDA = 13, TUMOR_FIELD_ETA = 14,   /* coefficients, read only */
-  TUMOR_FIELD_COUNT = 15
+  TUMOR_FIELD_BG = 15,      /* static background-material fraction (0 at init;
+                               call tumor_refresh after setting it)            */
+  TUMOR_FIELD_COUNT = 16
 };
 
 /* Device workspace size (bytes) a context for `cfg` needs.  Host arguments.
@@ -235,8 +243,8 @@ int tumor_adjoint_step(tumor_ctx* ctx, double* adj, double* grad);
 
 /* Copy a field out of / into the state (device arrays of N^3, or 3 N^3 for
  * TUMOR_FIELD_U and TUMOR_FIELD_UPREV).  Coefficient fields are read only;
- * setting a species refreshes nothing (call tumor_refresh afterwards to
- * recompute the coefficients from the species). */
+ * setting a species or the background refreshes nothing (call tumor_refresh
+ * afterwards to recompute the coefficients). */
 int tumor_get_field(tumor_ctx* ctx, int32_t field_id, double* dst);
 int tumor_set_field(tumor_ctx* ctx, int32_t field_id, const double* src);
 int tumor_refresh(tumor_ctx* ctx);

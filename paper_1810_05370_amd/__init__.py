@@ -21,7 +21,7 @@ PARAM_FIELDS = (
     "alpha0", "beta0", "gamma", "sigma_b", "o_hyp", "o_inv", "o_heal", "delta_s", "delta_p",
     "delta_e", "delta_half", "delta_l", "eta_tumor", "eta_healthy",
     "E_wm", "E_gm", "E_csf", "E_tumor", "nu_wm", "nu_gm", "nu_csf", "nu_tumor",
-    "lame_scale", "zeta", "heaviside_eps",
+    "lame_scale", "zeta", "heaviside_eps", "E_bg", "nu_bg", "eta_bg",
 )
 
 OK, EINVAL, ENOMEM, ENOCONV, EDEVICE, ENAN, ESTATE = 0, -1, -2, -3, -4, -5, -6
@@ -33,7 +33,7 @@ F_DEFAULT = F_ADVECTION | F_ELASTICITY | F_EDEMA
 F_ADJOINT = 0x8
 GRAD_NAMES = ("rho", "k_w", "k_g", "k_f", "lame_scale")
 FIELDS = {"p": 0, "i": 1, "n": 2, "o": 3, "l": 4, "g": 5, "w": 6, "f": 7, "u": 8, "u_prev": 9,
-          "K": 10, "rho": 11, "mu": 12, "lambda": 13, "eta": 14}
+          "K": 10, "rho": 11, "mu": 12, "lambda": 13, "eta": 14, "bg": 15}
 OPS = {"deriv_x": 0, "deriv_y": 1, "deriv_z": 2, "diffusion": 3, "elasticity": 4,
        "elast_precond": 5, "cn_precond": 6, "force": 7}
 VECTOR_OPS = ("elasticity", "elast_precond", "force")
@@ -355,9 +355,15 @@ class Tumor:
 
 
 def from_inputs(inputs: dict, params: dict, device="cuda", **kw) -> Tumor:
-    """Build a context from a ``synthetic.workload_inputs`` dictionary."""
+    """Build a context from a ``synthetic.workload_inputs`` dictionary (with
+    the background fraction set and the coefficients refreshed when the
+    inputs carry one)."""
     import torch
     n = inputs["n"]
     t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
-    return Tumor(n, params, t(inputs["wm"]), t(inputs["gm"]), t(inputs["csf"]),
-                 inputs["centers"], inputs["sigmas"], inputs["weights"], **kw)
+    sim = Tumor(n, params, t(inputs["wm"]), t(inputs["gm"]), t(inputs["csf"]),
+                inputs["centers"], inputs["sigmas"], inputs["weights"], **kw)
+    if inputs.get("bg") is not None:
+        sim.set("bg", t(inputs["bg"]))
+        sim.refresh()
+    return sim

@@ -179,8 +179,9 @@ __global__ void __launch_bounds__(256) k_coef_adj(CoefAdjArgs a) {
     a.L[5][v] += fc.mu_g * mb + fc.la_g * lb + fc.eta_h * eb;
     a.L[6][v] += fc.mu_w * mb + fc.la_w * lb + fc.eta_h * eb;
     a.L[7][v] += fc.mu_f * mb + fc.la_f * lb + fc.eta_h * eb;
-    const double mu = fc.mu_w * w + fc.mu_g * g + fc.mu_f * f + fc.mu_t * tau;
-    const double la = fc.la_w * w + fc.la_g * g + fc.la_f * f + fc.la_t * tau;
+    const double b = a.bg[v];
+    const double mu = fc.mu_w * w + fc.mu_g * g + fc.mu_f * f + fc.mu_t * tau + fc.mu_b * b;
+    const double la = fc.la_w * w + fc.la_g * g + fc.la_f * f + fc.la_t * tau + fc.la_b * b;
     acc[0] += (mu * mb + la * lb) * a.inv_scale;
   }
   store_grad_partials<1>(acc, a.partials);

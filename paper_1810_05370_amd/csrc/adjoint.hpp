@@ -30,6 +30,7 @@ struct ReactAdjArgs {
 struct CoefAdjArgs {
   const double *mub, *lamb, *etab;
   const double *p1, *i1, *n1, *g1, *w1, *f1;
+  const double* bg;  // static background fraction
   double* L[8];  // p, i, n, o, l, g, w, f
   RefreshConsts fc;
   double inv_scale;

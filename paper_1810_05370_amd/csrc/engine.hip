@@ -117,6 +117,7 @@ struct tumor_ctx {
   int n;
   long long V, S;
   bool mixed;
+  double* BG;   // static background-material fraction
   bool adj;     // adjoint scratch present
   bool single;  // single-species model (tumour c in F[P])
   int flags;
@@ -209,6 +210,7 @@ void layout(Ctx& c, Carver& cv) {
   c.U = cv.take<cplx<double>>(3 * S);
   c.Up = cv.take<cplx<double>>(3 * S);
   c.Un = cv.take<cplx<double>>(3 * S);
+  c.BG = cv.take<double>(V);
   c.K = cv.take<double>(V);
   c.rho = cv.take<double>(V);
   c.mu = cv.take<double>(V);
@@ -813,6 +815,7 @@ void refresh(Ctx& c, int do_reaction, const double* const* in, double* const* ou
   a.mu = c.mu;
   a.lam = c.lam;
   a.eta = c.eta;
+  a.bg = c.BG;
   a.K32 = c.K32;
   a.mu32 = c.mu32;
   a.lam32 = c.lam32;
@@ -855,6 +858,9 @@ void set_consts(Ctx& c) {
   c.fc.la_t = s * la_of(p.E_tumor, p.nu_tumor);
   c.fc.eta_t = p.eta_tumor;
   c.fc.eta_h = p.eta_healthy;
+  c.fc.mu_b = s * mu_of(p.E_bg, p.nu_bg);
+  c.fc.la_b = s * la_of(p.E_bg, p.nu_bg);
+  c.fc.eta_b = p.eta_bg;
   c.rc.dt = c.cfg.dt;
   c.rc.alpha0 = p.alpha0;
   c.rc.beta0 = p.beta0;
@@ -881,10 +887,10 @@ int check_params(const tumor_params* p) {
     if (!std::isfinite(v[k])) return TUMOR_EINVAL;
   if (!(p->heaviside_eps > 0.0)) return TUMOR_EINVAL;
   if (!(p->o_inv > p->o_hyp)) return TUMOR_EINVAL;  // o_mit strictly below o_inv
-  const double nus[4] = {p->nu_wm, p->nu_gm, p->nu_csf, p->nu_tumor};
+  const double nus[5] = {p->nu_wm, p->nu_gm, p->nu_csf, p->nu_tumor, p->nu_bg};
   for (double nu : nus)
     if (!(nu > -1.0 && nu < 0.5)) return TUMOR_EINVAL;
-  if (p->eta_tumor < 0.0 || p->eta_healthy < 0.0) return TUMOR_EINVAL;
+  if (p->eta_tumor < 0.0 || p->eta_healthy < 0.0 || p->eta_bg < 0.0) return TUMOR_EINVAL;
   return TUMOR_OK;
 }
 
@@ -1228,6 +1234,7 @@ void adjoint_core(Ctx& c, const double* x0, double* adj, int m, double* grad) {
     ca.g1 = c.F[G];
     ca.w1 = c.F[W];
     ca.f1 = c.F[F];
+    ca.bg = c.BG;
     for (int k = 0; k < 8; ++k) ca.L[k] = Lm[k];
     ca.fc = c.fc;
     ca.inv_scale = 1.0 / c.prm.lame_scale;
@@ -1459,6 +1466,7 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
     HIPCHECK(hipMemsetAsync(c->F[I], 0, fb, c->st));
     HIPCHECK(hipMemsetAsync(c->F[N], 0, fb, c->st));
     HIPCHECK(hipMemsetAsync(c->F[L], 0, fb, c->st));
+    HIPCHECK(hipMemsetAsync(c->BG, 0, fb, c->st));
     {
       std::vector<double> o(V, prm->o_heal);
       HIPCHECK(hipMemcpyAsync(c->F[O], o.data(), fb, hipMemcpyHostToDevice, c->st));
@@ -1667,7 +1675,7 @@ int tumor_get_field(tumor_ctx* ctx, int32_t id, double* dst) {
     } else if (id == TUMOR_FIELD_U || id == TUMOR_FIELD_UPREV) {
       u_to_phys(c, id == TUMOR_FIELD_U ? c.U : c.Up, dst);
     } else {
-      const double* src[5] = {c.K, c.rho, c.mu, c.lam, c.eta};
+      const double* src[6] = {c.K, c.rho, c.mu, c.lam, c.eta, c.BG};
       HIPCHECK(hipMemcpyAsync(dst, src[id - TUMOR_FIELD_K], fb, hipMemcpyDeviceToDevice, c.st));
     }
     HIPCHECK(hipGetLastError());
@@ -1679,11 +1687,13 @@ int tumor_get_field(tumor_ctx* ctx, int32_t id, double* dst) {
 int tumor_set_field(tumor_ctx* ctx, int32_t id, const double* src) {
   if (!ctx) return einval("ctx is NULL");
   if (!src) return einval("src is NULL");
-  if (id < 0 || id > TUMOR_FIELD_UPREV) return einval("field is not settable");
+  if (id < 0 || (id > TUMOR_FIELD_UPREV && id != TUMOR_FIELD_BG)) return einval("field is not settable");
   return guarded([&]() -> int {
     Ctx& c = *ctx;
     if (id < 8) {
       HIPCHECK(hipMemcpyAsync(c.F[id], src, c.V * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+    } else if (id == TUMOR_FIELD_BG) {
+      HIPCHECK(hipMemcpyAsync(c.BG, src, c.V * sizeof(double), hipMemcpyDeviceToDevice, c.st));
     } else {
       u_from_phys(c, src, id == TUMOR_FIELD_U ? c.U : c.Up);
     }

@@ -48,6 +48,7 @@ struct RefreshConsts {
   double mu_w, mu_g, mu_f, mu_t;
   double la_w, la_g, la_f, la_t;
   double eta_t, eta_h;
+  double mu_b, la_b, eta_b;  // background material
 };
 
 struct ReactConsts {
@@ -66,6 +67,7 @@ struct ReactArgs {
   // coefficient fields: rho is read (frozen growth rate) then overwritten
   double *K, *rho, *mu, *lam, *eta;
   float *K32, *mu32, *lam32, *eta32;  // nullable (mixed precision copies)
+  const double* bg;                   // static background fraction
   CoefScalars* cs;
   double* partials;
   long long V;

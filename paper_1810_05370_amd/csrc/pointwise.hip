@@ -148,9 +148,10 @@ __global__ void __launch_bounds__(kRedThreads) k_react(ReactArgs a) {
     const double tau = p + i + n;
     const double K = fc.k_w * w + fc.k_g * g + fc.k_f * f;
     const double rho = fc.rho_w * w + fc.rho_g * g;
-    const double mu = fc.mu_w * w + fc.mu_g * g + fc.mu_f * f + fc.mu_t * tau;
-    const double lam = fc.la_w * w + fc.la_g * g + fc.la_f * f + fc.la_t * tau;
-    const double eta = fc.eta_t * tau + fc.eta_h * (g + w + f);
+    const double b = a.bg[v];
+    const double mu = fc.mu_w * w + fc.mu_g * g + fc.mu_f * f + fc.mu_t * tau + fc.mu_b * b;
+    const double lam = fc.la_w * w + fc.la_g * g + fc.la_f * f + fc.la_t * tau + fc.la_b * b;
+    const double eta = fc.eta_t * tau + fc.eta_h * (g + w + f) + fc.eta_b * b;
     a.K[v] = K; a.rho[v] = rho; a.mu[v] = mu; a.lam[v] = lam; a.eta[v] = eta;
     if (a.K32) {
       a.K32[v] = (float)K; a.mu32[v] = (float)mu; a.lam32[v] = (float)lam; a.eta32[v] = (float)eta;

@@ -45,11 +45,18 @@ def _gpu_gradient(inp, P, steps, target, ckpt, precision="fp64", rtol=1e-12):
 
 
 def _compare(lam_g, grad_g, lam_o, gr_o, gw_o, tol, label, grad_tol=None):
+    """Each adjoint slot's error relative to the larger of its own norm and
+    1e-4 of the whole adjoint state's norm.  Slots above that floor are held
+    to the relative bar; a slot the loss barely reaches (the oxygen adjoint
+    far from the oxygen switches, ~1e-17 of the total) holds only values at
+    the rounding level of the computation and is held to tol * 1e-4 of the
+    total instead."""
+    ref = [lam_o[name] for name in SLOTS] + [lam_o["u"], lam_o["u_prev"]]
+    total = np.sqrt(sum(np.linalg.norm(r) ** 2 for r in ref))
+    got = [lam_g[k] for k in range(8)] + [lam_g[8:11], lam_g[11:14]]
     res = {}
-    for k, name in enumerate(SLOTS):
-        res[name] = rel_l2(lam_g[k], lam_o[name])
-    res["u"] = rel_l2(lam_g[8:11], lam_o["u"])
-    res["u_prev"] = rel_l2(lam_g[11:14], lam_o["u_prev"])
+    for name, g, r in zip(list(SLOTS) + ["u", "u_prev"], got, ref):
+        res[name] = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-4 * total)
     g_o = np.array([gr_o[k] for k in adj.GRAD_NAMES] + list(gw_o))
     res["grad"] = rel_l2(grad_g, g_o)
     say(label, {k: f"{v:.2e}" for k, v in res.items()})

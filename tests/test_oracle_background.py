@@ -48,7 +48,7 @@ def test_background_penalises_displacement_outside_the_brain():
 def test_lame_scale_gradient_with_background():
     steps = 2
     P = synthetic.params(delta_p=60.0)
-    inp = synthetic.workload_inputs("lattice_n128", n=16, masked=True)
+    inp = synthetic.workload_inputs("seeds3_n128", n=16, masked=True)
     Pt = dict(P, rho_w=P["rho_w"] * 1.1, rho_g=P["rho_g"] * 1.1)
     st, _ = model.run(Pt, inp, steps, TIGHT)
     target = st.f["p"] + st.f["i"] + st.f["n"]
