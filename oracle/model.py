@@ -14,7 +14,10 @@ The step follows the multispecies splitting list of Sec. 3 in its listed
 
 Readings: the paper calls the splitting "Strang" but lists the sub-steps
 sequentially and reports first-order convergence, so the listed order is
-used once per step (Lie).  Displacement starts undeformed, u^0 = u^{-1} = 0.
+used once per step (Lie).  cfg["strang"] selects the symmetric variant: S1
+over dt/2, a refresh of the half-transported state (its K, rho and means
+drive S2 and S3), S2-S4 over dt, S1 again over dt/2 with the same velocity,
+then S5-S7.  Oxygen and edema are not transported in either form.  Displacement starts undeformed, u^0 = u^{-1} = 0.
 Coefficients used by S2, S3 (and the means used by the preconditioners)
 come from the most recent refresh (from q^0 at initialisation).  The
 initial tumour is p_0 = Phi w with unnormalised periodic Gaussians
@@ -87,7 +90,19 @@ def init_state(P, n, wm, gm, csf, centers, sigmas, weights, bg=None):
 
 
 DEFAULT_CFG = dict(dt=0.01, rtol_diff=1e-8, rtol_elast=1e-8, max_it=1000,
-                   edema=True, elasticity=True, advection=True)
+                   edema=True, elasticity=True, advection=True, strang=False)
+
+
+def strang_halves(c):
+    """True when the step is the symmetric form: transport over dt/2 before and
+    after the diffusion-reaction stage (only meaningful with advection on)."""
+    return bool(c["strang"]) and bool(c["advection"])
+
+
+def transport_half(grid, P, fields, v, dt, bg):
+    """The dt/2 transport of the symmetric form and the refresh of its result."""
+    adv = transport.advect(grid, fields, v, 0.5 * dt)
+    return adv, rx.refresh(P, adv["p"], adv["i"], adv["n"], adv["g"], adv["w"], adv["f"], bg=bg)
 
 
 def step(st: State, cfg=None, forced=None, tape=None):
@@ -105,10 +120,15 @@ def step(st: State, cfg=None, forced=None, tape=None):
     F, coef = st.f, st.coef
     F_coef0 = coef
     fx = forced if forced is not None else (None, None, None, None)
+    half = strang_halves(c)
+    if half and tape is not None:
+        raise ValueError("the discrete adjoint covers the sequential (Lie) step only")
 
     # S1: transport with the backward-difference velocity.
     v = (st.u - st.u_prev) / dt
-    if c["advection"]:
+    if half:
+        adv, coef = transport_half(grid, P, F, v, dt, st.bg)
+    elif c["advection"]:
         adv = transport.advect(grid, F, v, dt)
     else:
         adv = {k: F[k].copy() for k in ("p", "i", "n", "g", "w", "f")}
@@ -138,6 +158,10 @@ def step(st: State, cfg=None, forced=None, tape=None):
     o1 = rx.oxygen_reaction(P, dt, o_dag, p1, g1, w1)
     l1 = rx.edema_reaction(P, dt, l_dag, i1) if c["edema"] else l_dag
     f1 = adv["f"]
+    if half:
+        # second transport half-step, same velocity
+        back = transport.advect(grid, dict(p=p1, i=i1, n=n1, g=g1, w=w1, f=f1), v, 0.5 * dt)
+        p1, i1, n1, g1, w1, f1 = (back[k] for k in ("p", "i", "n", "g", "w", "f"))
     # S5: refresh.
     coef = rx.refresh(P, p1, i1, n1, g1, w1, f1, bg=st.bg)
     # S6: elasticity.

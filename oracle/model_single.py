@@ -15,6 +15,8 @@ multispecies model (tumour = p + i + n) then reduce exactly to the
 single-species ones.  Readings as in the multispecies step (Lie splitting in
 the listed order, u^0 = u^{-1} = 0, exact logistic flow, one refresh per
 step after the reaction, K = k_w w + k_g g + k_f f with k_f = 0).
+cfg["strang"] selects the symmetric form as in the multispecies step: S1
+over dt/2 and a refresh before S2, S1 over dt/2 again after S3.
 """
 from __future__ import annotations
 
@@ -23,7 +25,7 @@ import numpy as np
 from . import reaction as rx
 from . import solvers
 from . import transport
-from .model import DEFAULT_CFG, FIELDS, State, init_state  # noqa: F401
+from .model import DEFAULT_CFG, FIELDS, State, init_state, strang_halves, transport_half  # noqa: F401
 
 
 def step(st: State, cfg=None, forced=None):
@@ -35,7 +37,10 @@ def step(st: State, cfg=None, forced=None):
     fx = forced if forced is not None else (None, None, None, None)
 
     v = (st.u - st.u_prev) / dt
-    if c["advection"]:
+    half = strang_halves(c)
+    if half:
+        adv, coef = transport_half(grid, P, F, v, dt, st.bg)
+    elif c["advection"]:
         adv = transport.advect(grid, F, v, dt)
     else:
         adv = {k: F[k].copy() for k in ("p", "i", "n", "g", "w", "f")}
@@ -45,6 +50,10 @@ def step(st: State, cfg=None, forced=None):
     conv = ok
     c1, g1, w1 = rx.single_species_reaction(P, dt, adv["p"], c_dd, adv["g"], adv["w"], coef["rho_p"])
     f1 = adv["f"]
+    n1 = adv["n"]
+    if half:
+        back = transport.advect(grid, dict(p=c1, i=F["i"], n=n1, g=g1, w=w1, f=f1), v, 0.5 * dt)
+        c1, n1, g1, w1, f1 = (back[k] for k in ("p", "n", "g", "w", "f"))
     z = np.zeros_like(c1)
     coef = rx.refresh(P, c1, z, z, g1, w1, f1, bg=st.bg)
     ie, re_ = 0, 0.0
@@ -59,7 +68,7 @@ def step(st: State, cfg=None, forced=None):
     else:
         u_new = st.u.copy()
     st.u_prev, st.u = st.u, u_new
-    st.f = dict(p=c1, i=F["i"], n=adv["n"], o=F["o"], l=F["l"], g=g1, w=w1, f=f1)
+    st.f = dict(p=c1, i=F["i"], n=n1, o=F["o"], l=F["l"], g=g1, w=w1, f=f1)
     st.coef = coef
     st.nstep += 1
     h3 = grid.h ** 3
