@@ -84,10 +84,12 @@ def run_form(tm, torch, inp, P, precision, steps, warmup):
                 diag=diag, diag_ms=diag_ms)
 
 
-def run_single(tm, torch, inp, P, precision, steps, warmup, model="single"):
-    """Split steps/s of a model variant (the single-species model, or the
-    multispecies model on masked inputs) on the 256^3 inputs."""
-    sim = tm.from_inputs(inp, P, precision=precision, model=model)
+def run_single(tm, torch, inp, P, precision, steps, warmup, model="single", flags=None):
+    """Split steps/s of a model variant (the single-species model, the
+    multispecies model on masked inputs, or the symmetric step) on the 256^3
+    inputs."""
+    sim = tm.from_inputs(inp, P, precision=precision, model=model,
+                         flags=tm.F_DEFAULT if flags is None else flags)
     for _ in range(warmup):
         sim.step(1)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -99,7 +101,7 @@ def run_single(tm, torch, inp, P, precision, steps, warmup, model="single"):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     sim.close()
-    log(f"[{model} {precision}] {steps} steps: {ms / steps:.1f} ms/step, elasticity it {[s['it_elast'] for s in its]}")
+    log(f"[{model} {precision} flags {flags}] {steps} steps: {ms / steps:.1f} ms/step, elasticity it {[s['it_elast'] for s in its]}")
     return dict(steps_per_s=round(steps / (ms / 1e3), 4), ms_per_step=round(ms / steps, 3),
                 elasticity_iterations=[s["it_elast"] for s in its], diffusion_iterations=[s["it_diff"][0] for s in its])
 
@@ -311,6 +313,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint form")
     ap.add_argument("--no-single", action="store_true", help="skip the single-species model")
+    ap.add_argument("--no-strang", action="store_true", help="skip the symmetric (Strang) form of the step")
     ap.add_argument("--no-masked", action="store_true",
                     help="skip the fictitious-domain form (brain mask and background material)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -385,6 +388,11 @@ def main():
     if not args.no_single:
         extra["single_species"] = {prec: run_single(tm, torch, inp, P, prec, args.steps, args.warmup)
                                    for prec in (("mixed", "fp64") if not args.no_fp64 else ("mixed",))}
+
+    if not args.no_strang:
+        extra["strang"] = {prec: run_single(tm, torch, inp, P, prec, args.steps, args.warmup, "multispecies",
+                                            tm.F_DEFAULT | tm.F_STRANG)
+                           for prec in (("mixed", "fp64") if not args.no_fp64 else ("mixed",))}
 
     if not args.no_masked:
         minp = synthetic.workload_inputs(args.workload, masked=True)

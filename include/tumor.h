@@ -67,6 +67,15 @@ typedef enum {
 #define TUMOR_F_EDEMA      0x4  /* edema diffusion + reaction (Sec. 2.4)        */
 #define TUMOR_F_DEFAULT    (TUMOR_F_ADVECTION | TUMOR_F_ELASTICITY | TUMOR_F_EDEMA)
 #define TUMOR_F_ADJOINT    0x8  /* reserve adjoint scratch in the workspace      */
+/* Symmetric (Strang) form of the step (Sec. 3 names Strang splitting; the
+ * default is the listed sequential order).  With TUMOR_F_ADVECTION set, each
+ * step transports over dt/2, refreshes the coefficients from that state (its
+ * K, rho and means drive the diffusion and reaction), runs diffusion and
+ * reaction over dt, transports over dt/2 again with the same velocity, then
+ * refreshes and solves the elasticity.  Oxygen and edema are not transported
+ * in either form.  Without TUMOR_F_ADVECTION the flag changes nothing.
+ * Forward only: rejected together with TUMOR_F_ADJOINT. */
+#define TUMOR_F_STRANG     0x10
 
 /* Model parameters.  Names follow Table t:setup (Sec. 2.5) and the equations
  * they enter:
@@ -136,7 +145,8 @@ typedef struct {
   double relres_diff[3];     /* final relative residuals (FP64)                */
   double relres_elast;
   double mass[8];            /* h^3 sum of p, i, n, o, l, g, w, f               */
-  double max_cfl;            /* max |dt v| / h of the velocity that was used    */
+  double max_cfl;            /* max |dt v| / h of the velocity that was used
+                                (full dt also for TUMOR_F_STRANG)               */
 } tumor_step_stats;
 
 typedef struct tumor_ctx tumor_ctx;
@@ -191,7 +201,8 @@ int tumor_solve_elasticity(tumor_ctx* ctx, const double* force, double* u_out,
  * and the semi-Lagrangian step of p, i, n, g, w (conservative form) and f,
  * exactly as tumor_step does it.  out: device, 6 N^3 values, the transported
  * p, i, n, g, w, f in that order.  max_cfl: host, nullable, receives
- * max |dt u_t^n| / h.  The state is unchanged. */
+ * max |dt u_t^n| / h.  The step is always the full-dt one, also for a context
+ * created with TUMOR_F_STRANG.  The state is unchanged. */
 int tumor_transport(tumor_ctx* ctx, double* out, double* max_cfl);
 
 /* Mass-effect diagnostics of the current displacement u^n (Sec. 3: stress by

@@ -31,6 +31,7 @@ PREC = {"fp64": 0, "mixed": 1}
 F_ADVECTION, F_ELASTICITY, F_EDEMA = 0x1, 0x2, 0x4
 F_DEFAULT = F_ADVECTION | F_ELASTICITY | F_EDEMA
 F_ADJOINT = 0x8
+F_STRANG = 0x10
 GRAD_NAMES = ("rho", "k_w", "k_g", "k_f", "lame_scale")
 FIELDS = {"p": 0, "i": 1, "n": 2, "o": 3, "l": 4, "g": 5, "w": 6, "f": 7, "u": 8, "u_prev": 9,
           "K": 10, "rho": 11, "mu": 12, "lambda": 13, "eta": 14, "bg": 15}

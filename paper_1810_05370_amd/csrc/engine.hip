@@ -86,7 +86,8 @@ int check_cfg(const tumor_config* c) {
   if (!(c->rtol_diff > 0.0 && c->rtol_diff < 1.0)) return TUMOR_EINVAL;
   if (!(c->rtol_elast > 0.0 && c->rtol_elast < 1.0)) return TUMOR_EINVAL;
   if (c->max_it < 1) return TUMOR_EINVAL;
-  if (c->flags & ~(TUMOR_F_DEFAULT | TUMOR_F_ADJOINT)) return TUMOR_EINVAL;
+  if (c->flags & ~(TUMOR_F_DEFAULT | TUMOR_F_ADJOINT | TUMOR_F_STRANG)) return TUMOR_EINVAL;
+  if ((c->flags & TUMOR_F_STRANG) && (c->flags & TUMOR_F_ADJOINT)) return TUMOR_EINVAL;
   if (c->model != TUMOR_MODEL_MULTISPECIES && c->model != TUMOR_MODEL_SINGLE) return TUMOR_EINVAL;
   if (c->model == TUMOR_MODEL_SINGLE && (c->flags & TUMOR_F_ADJOINT)) return TUMOR_EINVAL;
   for (int k = 0; k < 3; ++k)
@@ -340,8 +341,9 @@ constexpr ColTerm TR(int s, double c = 1.0) { return ColTerm{s, SYM_RAW, c}; }
 
 // Krylov work fused into an operator apply (see ZPUpdateArgs / ColProg.dsv).
 struct Fuse {
-  bool pupdate;  // first pass: p = M^-1 r + beta p (in place) before transforming p
+  bool pupdate;  // first pass: x += alpha p, p = M^-1 r + beta p (in place) before transforming p
   const void* r;
+  void* x;
   tumor::SolveScalars* sv;
   tumor::PrecConsts pc;
 };
@@ -397,11 +399,13 @@ void zinv_pupdate(Ctx& c, int ncomp, const Fuse& f, cplx<R>* p, void* const* out
   std::memset(&za, 0, sizeof(za));
   za.r = f.r;
   za.p = p;
+  za.x = f.x;
   for (int k = 0; k < 2 * ncomp; ++k) za.out[k] = outs[k];
   za.sv = f.sv;
   za.cs = c.cs;
   za.pc = f.pc;
-  timed(c, kcls<R>(TUMOR_K_ZINVP64, TUMOR_K_ZINVP32), 5.0 * ncomp * double(c.V) * sizeof(R),
+  // reads r, p, x; writes p, x and the two transformed outputs
+  timed(c, kcls<R>(TUMOR_K_ZINVP64, TUMOR_K_ZINVP32), 7.0 * ncomp * double(c.V) * sizeof(R),
         [&] { tumor::launch_zinv_pupdate<R>(c.n, ncomp, za, pb<R>(c).tw, c.st); });
 }
 
@@ -634,9 +638,9 @@ int pcg_iterate(Ctx& c, tumor::KrylovArgs a, Apply apply, double thr2, int limit
       c.cur_tag = launched;
       // iteration k: (p = M^-1 r + beta p fused into the first pass for k > 0),
       // q = A p with alpha = rho / <p, q> fused into the last pass, then x, r
-      Fuse fz{launched > 0, a.r, sv, a.pc};
+      Fuse fz{launched > 0, a.r, a.x, sv, a.pc};
       apply(static_cast<const cplx<R>*>(a.p), static_cast<cplx<R>*>(a.q), skip, &fz);
-      timed(c, kc, 6.0 * vb, [&] { tumor::launch_pcg_update<R>(a, c.st); });
+      timed(c, kc, 3.0 * vb, [&] { tumor::launch_pcg_update<R>(a, c.st); });
     }
     c.cur_tag = -1;
     HIPCHECK(hipGetLastError());
@@ -645,6 +649,7 @@ int pcg_iterate(Ctx& c, tumor::KrylovArgs a, Apply apply, double thr2, int limit
     if (c.hsv->done || launched >= limit) break;
     chunk = 4;
   }
+  timed(c, kc, 3.0 * vb, [&] { tumor::launch_pcg_xfinal<R>(a, c.st); });
   conv = c.hsv->conv != 0;
   bad = c.hsv->bad != 0;
   return c.hsv->it;
@@ -908,23 +913,25 @@ void twiddles(Ctx& c) {
   HIPCHECK(hipStreamSynchronize(c.st));
 }
 
-// S1 (Sec. 3): velocity u_t^n = (u^n - u^{n-1}) / dt and its divergence,
-// then the semi-Lagrangian step of p, i, n, g, w, f into outs[0..5] (in that
-// order).  max |dt v| / h lands in cs->cfl_bits.
-void transport(Ctx& c, double* const (&outs)[6]) {
-  enum { P, I, N, O, L, G, W, F };
-  velocity(c);
+// S1 (Sec. 3): velocity u_t^n = (u^n - u^{n-1}) / dt and its divergence
+// (unless `fresh_velocity` is false: the second half-step of the symmetric
+// form reuses them), then the semi-Lagrangian step over frac * dt of
+// ins[0..5] = p, i, n, g, w, f into outs[0..5].  max |frac dt v| / h lands in
+// cs->cfl_bits.
+void transport(Ctx& c, const double* const (&ins)[6], double* const (&outs)[6], double frac = 1.0,
+               bool fresh_velocity = true) {
+  if (fresh_velocity) velocity(c);
   tumor::SLArgs s;
   s.vx = c.vel[0];
   s.vy = c.vel[1];
   s.vz = c.vel[2];
   s.div = c.vel[3];
-  s.p = c.F[P];
-  s.i = c.F[I];
-  s.n = c.F[N];
-  s.g = c.F[G];
-  s.w = c.F[W];
-  s.f = c.F[F];
+  s.p = ins[0];
+  s.i = ins[1];
+  s.n = ins[2];
+  s.g = ins[3];
+  s.w = ins[4];
+  s.f = ins[5];
   s.po = outs[0];
   s.io = outs[1];
   s.no = outs[2];
@@ -932,8 +939,8 @@ void transport(Ctx& c, double* const (&outs)[6]) {
   s.wo = outs[4];
   s.fo = outs[5];
   s.n_grid = c.n;
-  s.dt = c.cfg.dt;
-  s.s = c.cfg.dt / (2.0 * M_PI / c.n);
+  s.dt = frac * c.cfg.dt;
+  s.s = frac * c.cfg.dt / (2.0 * M_PI / c.n);
   // pack: 10 FP64 reads, 12 RC writes; gather: 4 FP64 + 12 RC reads, 6 FP64
   // writes; FP32 adds the scan for the scales (6 FP64 reads).
   HIPCHECK(hipMemsetAsync(&c.cs->cfl_bits, 0, 7 * sizeof(unsigned long long), c.st));  // cfl + qmax[6]
@@ -947,10 +954,19 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
   enum { P, I, N, O, L, G, W, F };
   const int n = c.n;
   (void)n;
+  // Symmetric form: S1 over dt/2 here and again after the reaction.
+  const bool strang = (c.flags & TUMOR_F_STRANG) && (c.flags & TUMOR_F_ADVECTION);
   // S1: transport with u_t^n = (u^n - u^{n-1}) / dt
   if (c.flags & TUMOR_F_ADVECTION) {
+    const double* const ins[6] = {c.F[P], c.F[I], c.F[N], c.F[G], c.F[W], c.F[F]};
     double* const outs[6] = {c.G[P], c.G[I], c.G[N], c.G[G], c.G[W], c.G[F]};
-    transport(c, outs);
+    transport(c, ins, outs, strang ? 0.5 : 1.0);
+    if (strang) {
+      // coefficients (and their means) of the half-transported state
+      const double* in[9] = {c.G[P], c.G[I], c.G[I], c.G[N], c.G[G], c.G[W], c.F[O], c.F[L], c.G[F]};
+      double* out[8] = {nullptr};
+      refresh(c, 0, in, out);
+    }
   } else {
     const int ids[6] = {P, I, N, G, W, F};
     for (int k : ids)
@@ -975,6 +991,15 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
     double* out[8] = {c.F[P], c.F[I], c.F[N], c.F[G], c.F[W], c.F[O], c.F[L], c.F[F]};
     refresh(c, 1, in, out);
   }
+  }
+  if (strang) {
+    // second half-step of S1 with the same velocity, from F back into G; the
+    // two sets swap roles so the state stays in F; then the refresh (S5)
+    const double* const ins[6] = {c.F[P], c.F[I], c.F[N], c.F[G], c.F[W], c.F[F]};
+    double* const outs[6] = {c.G[P], c.G[I], c.G[N], c.G[G], c.G[W], c.G[F]};
+    transport(c, ins, outs, 0.5, false);
+    for (int k : {P, I, N, G, W, F}) std::swap(c.F[k], c.G[k]);
+    refresh_state(c);
   }
   // S6-S7: elasticity and rotation.
   SolveOut se;
@@ -1014,6 +1039,7 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
     if (c.flags & TUMOR_F_ADVECTION) {
       const unsigned long long bits = c.hcs->cfl_bits;
       std::memcpy(&stats->max_cfl, &bits, sizeof(double));
+      if (strang) stats->max_cfl *= 2.0;  // the half-steps measure |dt/2 v| / h
     } else {
       stats->max_cfl = 0.0;
     }
@@ -1438,7 +1464,8 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
     c->mixed = cfg->precision == TUMOR_PREC_MIXED;
     c->single = cfg->model == TUMOR_MODEL_SINGLE;
     c->adj = (cfg->flags & TUMOR_F_ADJOINT) != 0;
-    c->flags = (cfg->flags & TUMOR_F_DEFAULT) == 0 ? TUMOR_F_DEFAULT : (cfg->flags & TUMOR_F_DEFAULT);
+    c->flags = ((cfg->flags & TUMOR_F_DEFAULT) == 0 ? TUMOR_F_DEFAULT : (cfg->flags & TUMOR_F_DEFAULT)) |
+               (cfg->flags & TUMOR_F_STRANG);
     c->win_start = -1;
     int dev_count = 0;
     if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) throw Fail(TUMOR_EDEVICE, "no HIP device");
@@ -1560,8 +1587,10 @@ int tumor_transport(tumor_ctx* ctx, double* out, double* max_cfl) {
   if (!out) return einval("out is NULL");
   return guarded([&]() -> int {
     Ctx& c = *ctx;
+    enum { P, I, N, O, L, G, W, F };
+    const double* const ins[6] = {c.F[P], c.F[I], c.F[N], c.F[G], c.F[W], c.F[F]};
     double* const outs[6] = {out, out + c.V, out + 2 * c.V, out + 3 * c.V, out + 4 * c.V, out + 5 * c.V};
-    transport(c, outs);
+    transport(c, ins, outs);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipMemcpyAsync(c.hcs, c.cs, sizeof(tumor::CoefScalars), hipMemcpyDeviceToHost, c.st));
     HIPCHECK(hipStreamSynchronize(c.st));

@@ -133,15 +133,14 @@ void launch_cn_residual(const KrylovArgs& a, const void* c, const void* dc, hipS
 // p = M^-1 r; rho = <r, M^-1 r>; it = 0; done = 0.  zero_x: x = 0 as well.
 template <typename R>
 void launch_pcg_start(const KrylovArgs& a, int zero_x, hipStream_t st);
-// alpha = rho / <p, q>
-template <typename R>
-void launch_pcg_pq(const KrylovArgs& a, hipStream_t st);
-// x += alpha p, r -= alpha q, convergence test, beta
+// r -= alpha q, convergence test, beta.  x += alpha p is deferred: the fused
+// p-update pass of the next iteration applies it before replacing p
+// (ZPUpdateArgs.x), and launch_pcg_xfinal after the last iteration.
 template <typename R>
 void launch_pcg_update(const KrylovArgs& a, hipStream_t st);
-// p = M^-1 r + beta p
+// x += alpha p for the last iteration that ran (none: no-op)
 template <typename R>
-void launch_pcg_pupdate(const KrylovArgs& a, hipStream_t st);
+void launch_pcg_xfinal(const KrylovArgs& a, hipStream_t st);
 // out = M^-1 in (one application of the preconditioner)
 template <typename R>
 void launch_precond(const KrylovArgs& a, const void* in, void* out, hipStream_t st);

@@ -61,6 +61,7 @@ struct ColProg {
 struct ZPUpdateArgs {
   const void* r;
   void* p;
+  void* x;  // nullable: x += alpha p with the previous p and alpha, before p is replaced
   void* out[6];
   SolveScalars* sv;
   const CoefScalars* cs;

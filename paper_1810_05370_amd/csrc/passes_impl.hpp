@@ -197,8 +197,10 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
   const long long base = (long long)blockIdx.y * C + kx;
   const LdsView<R> lds{sbuf + col, TC, 1};
   const R beta = R(a.sv->beta);
+  const R alpha = R(a.sv->alpha);
   const cplx<R>* __restrict__ r = static_cast<const cplx<R>*>(a.r);
   cplx<R>* __restrict__ p = static_cast<cplx<R>*>(a.p);
+  cplx<R>* __restrict__ x = static_cast<cplx<R>*>(a.x);
   cplx<R> pn[NC][8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -211,6 +213,12 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const cplx<R> pv = p[c * S + idx];
+      if (x) {
+        cplx<R> xv = x[c * S + idx];
+        xv.x += alpha * pv.x;
+        xv.y += alpha * pv.y;
+        x[c * S + idx] = xv;
+      }
       pn[c][j] = {zv[c].x + beta * pv.x, zv[c].y + beta * pv.y};
       p[c * S + idx] = pn[c][j];
     }
@@ -397,7 +405,8 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xfwd(XProg prog, const c
 }
 
 template <typename R, int N>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2)) k_xelast(XElastArgs a, const cplx<R>* __restrict__ twg) {
+__global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
+    k_xelast(XElastArgs a, const cplx<R>* __restrict__ twg) {
   if (a.skip && *a.skip) return;
   TUMOR_ROW_SETUP(N)
   const R invV = R(1.0) / (R(N) * R(N) * R(N));
@@ -412,6 +421,11 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2)) 
   for (int f = 0; f < 8; ++f) out[f] = static_cast<cplx<R>*>(a.out[f]) + soff;
 
   {
+    // Group A: diagonal stresses and eta u_x.  The trace div u is formed in
+    // spectral space (i w_x U_x + dy u_y + dz u_z, one transform), so that each
+    // diagonal stress is then built and transformed on its own: at most three
+    // rows are live at a time, which lets the kernel reach 3 (FP32) or 2 (FP64)
+    // waves per SIMD.
     const ColTerm trace_terms[3] = {{0, SYM_IW, 1.0}, {4, SYM_ONE, 1.0}, {7, SYM_ONE, 1.0}};
     cplx<R> tr[8];
     row_c2r_terms<R, N>(tr, 3, trace_terms, a.in, soff, lds, t, tw);

@@ -739,22 +739,6 @@ __global__ void __launch_bounds__(kRedThreads) k_pcg_start(KrylovArgs a, SpecIdx
   block_store_partials<1>(acc, a.partials);
 }
 
-template <typename R, int NC>
-__global__ void __launch_bounds__(kRedThreads) k_pcg_pq(KrylovArgs a, SpecIdx ix) {
-  if (a.sv->done) return;
-  const long long S = (long long)a.n * a.n * (a.n / 2);
-  const cplx<R>* p = static_cast<const cplx<R>*>(a.p);
-  const cplx<R>* q = static_cast<const cplx<R>*>(a.q);
-  double acc[1] = {0.0};
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int kx = (int)(e & ix.hmask);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc[0] += wdot(p[e + c * S], q[e + c * S], kx);
-  }
-  block_store_partials<1>(acc, a.partials);
-}
-
 // alpha = rho / <p, q> from the partials of <p, q> (nb blocks, given stride).
 __global__ void __launch_bounds__(kRedThreads) k_fin_alpha(SolveScalars* sv, const double* part, int nb,
                                                             int stride) {
@@ -766,6 +750,7 @@ __global__ void __launch_bounds__(kRedThreads) k_fin_alpha(SolveScalars* sv, con
     if (!(isfinite(tot[0]) && tot[0] > 0.0)) {
       sv->bad = 1;
       sv->done = 1;
+      sv->alpha = 0.0;  // nothing left for the deferred x update to add
     } else {
       sv->alpha = sv->rho / tot[0];
     }
@@ -777,9 +762,7 @@ __global__ void __launch_bounds__(kRedThreads) k_pcg_update(KrylovArgs a, SpecId
   if (a.sv->done) return;
   const long long S = (long long)a.n * a.n * (a.n / 2);
   const R alpha = R(a.sv->alpha);
-  cplx<R>* x = static_cast<cplx<R>*>(a.x);
   cplx<R>* r = static_cast<cplx<R>*>(a.r);
-  const cplx<R>* p = static_cast<const cplx<R>*>(a.p);
   const cplx<R>* q = static_cast<const cplx<R>*>(a.q);
   double acc[2] = {0.0, 0.0};
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
@@ -790,11 +773,7 @@ __global__ void __launch_bounds__(kRedThreads) k_pcg_update(KrylovArgs a, SpecId
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const long long k = e + c * S;
-      const cplx<R> pv = p[k], qv = q[k];
-      cplx<R> xv = x[k];
-      xv.x += alpha * pv.x;
-      xv.y += alpha * pv.y;
-      x[k] = xv;
+      const cplx<R> qv = q[k];
       cplx<R> rr = r[k];
       rr.x -= alpha * qv.x;
       rr.y -= alpha * qv.y;
@@ -836,25 +815,25 @@ __global__ void __launch_bounds__(kRedThreads) k_fin_update(KrylovArgs a, int nb
   }
 }
 
+// The x update of the last iteration that ran (earlier ones happen in the
+// fused p-update pass of the next iteration).  Runs whatever `done` says; no
+// iteration ran when it == 0.
 template <typename R, int NC>
-__global__ void __launch_bounds__(256) k_pcg_pupdate(KrylovArgs a, SpecIdx ix) {
-  if (a.sv->done) return;
+__global__ void __launch_bounds__(256) k_pcg_xfinal(KrylovArgs a) {
+  if (a.sv->it == 0) return;
   const long long S = (long long)a.n * a.n * (a.n / 2);
-  const R beta = R(a.sv->beta);
-  const cplx<R>* r = static_cast<const cplx<R>*>(a.r);
-  cplx<R>* p = static_cast<cplx<R>*>(a.p);
+  const R alpha = R(a.sv->alpha);
+  cplx<R>* x = static_cast<cplx<R>*>(a.x);
+  const cplx<R>* p = static_cast<const cplx<R>*>(a.p);
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= S) return;
-  int kx, ky, kz;
-  ix.decode(e, kx, ky, kz);
-  cplx<R> rv[NC], zv[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) rv[c] = r[e + c * S];
-  apply_prec<R, NC>(rv, zv, kx, ky, kz, a.cs, a.pc);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const cplx<R> pv = p[e + c * S];
-    p[e + c * S] = {zv[c].x + beta * pv.x, zv[c].y + beta * pv.y};
+    cplx<R> xv = x[e + c * S];
+    xv.x += alpha * pv.x;
+    xv.y += alpha * pv.y;
+    x[e + c * S] = xv;
   }
 }
 
@@ -906,14 +885,6 @@ void launch_pcg_start(const KrylovArgs& a, int zero_x, hipStream_t st) {
   hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kRedThreads), 0, st, a.sv, a.partials, nb);
 }
 
-template <typename R>
-void launch_pcg_pq(const KrylovArgs& a, hipStream_t st) {
-  const SpecIdx ix = make_idx(a.n);
-  const int nb = red_blocks(spec_count(a.n));
-  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_pq<R, NCC>), dim3(nb), dim3(kRedThreads), 0, st, a, ix));
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kRedThreads), 0, st, a.sv, a.partials, nb, kPartialsPerBlock);
-}
-
 void launch_fin_alpha(SolveScalars* sv, const double* part, int nb, int stride, hipStream_t st) {
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kRedThreads), 0, st, sv, part, nb, stride);
 }
@@ -927,11 +898,10 @@ void launch_pcg_update(const KrylovArgs& a, hipStream_t st) {
 }
 
 template <typename R>
-void launch_pcg_pupdate(const KrylovArgs& a, hipStream_t st) {
-  const SpecIdx ix = make_idx(a.n);
+void launch_pcg_xfinal(const KrylovArgs& a, hipStream_t st) {
   const long long S = spec_count(a.n);
-  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_pupdate<R, NCC>), dim3((unsigned)((S + 255) / 256)),
-                                                 dim3(256), 0, st, a, ix));
+  TUMOR_NC_DISPATCH(a.ncomp, hipLaunchKernelGGL((k_pcg_xfinal<R, NCC>), dim3((unsigned)((S + 255) / 256)),
+                                                 dim3(256), 0, st, a));
 }
 
 template <typename R>
@@ -947,9 +917,8 @@ void launch_precond(const KrylovArgs& a, const void* in, void* out, hipStream_t 
   template void launch_residual<R>(const KrylovArgs&, void*, hipStream_t);                 \
   template void launch_cn_residual<R>(const KrylovArgs&, const void*, const void*, hipStream_t); \
   template void launch_pcg_start<R>(const KrylovArgs&, int, hipStream_t);                  \
-  template void launch_pcg_pq<R>(const KrylovArgs&, hipStream_t);                          \
   template void launch_pcg_update<R>(const KrylovArgs&, hipStream_t);                      \
-  template void launch_pcg_pupdate<R>(const KrylovArgs&, hipStream_t);                     \
+  template void launch_pcg_xfinal<R>(const KrylovArgs&, hipStream_t);                      \
   template void launch_precond<R>(const KrylovArgs&, const void*, void*, hipStream_t);
 TUMOR_INST_KRYLOV(double)
 TUMOR_INST_KRYLOV(float)

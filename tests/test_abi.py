@@ -76,11 +76,13 @@ def test_workspace_size_and_validation(lib):
     bmx = tm.workspace_bytes(tm.make_config(64, "mixed"))
     assert b64 > 60 * 64 ** 3 * 8 and bmx > b64
     for bad in (dict(n=100), dict(n=8), dict(n=1024), dict(n=32, dt=0.0), dict(n=32, rtol_diff=1.0),
-                dict(n=32, max_it=0), dict(n=32, flags=0x10), dict(n=32, model="nonsense"),
-                dict(n=32, model="single", flags=0x7 | 0x8)):
+                dict(n=32, max_it=0), dict(n=32, flags=0x20), dict(n=32, model="nonsense"),
+                dict(n=32, model="single", flags=0x7 | 0x8), dict(n=32, flags=0x7 | 0x8 | 0x10)):
         with pytest.raises(tm.TumorError) as e:
             tm.workspace_bytes(tm.make_config(**bad))
         assert e.value.code == tm.EINVAL
+    assert tm.workspace_bytes(tm.make_config(32, flags=tm.F_DEFAULT | tm.F_STRANG)) == tm.workspace_bytes(
+        tm.make_config(32))
     cfg = tm.make_config(32)
     cfg.reserved[1] = 3
     with pytest.raises(tm.TumorError):
