@@ -27,3 +27,33 @@ def say(*a):
 
 def to_dev(torch, a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to("cuda").contiguous()
+
+
+def shift_case(torch, inp, P, precision, flags, half):
+    """A context on `inp` prepared for the exact-shift identity of a split step:
+    i = 0.2 p, n = 0.1 p, uniform oxygen (between o_hyp and o_inv) and edema,
+    u = 0 and a uniform u_prev such that the velocity moves half[a] cells per
+    half-step along axis a; coefficients refreshed."""
+    import paper_1810_05370_amd as tm
+    n = inp["n"]
+    sim = tm.from_inputs(inp, P, precision=precision, flags=flags)
+    dev = "cuda"
+    p = sim.get("p")
+    sim.set("i", 0.2 * p)
+    sim.set("n", 0.1 * p)
+    sim.set("o", torch.full((n, n, n), P["o_hyp"] + 0.75 * (P["o_inv"] - P["o_hyp"]), dtype=torch.float64,
+                            device=dev))
+    sim.set("l", torch.full((n, n, n), 0.05, dtype=torch.float64, device=dev))
+    h = 2.0 * np.pi / n
+    u_prev = torch.empty((3, n, n, n), dtype=torch.float64, device=dev)
+    for a in range(3):
+        u_prev[a].fill_(-2.0 * half[a] * h)     # u = 0: dt v = 2 half h
+    sim.set("u", torch.zeros((3, n, n, n), dtype=torch.float64, device=dev))
+    sim.set("u_prev", u_prev)
+    sim.refresh()
+    return sim
+
+
+def roll_cells(t, cells):
+    """Shift a [..][z][y][x] tensor by cells = (cx, cy, cz) (periodic)."""
+    return t.roll((cells[2], cells[1], cells[0]), dims=(-3, -2, -1))

@@ -14,7 +14,7 @@ import pytest
 
 import paper_1810_05370_amd as tm
 import synthetic
-from gpu_common import need_gpu, rel_l2, say
+from gpu_common import need_gpu, rel_l2, roll_cells, say, shift_case
 from oracle import model, model_single
 
 pytestmark = pytest.mark.gpu
@@ -96,29 +96,6 @@ def test_reported_cfl_is_the_full_step_one():
     b.close()
 
 
-def _shift_case(torch, inp, P, precision, flags, half, n):
-    sim = tm.from_inputs(inp, P, precision=precision, flags=flags)
-    dev = "cuda"
-    p = sim.get("p")
-    sim.set("i", 0.2 * p)
-    sim.set("n", 0.1 * p)
-    sim.set("o", torch.full((n, n, n), P["o_hyp"] + 0.75 * (P["o_inv"] - P["o_hyp"]), dtype=torch.float64,
-                            device=dev))
-    sim.set("l", torch.full((n, n, n), 0.05, dtype=torch.float64, device=dev))
-    h = 2.0 * np.pi / n
-    u_prev = torch.empty((3, n, n, n), dtype=torch.float64, device=dev)
-    for a in range(3):
-        u_prev[a].fill_(-2.0 * half[a] * h)     # u = 0: dt v = 2 half h
-    sim.set("u", torch.zeros((3, n, n, n), dtype=torch.float64, device=dev))
-    sim.set("u_prev", u_prev)
-    sim.refresh()
-    return sim
-
-
-def _roll(t, cells):
-    return t.roll((cells[2], cells[1], cells[0]), dims=(-3, -2, -1))
-
-
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_exact_shift_commutes_with_the_symmetric_step_at_256(precision):
     torch = need_gpu()
@@ -127,11 +104,11 @@ def test_exact_shift_commutes_with_the_symmetric_step_at_256(precision):
     P = synthetic.params(delta_p=60.0)
     say(f"generating the 256^3 three-seed inputs ({precision})")
     inp = synthetic.workload_inputs("seeds3_n256")
-    ref = _shift_case(torch, inp, P, precision, tm.F_ELASTICITY | tm.F_EDEMA, half, n)
+    ref = shift_case(torch, inp, P, precision, tm.F_ELASTICITY | tm.F_EDEMA, half)
     s_ref = ref.step(1)
     want = {k: ref.get(k) for k in SPECIES + ("u",)}
     ref.close()
-    sym = _shift_case(torch, inp, P, precision, STRANG, half, n)
+    sym = shift_case(torch, inp, P, precision, STRANG, half)
     if precision == "fp64":
         sym.force_iterations(_iters(s_ref))      # same stopping point as the reference
     s_sym = sym.step(1)
@@ -139,7 +116,7 @@ def test_exact_shift_commutes_with_the_symmetric_step_at_256(precision):
     tol = 1e-10 if precision == "fp64" else 1e-5
     for k in SPECIES + ("u",):
         got = sym.get(k)
-        exp = _roll(want[k], half if k in ("o", "l") else total)
+        exp = roll_cells(want[k], half if k in ("o", "l") else total)
         err = float((got - exp).norm() / exp.norm())
         say(f"  {k}: relL2 {err:.2e}")
         assert err < tol, k
