@@ -333,6 +333,24 @@ __device__ __forceinline__ void row_c2r(cplx<R> (&v)[8], const cplx<R>* __restri
   fft_block<R, L, true, 2>(v, lds, t, tw);
 }
 
+// u = C2R(U) and s = C2R(i w_x U + D) from a single read of U.
+template <typename R, int N>
+__device__ __forceinline__ void row_c2r_two(cplx<R> (&u)[8], cplx<R> (&s)[8], const cplx<R>* __restrict__ U,
+                                            const cplx<R>* __restrict__ D, const LdsRowView<R>& lds, int t,
+                                            const cplx<R>* __restrict__ tw) {
+  constexpr int L = N / 2, TP = L / 8;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = t + TP * j;
+    const int kp = (L - k) & (L - 1);
+    const cplx<R> A = U[k], B = U[kp];
+    u[j] = c2r_pre<R, N>(A, B, k, tw);
+    s[j] = c2r_pre<R, N>(cadd(ciw(A, R(xwave<N>(k))), D[k]), cadd(ciw(B, R(xwave<N>(kp))), D[kp]), k, tw);
+  }
+  fft_block<R, L, true, 2>(u, lds, t, tw);
+  fft_block<R, L, true, 2>(s, lds, t, tw);
+}
+
 template <typename R, int N>
 __device__ __forceinline__ void store_row(cplx<R>* __restrict__ dst, const cplx<R> (&v)[8], int t) {
   constexpr int TP = N / 16;
@@ -420,12 +438,60 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
 #pragma unroll
   for (int f = 0; f < 8; ++f) out[f] = static_cast<cplx<R>*>(a.out[f]) + soff;
 
-  {
-    // Group A: diagonal stresses and eta u_x.  The trace div u is formed in
-    // spectral space (i w_x U_x + dy u_y + dz u_z, one transform), so that each
-    // diagonal stress is then built and transformed on its own: at most three
-    // rows are live at a time, which lets the kernel reach 3 (FP32) or 2 (FP64)
-    // waves per SIMD.
+  if constexpr (sizeof(R) == 4) {
+    // Group A (FP32): diagonal stresses and eta u_x.  d_x u_x, d_y u_y, d_z u_z
+    // are transformed once each and the trace and the three stresses are
+    // formed in one pointwise step, so mu, lambda, d_y u_y and d_z u_z are read
+    // once.  One row at a time is parked in LDS (each thread its own values:
+    // no barrier), which keeps at most two rows in registers.
+    __shared__ cplx<R> stash[RowCfg<N>::THREADS * 8];
+    cplx<R> ex[8], ey[8];
+    row_c2r<R, N>(ex, in[0], true, nullptr, lds, t, tw);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) stash[j * RC::THREADS + threadIdx.x] = ex[j];
+    asm volatile("" ::: "memory");  // reload from LDS: ex is not kept live in registers
+    row_c2r<R, N>(ey, in[4], false, nullptr, lds, t, tw);
+    {
+      cplx<R> ez[8];
+      row_c2r<R, N>(ez, in[7], false, nullptr, lds, t, tw);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int p = t + TP * j;
+        const cplx<R> m = mu[p], l = lam[p];
+        ex[j] = stash[j * RC::THREADS + threadIdx.x];
+        const cplx<R> ax = {ex[j].x * invV, ex[j].y * invV}, by = {ey[j].x * invV, ey[j].y * invV},
+                      cz = {ez[j].x * invV, ez[j].y * invV};
+        const cplx<R> lt = {l.x * (ax.x + by.x + cz.x), l.y * (ax.y + by.y + cz.y)};
+        stash[j * RC::THREADS + threadIdx.x] = {R(2) * m.x * ax.x + lt.x, R(2) * m.y * ax.y + lt.y};
+        ey[j] = {R(2) * m.x * by.x + lt.x, R(2) * m.y * by.y + lt.y};
+        ez[j] = {R(2) * m.x * cz.x + lt.x, R(2) * m.y * cz.y + lt.y};
+      }
+      asm volatile("" ::: "memory");
+      row_r2c<R, N>(ez, lds, t, tw);
+      store_row<R, N>(out[7], ez, t);
+    }
+    row_r2c<R, N>(ey, lds, t, tw);
+    store_row<R, N>(out[4], ey, t);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ex[j] = stash[j * RC::THREADS + threadIdx.x];
+    row_r2c<R, N>(ex, lds, t, tw);
+    cplx<R> ux[8];
+    row_c2r<R, N>(ux, in[0], false, nullptr, lds, t, tw);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const cplx<R> e = eta[t + TP * j];
+      ux[j] = {e.x * ux[j].x * invV, e.y * ux[j].y * invV};
+    }
+    row_r2c<R, N>(ux, lds, t, tw);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ux[j] = csub(ux[j], iwx<R, N>(ex[j], t + TP * j));
+    store_row<R, N>(out[0], ux, t);
+  } else {
+    // Group A (FP64, where a parked row would cost a wave per SIMD of LDS
+    // occupancy): the trace div u is formed in spectral space (i w_x U_x +
+    // dy u_y + dz u_z, one transform), so that each diagonal stress is then
+    // built and transformed on its own: at most three rows are live at a time,
+    // which lets the kernel reach 2 waves per SIMD.
     const ColTerm trace_terms[3] = {{0, SYM_IW, 1.0}, {4, SYM_ONE, 1.0}, {7, SYM_ONE, 1.0}};
     cplx<R> tr[8];
     row_c2r_terms<R, N>(tr, 3, trace_terms, a.in, soff, lds, t, tw);
@@ -472,8 +538,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
     const cplx<R>* U = g == 0 ? in[1] : in[2];
     const cplx<R>* D = g == 0 ? in[3] : in[6];
     cplx<R> u[8], s[8];
-    row_c2r<R, N>(u, U, false, nullptr, lds, t, tw);
-    row_c2r<R, N>(s, U, true, D, lds, t, tw);
+    row_c2r_two<R, N>(u, s, U, D, lds, t, tw);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int p = t + TP * j;
