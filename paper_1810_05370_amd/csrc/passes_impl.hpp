@@ -74,8 +74,10 @@ __device__ void store_dot_partial(double v, double* part) {
 }
 
 // ---------------------------------------------------------------- col pass
+// The FP32 inner-product variant is held to 128 VGPRs (4 waves per SIMD) so
+// that two of its 8-wave blocks share a CU, like the other FP32 passes.
 template <typename R, int N, bool INV, bool DOT = false>
-__global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
+__global__ void __launch_bounds__((ColCfg<N, R>::THREADS), ((DOT && sizeof(R) == 4) ? 4 : 1))
     k_col_pass(ColProg prog, long long fstride, long long astride, const cplx<R>* __restrict__ twg) {
   if (prog.skip && *prog.skip) return;
   using Cfg = ColCfg<N, R>;
