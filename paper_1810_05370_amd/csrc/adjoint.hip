@@ -5,11 +5,14 @@
 //   k_coef_adj  : Lame / screening mixture -> species adjoints, d/d lame_scale
 //   k_s0_adj    : step coefficients K, rho -> w, g, f and d/d(k_w, k_g, k_f, rho)
 //   k_force_adj : pointwise part of the force b = zeta tanh(tau) G tau
-//   k_sl_adj    : semi-Lagrangian transport (interpolation transpose by FP64
-//                 atomic scatter, velocity sensitivity through X and X*)
+//   k_sl_adj    : semi-Lagrangian transport (interpolation transpose summed
+//                 per brick in LDS, then FP64 atomics; velocity sensitivity
+//                 through X and X*)
 //   k_ic_adj    : projections onto the Gaussian initial-condition basis
 // Parameter sums use deterministic block partials totalled by a one-block kernel.
+#include <climits>
 #include <cmath>
+#include <stdexcept>
 
 #include "adjoint.hpp"
 
@@ -266,8 +269,12 @@ __device__ __forceinline__ void gather_grad(const Stencil& s, const double* cons
   const int m = n - 1;
 #pragma unroll
   for (int f = 0; f < NF; ++f) val[f] = gx[f] = gy[f] = gz[f] = 0.0;
+  // the 16 (z, y) rows stay rolled: unrolled, they hold far more loads in
+  // flight than the register file has room for
+#pragma unroll 1
   for (int c = 0; c < 4; ++c) {
     const long long zo = (long long)((s.iz + c - 1) & m) * n * n;
+#pragma unroll 1
     for (int b = 0; b < 4; ++b) {
       const long long yo = zo + (long long)((s.iy + b - 1) & m) * n;
       const double wzy = s.wz[c] * s.wy[b], dzy = s.dz[c] * s.wy[b], wzdy = s.wz[c] * s.dy[b];
@@ -291,8 +298,10 @@ __device__ __forceinline__ void gather_grad(const Stencil& s, const double* cons
 template <int NF>
 __device__ __forceinline__ void scatter(const Stencil& s, double* const (&out)[NF], const double (&val)[NF], int n) {
   const int m = n - 1;
+#pragma unroll 1
   for (int c = 0; c < 4; ++c) {
     const long long zo = (long long)((s.iz + c - 1) & m) * n * n;
+#pragma unroll 1
     for (int b = 0; b < 4; ++b) {
       const long long yo = zo + (long long)((s.iy + b - 1) & m) * n;
       const double wzy = s.wz[c] * s.wy[b];
@@ -307,12 +316,86 @@ __device__ __forceinline__ void scatter(const Stencil& s, double* const (&out)[N
   }
 }
 
+// One 16 x 4 x 4 brick of arrival voxels per 256-thread block (n >= 16, so the
+// bricks tile the grid), bricks laid out x fastest, and consecutive block
+// indices spread over the 8 XCDs so that each XCD sweeps a contiguous slab.
+constexpr int kSlAdjBX = 16, kSlAdjBY = 4, kSlAdjBZ = 4;
+// LDS accumulation tile for the transposed interpolation (doubles).  A brick's
+// stencils span (16 + 3 + dx) x (4 + 3 + dy) x (4 + 3 + dz) nodes, dx, dy, dz
+// the spread of its departure cells; 2048 covers a spread of 2 cells per axis.
+constexpr int kSlAdjTile = 2048;
+
+// Transposed interpolation of NF values per voxel of a block: each tap's
+// contribution w * val[f] goes to the node it was read from.  Contributions
+// are first summed in an LDS tile over the bounding box of the block's
+// stencils (LDS atomics), then each tile node is added to global memory with
+// one atomic, one field at a time.  A block whose box exceeds the tile adds
+// every contribution with a global atomic instead.  Called by all threads of
+// the block (block-uniform control flow).
+template <int NF>
+__device__ void scatter_tiled(const Stencil& s, double* const (&out)[NF], const double (&val)[NF], int n,
+                              double* tile, int* box) {
+  __syncthreads();  // every thread is done with box from a previous call
+  if (threadIdx.x == 0) {
+    box[0] = box[1] = box[2] = INT_MAX;
+    box[3] = box[4] = box[5] = INT_MIN;
+  }
+  __syncthreads();
+  atomicMin(&box[0], s.ix);
+  atomicMin(&box[1], s.iy);
+  atomicMin(&box[2], s.iz);
+  atomicMax(&box[3], s.ix);
+  atomicMax(&box[4], s.iy);
+  atomicMax(&box[5], s.iz);
+  __syncthreads();
+  const int x0 = box[0], y0 = box[1], z0 = box[2];
+  const long long DX = (long long)box[3] - x0 + 4, DY = (long long)box[4] - y0 + 4, DZ = (long long)box[5] - z0 + 4;
+  if (DX * DY * DZ > kSlAdjTile) {
+    scatter<NF>(s, out, val, n);
+    return;
+  }
+  const int m = n - 1;
+  const int dxn = (int)DX, dyn = (int)DY, cnt = (int)(DX * DY * DZ);
+  // tile coordinates of the stencil's first node (x0 - 1, y0 - 1, z0 - 1 is the tile origin)
+  const int bx = s.ix - x0, by = s.iy - y0, bz = s.iz - z0;
+  for (int f = 0; f < NF; ++f) {
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) tile[k] = 0.0;
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const double wzy = s.wz[c] * s.wy[b];
+        const int row = ((bz + c) * dyn + (by + b)) * dxn + bx;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) atomicAdd(&tile[row + a], wzy * s.wx[a] * val[f]);
+      }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+      const double t = tile[k];
+      if (t != 0.0) {
+        const int tx = k % dxn, ty = (k / dxn) % dyn, tz = k / (dxn * dyn);
+        const long long idx =
+            ((long long)((z0 - 1 + tz) & m) * n + ((y0 - 1 + ty) & m)) * n + ((x0 - 1 + tx) & m);
+        unsafeAtomicAdd(out[f] + idx, t);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void __launch_bounds__(256) k_sl_adj(SLAdjArgs a) {
+  __shared__ double tile[kSlAdjTile];
+  __shared__ int box[6];
   const int n = a.n_grid;
-  const long long V = (long long)n * n * n;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= V) return;
-  const int jx = (int)(v % n), jy = (int)((v / n) % n), jz = (int)(v / ((long long)n * n));
+  const int nbx = n / kSlAdjBX, nby = n / kSlAdjBY;
+  const int nb = (int)gridDim.x;
+  const int blk = (int)(blockIdx.x % 8) * (nb / 8) + (int)(blockIdx.x / 8);
+  const int jx = (blk % nbx) * kSlAdjBX + (int)(threadIdx.x % kSlAdjBX);
+  const int jy = ((blk / nbx) % nby) * kSlAdjBY + (int)((threadIdx.x / kSlAdjBX) % kSlAdjBY);
+  const int jz = (blk / (nbx * nby)) * kSlAdjBZ + (int)(threadIdx.x / (kSlAdjBX * kSlAdjBY));
+  const long long v = ((long long)jz * n + jy) * n + jx;
   const double s = a.s, dt = a.dt;
   const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v], d0 = a.div[v];
   // X* and v(X*)
@@ -348,7 +431,7 @@ __global__ void __launch_bounds__(256) k_sl_adj(SLAdjArgs a) {
     Jb[2] += bar[k] * qz[k];
   }
   double* const outs[7] = {a.out[0], a.out[1], a.out[2], a.out[3], a.out[4], a.out[5], a.divb};
-  scatter<7>(st, outs, bar, n);
+  scatter_tiled<7>(st, outs, bar, n, tile, box);
   unsafeAtomicAdd(a.divb + v, ddirect);
   // X = x - s/2 (v + v*), v* = I[v](X*), X* = x - s v
   double vsb[3], vown[3];
@@ -367,7 +450,7 @@ __global__ void __launch_bounds__(256) k_sl_adj(SLAdjArgs a) {
 #pragma unroll
   for (int b = 0; b < 3; ++b) vown[b] += -s * Jsb[b];
   double* const vb[3] = {a.vb[0], a.vb[1], a.vb[2]};
-  scatter<3>(st_s, vb, vsb, n);
+  scatter_tiled<3>(st_s, vb, vsb, n, tile, box);
 #pragma unroll
   for (int b = 0; b < 3; ++b) unsafeAtomicAdd(a.vb[b] + v, vown[b]);
 }
@@ -436,8 +519,11 @@ void launch_xpay(long long V, const double* x, double coef, const double* y, dou
   hipLaunchKernelGGL(k_xpay, dim3(pw_blocks(V)), dim3(256), 0, st, V, x, coef, y, out);
 }
 void launch_sl_adj(const SLAdjArgs& a, hipStream_t st) {
-  const long long V = (long long)a.n_grid * a.n_grid * a.n_grid;
-  hipLaunchKernelGGL(k_sl_adj, dim3(pw_blocks(V)), dim3(256), 0, st, a);
+  const int n = a.n_grid;
+  if (n < 16 || (n & (n - 1)) != 0) throw std::runtime_error("k_sl_adj: grid size must be a power of two >= 16");
+  // one 16 x 4 x 4 brick per block; n^3 / 256 is a multiple of 8 for n >= 16
+  const long long nb = (long long)n * n * n / (kSlAdjBX * kSlAdjBY * kSlAdjBZ);
+  hipLaunchKernelGGL(k_sl_adj, dim3((unsigned)nb), dim3(kSlAdjBX * kSlAdjBY * kSlAdjBZ), 0, st, a);
 }
 int ic_adj_blocks(int n) { return rblocks((long long)n * n * n); }
 void launch_ic_adj(int n, const double* ic, int n_ic, const double* lam_p, double* part, double* out,
