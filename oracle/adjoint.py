@@ -380,13 +380,20 @@ def loss(P, grid, st, tau_target):
     return 0.5 * grid.h ** 3 * float(((tau - tau_target) ** 2).sum())
 
 
-def gradient(P, inputs, steps, tau_target, cfg=None):
-    """Loss and its gradient with respect to (rho, k_w, k_g, k_f, lame_scale, ic weights)."""
+def gradient(P, inputs, steps, tau_target, cfg=None, u0=None, u_prev0=None):
+    """Loss and its gradient with respect to (rho, k_w, k_g, k_f, lame_scale, ic weights).
+
+    u0, u_prev0: optional initial displacements (default zero), held fixed;
+    the returned adjoint state holds their adjoints in lam["u"], lam["u_prev"]."""
     c = dict(model.DEFAULT_CFG)
     if cfg:
         c.update(cfg)
     st = model.init_state(P, inputs["n"], inputs["wm"], inputs["gm"], inputs["csf"], inputs["centers"],
                           inputs["sigmas"], inputs["weights"], inputs.get("bg"))
+    if u0 is not None:
+        st.u = np.array(u0, dtype=np.float64)
+    if u_prev0 is not None:
+        st.u_prev = np.array(u_prev0, dtype=np.float64)
     grid = st.grid
     tapes = []
     for k in range(steps):

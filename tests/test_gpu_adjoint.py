@@ -22,10 +22,14 @@ ORACLE_CFG = dict(rtol_diff=1e-13, rtol_elast=1e-13, rtol_adj=1e-13, max_it=2000
 SLOTS = ("p", "i", "n", "o", "l", "g", "w", "f")
 
 
-def _gpu_gradient(inp, P, steps, target, ckpt, precision="fp64", rtol=1e-12):
+def _gpu_gradient(inp, P, steps, target, ckpt, precision="fp64", rtol=1e-12, u0=None, u_prev0=None):
     torch = need_gpu()
     sim = tm.from_inputs(inp, P, precision=precision, rtol_diff=rtol, rtol_elast=rtol, max_it=2000,
                          flags=tm.F_DEFAULT | tm.F_ADJOINT)
+    if u0 is not None:
+        sim.set("u", torch.as_tensor(u0).cuda())
+    if u_prev0 is not None:
+        sim.set("u_prev", torch.as_tensor(u_prev0).cuda())
     sim.record(steps, ckpt)
     sim.step(steps)
     n = inp["n"]
@@ -93,6 +97,53 @@ def test_adjoint_matches_oracle_32_hypoxic():
     L, gr, gw, lam_o = adj.gradient(P, inp, steps, target, ORACLE_CFG)
     lam_g, grad_g = _gpu_gradient(inp, P, steps, target, 3)
     _compare(lam_g, grad_g, lam_o, gr, gw, 1e-8, "fp64 n=32")
+
+
+def _brick_boxes(X, n, bx=16, by=4, bz=4):
+    """Node count of the stencil bounding box of every bx x by x bz brick of
+    arrival voxels, for departure points X (grid-index units, [z][y][x])."""
+    base = [np.floor(a).astype(np.int64) for a in X]
+    out = []
+    for z0 in range(0, n, bz):
+        for y0 in range(0, n, by):
+            for x0 in range(0, n, bx):
+                sl = (slice(z0, z0 + bz), slice(y0, y0 + by), slice(x0, x0 + bx))
+                ext = [int(b[sl].max() - b[sl].min() + 4) for b in base]
+                out.append(ext[0] * ext[1] * ext[2])
+    return np.array(out)
+
+
+def test_adjoint_with_a_large_shear_velocity():
+    """A divergence-free shear displacement history of up to 2.5 cells per step
+    (v_y varies with x and z, v_z with x and y): in most bricks of arrival
+    voxels the stencils spread over more nodes than the transposed
+    interpolation's LDS tile (2048) holds, and the scatter takes the
+    direct-atomic path; in the others, the tile path.  Both must match the
+    oracle."""
+    from oracle import transport
+    from oracle.spectral import Grid
+    steps = 2
+    n = 16
+    P, inp, target = _case("lattice_n128", n, steps, dict(delta_p=60.0))
+    g = Grid(n)
+    x = g.axis()
+    Z, Y, X0 = np.meshgrid(x, x, x, indexing="ij")
+    cells = 2.5
+    disp = np.zeros((3, n, n, n))
+    # phases keep every zero of the field off the grid nodes: a departure point
+    # exactly on a node sits where the tricubic interpolant's gradient (the
+    # velocity sensitivity) jumps, and rounding picks either side
+    disp[1] = g.h * cells * 0.5 * (1 + np.cos(Z + 0.1)) * np.sin(X0 + 0.1)
+    disp[2] = g.h * cells * 0.5 * (1 + np.cos(Y + 0.2)) * np.sin(X0 + 1.0)
+    u0, u_prev0 = np.zeros_like(disp), -disp
+    dt = model.DEFAULT_CFG["dt"]
+    X = transport.departure_points(g, (u0 - u_prev0) / dt, dt)
+    boxes = _brick_boxes(X, n)
+    say(f"brick stencil boxes: {int((boxes > 2048).sum())} of {boxes.size} exceed the tile")
+    assert (boxes > 2048).any() and (boxes <= 2048).any()
+    L, gr, gw, lam_o = adj.gradient(P, inp, steps, target, ORACLE_CFG, u0=u0, u_prev0=u_prev0)
+    lam_g, grad_g = _gpu_gradient(inp, P, steps, target, 1, u0=u0, u_prev0=u_prev0)
+    _compare(lam_g, grad_g, lam_o, gr, gw, 1e-8, "fp64 large shear")
 
 
 def test_mixed_precision_adjoint():
