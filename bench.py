@@ -334,8 +334,9 @@ def main():
         summarize_counters(fd, wd, int(mib), COUNTERS_FILE)
         return
     if args.gpus != 1:
-        print("bench.py: this implementation runs one simulation on exactly one GPU; "
-              "--gpus must be 1 (multi-GPU runs are not part of this build)", file=sys.stderr)
+        print("bench.py: one simulation runs on exactly one GPU, so --gpus must be 1 "
+              "(several GPUs would run independent simulations, which this benchmark does not time)",
+              file=sys.stderr)
         sys.exit(2)
     if args.steps < 1 or args.warmup < 0:
         print("bench.py: --steps must be >= 1 and --warmup >= 0", file=sys.stderr)
