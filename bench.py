@@ -325,7 +325,10 @@ def main():
                          "coupled transport/elasticity loses stability after about 9 steps at 256^3, and its "
                          "gradient stops being smooth (central differences disagree) near step 8; over 4 steps "
                          "the adjoint gradient matches central differences")
-    ap.add_argument("--ckpt-every", type=int, default=2)
+    ap.add_argument("--ckpt-every", type=int, default=1,
+                    help="checkpoint interval of the forward+adjoint form; 1 keeps every state and the step "
+                         "intermediates on the tape (about 14 GB at 256^3 for 4 steps), so the reverse sweep "
+                         "recomputes no forward step")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_MIB"),
                     help="no GPU work: write the HBM counter summary from two rocprofv3 --pmc output folders")
     args = ap.parse_args()

@@ -233,11 +233,16 @@ int tumor_diagnose(tumor_ctx* ctx, double threshold, double* fields, tumor_diagn
  * future work, Sec. 5).  Requires a context created with TUMOR_F_ADJOINT.
  *
  * tumor_record(ctx, nsteps, ckpt_every, tape, tape_bytes): the next nsteps
- * calls of tumor_step are recorded.  The full state (species and both
- * displacements) is checkpointed every ckpt_every (>= 1) steps into `tape`
- * (device, 256-byte aligned, >= tumor_tape_bytes(cfg, nsteps, ckpt_every));
- * the tape also holds a window of ckpt_every states that the reverse sweep
- * recomputes from the nearest checkpoint.
+ * calls of tumor_step are recorded into `tape` (device, 256-byte aligned,
+ * >= tumor_tape_bytes(cfg, nsteps, ckpt_every)).
+ *   ckpt_every = 1: every state and, per step, the 8 intermediate fields the
+ *     transposes read are kept ((nsteps + 1) * 14 + nsteps * 8 fields of N^3
+ *     doubles); the reverse sweep recomputes no forward step.
+ *   ckpt_every = K > 1: the full state (species and both displacements) is
+ *     checkpointed every K steps; the tape also holds a window of K states
+ *     that the reverse sweep recomputes from the nearest checkpoint, plus one
+ *     recomputed forward step per reversed step (about 14 (nsteps / K + K)
+ *     fields). 
  *
  * tumor_adjoint_step(ctx, adj, grad): reverses the latest recorded step not
  * yet reversed.  adj: device, 14 N^3 values, the adjoint of the state

@@ -1118,6 +1118,30 @@ size_t slot_doubles(long long V) { return (size_t)(14 * V); }
 size_t slot_bytes(long long V) { return (slot_doubles(V) * sizeof(double) + 255) & ~size_t(255); }
 
 double* tape_slot(Ctx& c, int k) { return reinterpret_cast<double*>(c.tape + (size_t)k * slot_bytes(c.V)); }
+
+// With a checkpoint every step (K = 1) the tape keeps every state X^0 .. X^T
+// (T + 1 state slots) and, per step, the intermediates the transposes read:
+// the transported p, i, n, g, w and the diffusion outputs i'', o', l'.  The
+// reverse sweep then restores them instead of recomputing the step.
+constexpr int kMidFields = 8;
+size_t mid_bytes(long long V) { return ((size_t)kMidFields * V * sizeof(double) + 255) & ~size_t(255); }
+double* mid_slot(Ctx& c, int m) {
+  return reinterpret_cast<double*>(c.tape + (size_t)(c.rec_nsteps + 1) * slot_bytes(c.V) + (size_t)m * mid_bytes(c.V));
+}
+void save_mid(Ctx& c, double* slot) {
+  enum { P, I, N, O, L, G, W, F };
+  const size_t fb = c.V * sizeof(double);
+  const double* src[kMidFields] = {c.G[P], c.G[I], c.G[N], c.G[G], c.G[W], c.Rdd[0], c.Rdd[1], c.Rdd[2]};
+  for (int k = 0; k < kMidFields; ++k)
+    HIPCHECK(hipMemcpyAsync(slot + k * c.V, src[k], fb, hipMemcpyDeviceToDevice, c.st));
+}
+void load_mid(Ctx& c, const double* slot) {
+  enum { P, I, N, O, L, G, W, F };
+  const size_t fb = c.V * sizeof(double);
+  double* dst[kMidFields] = {c.G[P], c.G[I], c.G[N], c.G[G], c.G[W], c.Rdd[0], c.Rdd[1], c.Rdd[2]};
+  for (int k = 0; k < kMidFields; ++k)
+    HIPCHECK(hipMemcpyAsync(dst[k], slot + k * c.V, fb, hipMemcpyDeviceToDevice, c.st));
+}
 int n_ckpt(int nsteps, int K) { return (nsteps + K - 1) / K; }
 
 void save_state(Ctx& c, double* slot) {
@@ -1541,12 +1565,17 @@ int tumor_step(tumor_ctx* ctx, int32_t nsteps, tumor_step_stats* last) {
     tumor_step_stats st;
     Ctx& c = *ctx;
     for (int s = 0; s < nsteps; ++s) {
+      int m = -1;  // index of the step being recorded
       if (c.rec_active && c.rev_done == 0 && c.rec_steps < c.rec_nsteps) {
         if (c.rec_steps % c.rec_K == 0) save_state(c, tape_slot(c, c.rec_steps / c.rec_K));
-        c.rec_steps++;
+        m = c.rec_steps++;
       }
       do_step(c, &st, status);
       if (status == TUMOR_ENAN) break;
+      if (m >= 0 && c.rec_K == 1) {
+        save_mid(c, mid_slot(c, m));
+        if (m == c.rec_nsteps - 1) save_state(c, tape_slot(c, c.rec_nsteps));
+      }
     }
     if (last && nsteps > 0) *last = st;
     return status;
@@ -1797,6 +1826,7 @@ int tumor_tape_bytes(const tumor_config* cfg, int32_t nsteps, int32_t ckpt_every
   const long long V = (long long)cfg->n * cfg->n * cfg->n;
   const int K = std::min(ckpt_every, nsteps);
   *bytes = (size_t)(n_ckpt(nsteps, K) + K) * slot_bytes(V);
+  if (K == 1) *bytes += (size_t)nsteps * mid_bytes(V);
   return TUMOR_OK;
 }
 
@@ -1838,6 +1868,26 @@ int tumor_adjoint_step(tumor_ctx* ctx, double* adj, double* grad) {
     Ctx& c = *ctx;
     const int m = c.rec_steps - 1 - c.rev_done;
     const int K = c.rec_K;
+    if (K == 1 && c.rec_steps == c.rec_nsteps) {
+      // Every state and the step's intermediates are on the tape: restore the
+      // context as the forward step m left it, then transpose.
+      const double* x0 = tape_slot(c, m);
+      if (c.flags & TUMOR_F_ADVECTION) {
+        // the step's velocity (u^m - u^{m-1}) / dt, from the state it started from
+        cplx<double>* u = c.U;
+        cplx<double>* up = c.Up;
+        c.U = reinterpret_cast<cplx<double>*>(const_cast<double*>(x0) + 8 * c.V);
+        c.Up = reinterpret_cast<cplx<double>*>(const_cast<double*>(x0) + 11 * c.V);
+        velocity(c);
+        c.U = u;
+        c.Up = up;
+      }
+      load_state(c, tape_slot(c, m + 1));  // post-step species and displacements, refreshed coefficients
+      load_mid(c, mid_slot(c, m));
+      adjoint_core(c, x0, adj, m, grad);
+      c.rev_done++;
+      return TUMOR_OK;
+    }
     const int nck = n_ckpt(c.rec_nsteps, K);
     if (c.win_start < 0 || m < c.win_start || m >= c.win_start + K) {
       // rebuild the window of states X^ws .. X^m from checkpoint m / K

@@ -146,6 +146,23 @@ def test_adjoint_with_a_large_shear_velocity():
     _compare(lam_g, grad_g, lam_o, gr, gw, 1e-8, "fp64 large shear")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_stored_intermediates_equal_recomputation(precision):
+    """A checkpoint every step keeps every state and the step intermediates on
+    the tape, so the reverse sweep recomputes nothing; checkpoints every 3
+    steps recompute them.  The forward step is deterministic, so both sweeps
+    see the same intermediates; they differ only by the order in which the
+    transposed interpolation's FP64 atomics add up (which also varies from run
+    to run), i.e. at the rounding level."""
+    steps = 3
+    P, inp, target = _case("lattice_n128", 16, steps, dict(delta_p=60.0))
+    lam1, g1 = _gpu_gradient(inp, P, steps, target, 1, precision=precision)
+    lam3, g3 = _gpu_gradient(inp, P, steps, target, 3, precision=precision)
+    e_lam, e_g = rel_l2(lam1, lam3), rel_l2(g1, g3)
+    say(f"{precision}: adjoint relL2 {e_lam:.2e}, gradient relL2 {e_g:.2e}")
+    assert e_lam < 1e-12 and e_g < 1e-12
+
+
 def test_mixed_precision_adjoint():
     steps = 3
     P, inp, target = _case("lattice_n128", 16, steps, dict(delta_p=60.0))
