@@ -156,7 +156,7 @@ def test_adjoint_gradient_matches_central_differences(precision):
 
     t0 = tau(P0)
     sim = tm.from_inputs(inp, P0, precision=precision, flags=tm.F_DEFAULT | tm.F_ADJOINT)
-    sim.record(steps, 2)
+    sim.record(steps, 1)     # every state and intermediate kept, as bench.py runs it
     sim.step(steps)
     lam = torch.zeros((14, N, N, N), dtype=torch.float64, device="cuda")
     for k in range(3):
