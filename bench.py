@@ -146,12 +146,14 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_256.json")
 
 
 def kernel_sources_digest():
-    """SHA-256 over the HIP sources and headers of the library (sorted by name)."""
+    """SHA-256 over the library's device sources: every HIP source and header
+    (sorted by name) except engine.hip, which holds host-side control only (no
+    kernel and no launch configuration)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1810_05370_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
+        if f.endswith((".hip", ".hpp")) and f != "engine.hip":
             h.update(f.encode())
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()
