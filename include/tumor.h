@@ -88,6 +88,9 @@ typedef enum {
  *   oxygen: -delta_p p + delta_s (o_heal - o)(g + w)                    (e:ox)
  *   edema:  delta_e i/(i + delta_half)(1 - i) - delta_l l             (e:edema)
  *   eta    = eta_tumor (p+i+n) + eta_healthy (g+w+f) + eta_bg bg  (e:screening)
+ *            (all >= 0, not all zero: without screening the operator vanishes on
+ *            the modes whose derivative symbols are all zero -- the mean and
+ *            the Nyquist corner modes -- and the system has no solution)
  *   mu, lambda from (E_s, nu_s) of w, g, f, the tumour p+i+n and the
  *           background bg (e:lame), both multiplied by lame_scale
  *   force  b = zeta tanh(p+n) grad(p+n)                   (e:forcingfunction)

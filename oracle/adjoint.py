@@ -161,11 +161,9 @@ def cn_adjoint(grid, K, Kbar, dt, c_minus, c_plus, cbar_plus, rtol, max_it):
     return cbar_minus, Kb
 
 
-def elasticity_adjoint(grid, coef, u, ubar, rtol, max_it, singular=False):
+def elasticity_adjoint(grid, coef, u, ubar, rtol, max_it):
     """Adjoint of u = A^-1 (-b): returns (b_bar, mu_bar, lambda_bar, eta_bar)."""
     rhs = np.array(ubar, dtype=np.float64)
-    if singular:
-        rhs = rhs - rhs.mean(axis=(1, 2, 3), keepdims=True)
     y = _solve(lambda x: solvers.elasticity_op(grid, coef["mu"], coef["lam"], coef["eta"], x),
                lambda r: solvers.elasticity_precond(grid, coef["mubar"], coef["lambar"], coef["etabar"], r),
                rhs, rtol, max_it)
@@ -291,8 +289,7 @@ def adjoint_step(P, grid, tape, lam, grad, cfg=None):
 
     # S6 (elasticity) and the force
     if c["elasticity"]:
-        singular = P["eta_tumor"] == 0.0 and P["eta_healthy"] == 0.0
-        bbar, mub, lamb, etab = elasticity_adjoint(grid, c1, tape["u_new"], u_bar_new, rt, mi, singular)
+        bbar, mub, lamb, etab = elasticity_adjoint(grid, c1, tape["u_new"], u_bar_new, rt, mi)
         taub = force_adjoint(grid, P["zeta"], p1 + n1, bbar)
         bar["p"] += taub
         bar["n"] += taub

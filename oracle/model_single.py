@@ -59,11 +59,10 @@ def step(st: State, cfg=None, forced=None):
     ie, re_ = 0, 0.0
     if c["elasticity"]:
         force = rx.elastic_force(grid, P["zeta"], c1, z)
-        singular = P["eta_tumor"] == 0.0 and P["eta_healthy"] == 0.0
         u_new, ie, re_, ok = solvers.solve_elasticity(
             grid, coef["mu"], coef["lam"], coef["eta"],
             (coef["mubar"], coef["lambar"], coef["etabar"]), force, st.u,
-            c["rtol_elast"], c["max_it"], fx[3], singular)
+            c["rtol_elast"], c["max_it"], fx[3])
         conv &= ok
     else:
         u_new = st.u.copy()

@@ -145,17 +145,18 @@ def elasticity_precond(grid, mubar, lambar, etabar, r):
     return out
 
 
-def solve_elasticity(grid, mu, lam, eta, means, force, u0, rtol, max_it,
-                     fixed_iters=None, singular=False):
+def solve_elasticity(grid, mu, lam, eta, means, force, u0, rtol, max_it, fixed_iters=None):
     """Solve (eta - L) u = -b by PCG from u0.  ``means`` = (mubar, lambar, etabar).
 
-    ``singular`` (no screening anywhere): the mean of the right-hand side is
-    projected out, since rigid translations are then in the null space.
+    The screening must be positive somewhere (e:screening).  Without it the
+    operator vanishes on every mode whose derivative symbols are all zero (the
+    mean and the Nyquist corner modes, where the dropped Nyquist derivative
+    leaves no stiffness) while the force has content there: no solution.
     """
+    if not np.any(np.asarray(eta) > 0.0):
+        raise ValueError("the elasticity needs screening: eta > 0 somewhere")
     mubar, lambar, etabar = means
     rhs = -np.asarray(force, dtype=np.float64)
-    if singular:
-        rhs = rhs - rhs.mean(axis=(1, 2, 3), keepdims=True)
     return pcg(lambda x: elasticity_op(grid, mu, lam, eta, x),
                lambda r: elasticity_precond(grid, mubar, lambar, etabar, r),
                rhs, u0, rtol, max_it, fixed_iters)

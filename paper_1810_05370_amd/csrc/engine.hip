@@ -612,7 +612,6 @@ tumor::KrylovArgs kargs(Ctx& c, int ncomp, cplx<R>* x, tumor::SolveScalars* sv, 
   a.pc.h = h;
   a.pc.kind = kind;
   a.scale32 = 1.0;
-  a.pc.singular = (kind == tumor::PREC_ELAST && c.prm.eta_tumor == 0.0 && c.prm.eta_healthy == 0.0) ? 1 : 0;
   return a;
 }
 
@@ -896,6 +895,9 @@ int check_params(const tumor_params* p) {
   for (double nu : nus)
     if (!(nu > -1.0 && nu < 0.5)) return TUMOR_EINVAL;
   if (p->eta_tumor < 0.0 || p->eta_healthy < 0.0 || p->eta_bg < 0.0) return TUMOR_EINVAL;
+  // e:screening: without any screening the elasticity operator vanishes on the
+  // modes whose derivative symbols are all zero, and the force has content there
+  if (p->eta_tumor == 0.0 && p->eta_healthy == 0.0 && p->eta_bg == 0.0) return TUMOR_EINVAL;
   return TUMOR_OK;
 }
 

@@ -107,7 +107,6 @@ enum PrecKind : int { PREC_DIFF = 0, PREC_ELAST = 1 };
 struct PrecConsts {
   double h;  // dt/2 for CN
   int kind;  // PrecKind
-  int singular;  // elasticity without screening: zero the mean mode
 };
 
 struct KrylovArgs {

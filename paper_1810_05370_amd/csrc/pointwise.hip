@@ -662,7 +662,6 @@ __device__ __forceinline__ double wdot(cplx<R> a, cplx<R> b, int kx) {
 }
 
 // r = b - ax (ax nullable); bb = ||b||^2, rr = ||r||^2 (Parseval-weighted).
-// Without screening (singular elasticity) the mean mode of b is dropped.
 template <typename R, int NC>
 __global__ void __launch_bounds__(kRedThreads) k_residual(KrylovArgs a, SpecIdx ix, cplx<float>* r32) {
   const long long S = (long long)a.n * a.n * (a.n / 2);
@@ -672,13 +671,11 @@ __global__ void __launch_bounds__(kRedThreads) k_residual(KrylovArgs a, SpecIdx 
   double acc[2] = {0.0, 0.0};
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
        e += (long long)gridDim.x * blockDim.x) {
-    int kx, ky, kz;
-    ix.decode(e, kx, ky, kz);
-    const bool drop = a.pc.singular && e == 0;
+    const int kx = (int)(e & ix.hmask);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const long long k = e + c * S;
-      const cplx<R> bv = drop ? czero<R>() : b[k];
+      const cplx<R> bv = b[k];
       const cplx<R> rv = ax ? csub(bv, ax[k]) : bv;
       r[k] = rv;
       if (r32) r32[k] = {float(a.scale32 * rv.x), float(a.scale32 * rv.y)};

@@ -125,6 +125,10 @@ def test_init_validates_arguments_before_the_device(lib):
     bad = synthetic.params(heaviside_eps=0.0)
     assert lib.tumor_init(ctypes.byref(ctx), ctypes.byref(cfg), ctypes.byref(tm.make_params(bad)), fake,
                           1 << 30, fake, fake, fake, 0, None, None, None, None) == tm.EINVAL
+    # no screening at all (e:screening): the elasticity system would have no solution
+    bad = synthetic.params(eta_tumor=0.0, eta_healthy=0.0, eta_bg=0.0)
+    assert lib.tumor_init(ctypes.byref(ctx), ctypes.byref(cfg), ctypes.byref(tm.make_params(bad)), fake,
+                          1 << 30, fake, fake, fake, 0, None, None, None, None) == tm.EINVAL
     # negative width of a tumour seed
     s = (ctypes.c_double * 1)(-0.3)
     c3 = (ctypes.c_double * 3)(1.0, 1.0, 1.0)

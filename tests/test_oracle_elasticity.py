@@ -63,6 +63,27 @@ def test_rigid_translation_has_no_elastic_response():
     assert np.max(np.abs(out)) < 1e-9
 
 
+def test_nyquist_corner_modes_need_screening():
+    """The spectral derivative drops the Nyquist mode, so on a field such as
+    (-1)^(jx + jz) every derivative vanishes: without screening the operator
+    maps it to zero (as it does a translation), and with screening it is eta u.
+    The force has content on such modes, so the solve requires eta > 0
+    somewhere and refuses eta = 0 everywhere."""
+    n = 12
+    g = Grid(n)
+    mu = 500 + 100 * synthetic.random_field(n, 1, 2.0)
+    lam = 2000 + 300 * synthetic.random_field(n, 2, 2.0)
+    j = np.arange(n)
+    corner = ((-1.0) ** (j[:, None, None] + j[None, None, :])) * np.ones((n, n, n))   # [z][y][x]: (-1)^(jz + jx)
+    U = np.stack([corner, 0.5 * corner, -corner])
+    zero = np.zeros((n, n, n))
+    assert np.max(np.abs(solvers.elasticity_op(g, mu, lam, zero, U))) < 1e-9
+    eta = np.full((n, n, n), 3.0)
+    assert np.max(np.abs(solvers.elasticity_op(g, mu, lam, eta, U) - 3.0 * U)) < 1e-9
+    with pytest.raises(ValueError):
+        solvers.solve_elasticity(g, mu, lam, zero, (mu.mean(), lam.mean(), 0.0), U, zero[None] * U, 1e-8, 50)
+
+
 @pytest.mark.parametrize("k", [(1, 0, 0), (1, 2, -1), (0, 3, 2)])
 def test_constant_coefficient_single_mode_closed_form(k):
     n = 16
