@@ -440,13 +440,16 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
 #pragma unroll
   for (int f = 0; f < 8; ++f) out[f] = static_cast<cplx<R>*>(a.out[f]) + soff;
 
+  // FP32: per-thread parking space for one row (each thread reads back only
+  // its own values, so no barrier is needed)
+  __shared__ cplx<R> stash[sizeof(R) == 4 ? RowCfg<N>::THREADS * 8 : 1];
+  (void)stash;
   if constexpr (sizeof(R) == 4) {
     // Group A (FP32): diagonal stresses and eta u_x.  d_x u_x, d_y u_y, d_z u_z
     // are transformed once each and the trace and the three stresses are
     // formed in one pointwise step, so mu, lambda, d_y u_y and d_z u_z are read
-    // once.  One row at a time is parked in LDS (each thread its own values:
-    // no barrier), which keeps at most two rows in registers.
-    __shared__ cplx<R> stash[RowCfg<N>::THREADS * 8];
+    // once.  One row at a time is parked in LDS, which keeps at most two rows
+    // in registers.
     cplx<R> ex[8], ey[8];
     row_c2r<R, N>(ex, in[0], true, nullptr, lds, t, tw);
 #pragma unroll
@@ -474,8 +477,13 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
     }
     row_r2c<R, N>(ey, lds, t, tw);
     store_row<R, N>(out[4], ey, t);
+    // the parking space now takes mu for the three shear groups, which then
+    // read it from LDS instead of global memory
 #pragma unroll
-    for (int j = 0; j < 8; ++j) ex[j] = stash[j * RC::THREADS + threadIdx.x];
+    for (int j = 0; j < 8; ++j) {
+      ex[j] = stash[j * RC::THREADS + threadIdx.x];
+      stash[j * RC::THREADS + threadIdx.x] = mu[t + TP * j];
+    }
     row_r2c<R, N>(ex, lds, t, tw);
     cplx<R> ux[8];
     row_c2r<R, N>(ux, in[0], false, nullptr, lds, t, tw);
@@ -544,7 +552,8 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int p = t + TP * j;
-      const cplx<R> m = mu[p], e = eta[p];
+      const cplx<R> m = sizeof(R) == 4 ? stash[j * RC::THREADS + threadIdx.x] : mu[p];
+      const cplx<R> e = eta[p];
       s[j] = {m.x * s[j].x * invV, m.y * s[j].y * invV};
       u[j] = {e.x * u[j].x * invV, e.y * u[j].y * invV};
     }
@@ -561,7 +570,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
     row_c2r<R, N>(s, in[5], false, nullptr, lds, t, tw);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const cplx<R> m = mu[t + TP * j];
+      const cplx<R> m = sizeof(R) == 4 ? stash[j * RC::THREADS + threadIdx.x] : mu[t + TP * j];
       s[j] = {m.x * s[j].x * invV, m.y * s[j].y * invV};
     }
     row_r2c<R, N>(s, lds, t, tw);
