@@ -465,20 +465,21 @@ void elast_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, const int* skip, const
               .in(1, in + S)
               .in(2, in + 2 * S)
               .out(A[0], {T1(0)})
-              .out(A[1], {T1(1)})
-              .out(A[2], {T1(2)})
               .out(A[3], {TW(0)})
+              .out(A[1], {T1(1)})
               .out(A[4], {TW(1)})
+              .out(A[2], {T1(2)})
               .out(A[5], {TW(2)})
               .skip(skip));
   Prog y;
   for (int k = 0; k < 6; ++k) y.in(k, A[k]);
+  // outputs that share a source are adjacent, so the pass loads each input once
   y.out(B[0], {T1(0)})
-      .out(B[1], {T1(1)})
-      .out(B[2], {T1(2)})
       .out(B[3], {TW(0)})
+      .out(B[1], {T1(1)})
       .out(B[4], {TW(1)})
-      .out(B[5], {T1(4), TW(2)})
+      .out(B[2], {T1(2)})
+      .out(B[5], {TW(2), T1(4)})
       .out(B[6], {T1(3)})
       .out(B[7], {T1(5)})
       .skip(skip);

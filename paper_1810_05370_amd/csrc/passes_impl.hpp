@@ -130,18 +130,16 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS), ((DOT && sizeof(R) ==
           acc[j].y += cf * v.y;
         }
       }
-      if (o + 1 < prog.nout) load_col(nxt, prog.term[o + 1][0].src);
+      // nxt still holds the raw column of term 0: an output that starts from
+      // the same source (and does not overwrite it) reuses it
+      if (o + 1 < prog.nout) {
+        const int ns = prog.term[o + 1][0].src;
+        if (ns != prog.term[o][0].src || prog.out[o] == prog.in[ns]) load_col(nxt, ns);
+      }
       fft_block<R, N, true, 1>(acc, lds, t, tw);
     } else {
 #pragma unroll
       for (int j = 0; j < 8; ++j) acc[j] = czero<R>();
-      if constexpr (DOT) {
-        // the inner-product operand at the output positions, loaded before the
-        // transforms so that its latency overlaps them
-        const cplx<R>* __restrict__ pp = static_cast<const cplx<R>*>(prog.dotp[o]);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) pdot[j] = pp[base + (long long)(t + TP * j) * astride];
-      }
       for (int q = 0; q < nt; ++q) {
         const ColTerm tm = prog.term[o][q];
         const R cf = R(tm.coef);
@@ -159,6 +157,13 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS), ((DOT && sizeof(R) ==
           acc[j].y += cf * v.y;
         }
       }
+    }
+    if constexpr (DOT) {
+      // the inner-product operand at the output positions, loaded after the
+      // transforms: held across them it would push the pass into spills
+      const cplx<R>* __restrict__ pp = static_cast<const cplx<R>*>(prog.dotp[o]);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) pdot[j] = pp[base + (long long)(t + TP * j) * astride];
     }
     cplx<R>* __restrict__ dst = static_cast<cplx<R>*>(prog.out[o]);
 #pragma unroll
@@ -585,16 +590,20 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdiff(XDiffArgs a, const
   const R invV = R(1.0) / (R(N) * R(N) * R(N));
   const cplx<R>* K = reinterpret_cast<const cplx<R>*>(static_cast<const R*>(a.K) + poff);
   const cplx<R>* C = static_cast<const cplx<R>*>(a.in[0]) + soff;
+  // K / N^3 for this row, loaded once for the three directions
+  cplx<R> kr[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const cplx<R> k = K[t + TP * j];
+    kr[j] = {k.x * invV, k.y * invV};
+  }
 #pragma unroll 1
   for (int d = 0; d < 3; ++d) {
     cplx<R> g[8];
     if (d == 0) row_c2r<R, N>(g, C, true, nullptr, lds, t, tw);
     else row_c2r<R, N>(g, static_cast<const cplx<R>*>(a.in[d]) + soff, false, nullptr, lds, t, tw);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const cplx<R> k = K[t + TP * j];
-      g[j] = {k.x * g[j].x * invV, k.y * g[j].y * invV};
-    }
+    for (int j = 0; j < 8; ++j) g[j] = {kr[j].x * g[j].x, kr[j].y * g[j].y};
     row_r2c<R, N>(g, lds, t, tw);
     if (d == 0) {
 #pragma unroll
