@@ -151,6 +151,7 @@ struct tumor_ctx {
   tumor::SolveScalars* hsv;
   tumor::CoefScalars* hcs;
   int pred[8];
+  int pred_in[8][3];  // mixed precision: inner iterations of outer pass 0, 1, >= 2
   int forced[4];
   bool has_forced;
   tumor::RefreshConsts fc;
@@ -618,11 +619,13 @@ tumor::KrylovArgs kargs(Ctx& c, int ncomp, cplx<R>* x, tumor::SolveScalars* sv, 
 
 // Plain PCG iterations after the residual r and its norms are in place.
 // `apply(p, q, skip)` computes q = A p.  Iterations are queued in chunks
-// (predicted count + 2, then 4) between scalar read-backs; kernels of an
-// iteration after convergence see the device `done` flag and return at once.
+// between scalar read-backs: first the predicted count + 1, then the count
+// that the residual reduction observed so far (from rr0, ||r||^2 at the
+// start) predicts, + 1.  Kernels of an iteration after convergence see the
+// device `done` flag and return at once, so the chunking changes only timing.
 template <typename R, typename Apply>
 int pcg_iterate(Ctx& c, tumor::KrylovArgs a, Apply apply, double thr2, int limit, bool fixed, int pred,
-                int zero_x, bool& conv, bool& bad) {
+                int zero_x, bool& conv, bool& bad, double rr0) {
   a.thr2 = thr2;
   a.limit = limit;
   a.fixed = fixed ? 1 : 0;
@@ -630,7 +633,7 @@ int pcg_iterate(Ctx& c, tumor::KrylovArgs a, Apply apply, double thr2, int limit
   const double vb = double(a.ncomp) * double(c.V) * sizeof(R);  // one Krylov vector
   timed(c, kc, (zero_x ? 3.0 : 2.0) * vb, [&] { tumor::launch_pcg_start<R>(a, zero_x, c.st); });
   int launched = 0;
-  int chunk = std::max(1, std::min(limit, pred + 2));
+  int chunk = fixed ? std::min(limit, 64) : std::max(1, std::min(limit, pred + 1));
   tumor::SolveScalars* sv = a.sv;
   const int* skip = &sv->done;
   for (;;) {
@@ -648,6 +651,16 @@ int pcg_iterate(Ctx& c, tumor::KrylovArgs a, Apply apply, double thr2, int limit
     timers_flush(c, c.hsv->it);
     if (c.hsv->done || launched >= limit) break;
     chunk = 4;
+    const double rr = c.hsv->rr;
+    const int it = c.hsv->it;
+    if (fixed) {
+      chunk = std::min(limit - launched, 64);
+    } else if (rr0 > 0.0 && it > 0 && rr > thr2 && rr < rr0 && std::isfinite(rr)) {
+      // mean log reduction per iteration so far; CG does not slow down late
+      const double per_it = std::log(rr / rr0) / it;
+      const double left = std::log(thr2 / rr) / per_it;
+      if (std::isfinite(left)) chunk = std::max(1, std::min(32, (int)std::ceil(left) + 1));
+    }
   }
   timed(c, kc, 3.0 * vb, [&] { tumor::launch_pcg_xfinal<R>(a, c.st); });
   conv = c.hsv->conv != 0;
@@ -690,7 +703,7 @@ SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cp
     bool conv = true, bad = false;
     const bool fixed = forced >= 0;
     const int limit = fixed ? forced : c.cfg.max_it;
-    if (limit > 0) so.it = pcg_iterate<double>(c, a, A64, thr2, limit, fixed, pred, 0, conv, bad);
+    if (limit > 0) so.it = pcg_iterate<double>(c, a, A64, thr2, limit, fixed, pred, 0, conv, bad, rr);
     so.conv = conv;
     so.bad = bad;
     so.relres = std::sqrt(c.hsv->rr / bb);
@@ -723,8 +736,9 @@ SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cp
     tumor::KrylovArgs ai = a32;
     ai.x = P.x;
     const double thr_in = in_rtol * in_rtol * rr * sc * sc;
-    inner_it = pcg_iterate<float>(c, ai, A32, thr_in, c.cfg.max_it, false,
-                                  std::max(1, c.pred[which >= 0 ? which : 3] / 2), 1, conv, bad);
+    int* pin = &c.pred_in[which >= 0 ? which : 3][std::min(so.outer, 2)];
+    inner_it = pcg_iterate<float>(c, ai, A32, thr_in, c.cfg.max_it, false, *pin, 1, conv, bad, rr * sc * sc);
+    if (conv) *pin = std::max(1, inner_it);
     total += inner_it;
     so.outer++;
     if (bad) {
@@ -1506,6 +1520,10 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
     c->hcs = static_cast<tumor::CoefScalars*>(h2);
     c->pred[0] = c->pred[1] = c->pred[2] = c->pred[4] = c->pred[5] = c->pred[6] = 6;
     c->pred[3] = c->pred[7] = 30;
+    for (int w = 0; w < 8; ++w) {
+      c->pred_in[w][0] = c->pred[w] * 2 / 3;
+      c->pred_in[w][1] = c->pred_in[w][2] = std::max(1, c->pred[w] / 3);
+    }
     c->cur_tag = -1;
     set_consts(*c);
     twiddles(*c);
