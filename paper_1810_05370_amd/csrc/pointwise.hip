@@ -465,26 +465,34 @@ __device__ __forceinline__ void block_max_cfl(double c, CoefScalars* cs) {
 // The copies turn the ten separate gathers of every stencil node into one
 // (v4) and one (q8) contiguous load.  The same pass publishes
 // max |dt v| / h with one atomic max per block.
+// Grid-stride over the nodes with at most kPackBlocks blocks: one atomic max
+// per block on a single address serialises, so the block count is kept small.
+constexpr int kPackBlocks = 2048;
 template <typename RC>
 __global__ void __launch_bounds__(256) k_sl_pack(SLArgs a, RC* __restrict__ v4, RC* __restrict__ q8,
                                                  CoefScalars* cs) {
-  const long long v = (long long)blockIdx.x * 256 + threadIdx.x;  // the grid covers V exactly
-  const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v];
-  RC* o = v4 + 4 * v;
-  o[0] = RC(vx);
-  o[1] = RC(vy);
-  o[2] = RC(vz);
-  o[3] = RC(0);
-  const double* const src[6] = {a.p, a.i, a.n, a.g, a.w, a.f};
-  RC* q = q8 + 8 * v;
+  const long long V = (long long)a.n_grid * a.n_grid * a.n_grid;
+  double sc[6];
 #pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    const double sc = sizeof(RC) == sizeof(double) ? 1.0 : pow2_scale(cs->qmax_bits[f]);
-    q[f] = RC(sc * src[f][v]);
+  for (int f = 0; f < 6; ++f) sc[f] = sizeof(RC) == sizeof(double) ? 1.0 : pow2_scale(cs->qmax_bits[f]);
+  const double* const src[6] = {a.p, a.i, a.n, a.g, a.w, a.f};
+  double vmax = 0.0;
+  for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < V; v += (long long)gridDim.x * 256) {
+    const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v];
+    RC* o = v4 + 4 * v;
+    o[0] = RC(vx);
+    o[1] = RC(vy);
+    o[2] = RC(vz);
+    o[3] = RC(0);
+    RC* q = q8 + 8 * v;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) q[f] = RC(sc[f] * src[f][v]);
+    q[6] = RC(a.div[v]);
+    q[7] = RC(0);
+    const double c = a.s * sqrt(vx * vx + vy * vy + vz * vz);
+    vmax = (c >= 0.0 && vmax >= 0.0) ? fmax(vmax, c) : -1.0;  // -1: a NaN was seen
   }
-  q[6] = RC(a.div[v]);
-  q[7] = RC(0);
-  block_max_cfl(a.s * sqrt(vx * vx + vy * vy + vz * vz), cs);
+  block_max_cfl(vmax, cs);
 }
 
 
@@ -607,7 +615,8 @@ void launch_sl(const SLArgs& a, void* packed, CoefScalars* cs, hipStream_t st) {
     const long long blocks = std::min<long long>(V / 256, 4096);
     hipLaunchKernelGGL(k_sl_scan, dim3((unsigned)blocks), dim3(256), 0, st, a, cs);
   }
-  hipLaunchKernelGGL(k_sl_pack<RC>, dim3((unsigned)(V / 256)), dim3(256), 0, st, a, v4, q8, cs);
+  hipLaunchKernelGGL(k_sl_pack<RC>, dim3((unsigned)std::min<long long>(V / 256, kPackBlocks)), dim3(256), 0, st, a,
+                     v4, q8, cs);
   // 64-voxel rows per wave (measured best for both types at 256^3); grids
   // below 64 use 16 x 4 x 4 bricks.
   if (a.n_grid >= 64)
