@@ -180,7 +180,10 @@ def summarize_counters(fetch_dir, write_dir, probe_mib, out_path):
     per-kernel summary read by counter_traffic().
 
     Each run's counter_collection CSV holds one row per dispatch; rows are
-    averaged per kernel (name up to the argument list).  The first torch
+    averaged per kernel (name up to the argument list) over the dispatches
+    that did work: longer than 20 us, since PCG launches queued after
+    convergence exit at once (the library's timers drop them too).  A kernel
+    with no such dispatch is averaged over all of them.  The first torch
     multiply dispatch is the copy probe (--copy-probe-mib): it reads and writes
     probe_mib MiB, which fixes the factor from counter KiB to bytes."""
     import csv
@@ -196,10 +199,15 @@ def summarize_counters(fetch_dir, write_dir, probe_mib, out_path):
         per = {}
         for r in rows:
             name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("tumor::", "").strip()
-            acc = per.setdefault(name, [0.0, 0])
+            worked = int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) >= 20000
+            acc = per.setdefault(name, [0.0, 0, 0.0, 0])
             acc[0] += float(r["Counter_Value"])
             acc[1] += 1
-        return float(probe["Counter_Value"]), {k: (v[0] / v[1], v[1]) for k, v in per.items()}
+            if worked:
+                acc[2] += float(r["Counter_Value"])
+                acc[3] += 1
+        return float(probe["Counter_Value"]), {
+            k: ((v[2] / v[3], v[3]) if v[3] else (v[0] / v[1], v[1])) for k, v in per.items()}
 
     probe_bytes = probe_mib * 2.0 ** 20
     pf, fetch = load(fetch_dir, "FETCH_SIZE")

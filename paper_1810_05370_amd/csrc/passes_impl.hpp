@@ -317,23 +317,25 @@ __device__ __forceinline__ void row_c2r_terms(cplx<R> (&v)[8], int nt, const Col
 }
 
 // Single-input C2R with an optional x-derivative and an optional added input.
+// `off`: the row's offset from a and b (lets a block-uniform base pointer
+// with a 32-bit lane offset address the row).
 template <typename R, int N>
 __device__ __forceinline__ void row_c2r(cplx<R> (&v)[8], const cplx<R>* __restrict__ a, bool iw_a,
                                         const cplx<R>* __restrict__ b, const LdsRowView<R>& lds, int t,
-                                        const cplx<R>* __restrict__ tw) {
+                                        const cplx<R>* __restrict__ tw, int off = 0) {
   constexpr int L = N / 2, TP = L / 8;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int k = t + TP * j;
     const int kp = (L - k) & (L - 1);
-    cplx<R> A = a[k], B = a[kp];
+    cplx<R> A = a[off + k], B = a[off + kp];
     if (iw_a) {
       A = ciw(A, R(xwave<N>(k)));
       B = ciw(B, R(xwave<N>(kp)));
     }
     if (b) {
-      A = cadd(A, b[k]);
-      B = cadd(B, b[kp]);
+      A = cadd(A, b[off + k]);
+      B = cadd(B, b[off + kp]);
     }
     v[j] = c2r_pre<R, N>(A, B, k, tw);
   }
@@ -344,25 +346,26 @@ __device__ __forceinline__ void row_c2r(cplx<R> (&v)[8], const cplx<R>* __restri
 template <typename R, int N>
 __device__ __forceinline__ void row_c2r_two(cplx<R> (&u)[8], cplx<R> (&s)[8], const cplx<R>* __restrict__ U,
                                             const cplx<R>* __restrict__ D, const LdsRowView<R>& lds, int t,
-                                            const cplx<R>* __restrict__ tw) {
+                                            const cplx<R>* __restrict__ tw, int off = 0) {
   constexpr int L = N / 2, TP = L / 8;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int k = t + TP * j;
     const int kp = (L - k) & (L - 1);
-    const cplx<R> A = U[k], B = U[kp];
+    const cplx<R> A = U[off + k], B = U[off + kp];
     u[j] = c2r_pre<R, N>(A, B, k, tw);
-    s[j] = c2r_pre<R, N>(cadd(ciw(A, R(xwave<N>(k))), D[k]), cadd(ciw(B, R(xwave<N>(kp))), D[kp]), k, tw);
+    s[j] = c2r_pre<R, N>(cadd(ciw(A, R(xwave<N>(k))), D[off + k]), cadd(ciw(B, R(xwave<N>(kp))), D[off + kp]), k,
+                         tw);
   }
   fft_block<R, L, true, 2>(u, lds, t, tw);
   fft_block<R, L, true, 2>(s, lds, t, tw);
 }
 
 template <typename R, int N>
-__device__ __forceinline__ void store_row(cplx<R>* __restrict__ dst, const cplx<R> (&v)[8], int t) {
+__device__ __forceinline__ void store_row(cplx<R>* __restrict__ dst, const cplx<R> (&v)[8], int t, int off = 0) {
   constexpr int TP = N / 16;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) dst[t + TP * j] = v[j];
+  for (int j = 0; j < 8; ++j) dst[off + t + TP * j] = v[j];
 }
 
 // iw_x (packed) times a row held in registers
@@ -435,15 +438,20 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
   if (a.skip && *a.skip) return;
   TUMOR_ROW_SETUP(N)
   const R invV = R(1.0) / (R(N) * R(N) * R(N));
+  // Rows are addressed as a block-uniform base plus a 32-bit lane offset ro
+  // (the physical coefficient rows hold N reals = L complex pairs), which
+  // keeps 64-bit per-lane addresses out of the registers.
+  const long long bs = (long long)blockIdx.x * RC::RW * L;
+  const int ro = rl * L;
   const cplx<R>* in[8];
 #pragma unroll
-  for (int f = 0; f < 8; ++f) in[f] = static_cast<const cplx<R>*>(a.in[f]) + soff;
-  const cplx<R>* mu = reinterpret_cast<const cplx<R>*>(static_cast<const R*>(a.mu) + poff);
-  const cplx<R>* lam = reinterpret_cast<const cplx<R>*>(static_cast<const R*>(a.lam) + poff);
-  const cplx<R>* eta = reinterpret_cast<const cplx<R>*>(static_cast<const R*>(a.eta) + poff);
+  for (int f = 0; f < 8; ++f) in[f] = static_cast<const cplx<R>*>(a.in[f]) + bs;
+  const cplx<R>* mu = static_cast<const cplx<R>*>(a.mu) + bs;
+  const cplx<R>* lam = static_cast<const cplx<R>*>(a.lam) + bs;
+  const cplx<R>* eta = static_cast<const cplx<R>*>(a.eta) + bs;
   cplx<R>* out[8];
 #pragma unroll
-  for (int f = 0; f < 8; ++f) out[f] = static_cast<cplx<R>*>(a.out[f]) + soff;
+  for (int f = 0; f < 8; ++f) out[f] = static_cast<cplx<R>*>(a.out[f]) + bs;
 
   // FP32: per-thread parking space for one row (each thread reads back only
   // its own values, so no barrier is needed)
@@ -456,18 +464,18 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
     // once.  One row at a time is parked in LDS, which keeps at most two rows
     // in registers.
     cplx<R> ex[8], ey[8];
-    row_c2r<R, N>(ex, in[0], true, nullptr, lds, t, tw);
+    row_c2r<R, N>(ex, in[0], true, nullptr, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) stash[j * RC::THREADS + threadIdx.x] = ex[j];
     asm volatile("" ::: "memory");  // reload from LDS: ex is not kept live in registers
-    row_c2r<R, N>(ey, in[4], false, nullptr, lds, t, tw);
+    row_c2r<R, N>(ey, in[4], false, nullptr, lds, t, tw, ro);
     {
       cplx<R> ez[8];
-      row_c2r<R, N>(ez, in[7], false, nullptr, lds, t, tw);
+      row_c2r<R, N>(ez, in[7], false, nullptr, lds, t, tw, ro);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int p = t + TP * j;
-        const cplx<R> m = mu[p], l = lam[p];
+        const cplx<R> m = mu[ro + p], l = lam[ro + p];
         ex[j] = stash[j * RC::THREADS + threadIdx.x];
         const cplx<R> ax = {ex[j].x * invV, ex[j].y * invV}, by = {ey[j].x * invV, ey[j].y * invV},
                       cz = {ez[j].x * invV, ez[j].y * invV};
@@ -478,29 +486,29 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
       }
       asm volatile("" ::: "memory");
       row_r2c<R, N>(ez, lds, t, tw);
-      store_row<R, N>(out[7], ez, t);
+      store_row<R, N>(out[7], ez, t, ro);
     }
     row_r2c<R, N>(ey, lds, t, tw);
-    store_row<R, N>(out[4], ey, t);
+    store_row<R, N>(out[4], ey, t, ro);
     // the parking space now takes mu for the three shear groups, which then
     // read it from LDS instead of global memory
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       ex[j] = stash[j * RC::THREADS + threadIdx.x];
-      stash[j * RC::THREADS + threadIdx.x] = mu[t + TP * j];
+      stash[j * RC::THREADS + threadIdx.x] = mu[ro + t + TP * j];
     }
     row_r2c<R, N>(ex, lds, t, tw);
     cplx<R> ux[8];
-    row_c2r<R, N>(ux, in[0], false, nullptr, lds, t, tw);
+    row_c2r<R, N>(ux, in[0], false, nullptr, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const cplx<R> e = eta[t + TP * j];
+      const cplx<R> e = eta[ro + t + TP * j];
       ux[j] = {e.x * ux[j].x * invV, e.y * ux[j].y * invV};
     }
     row_r2c<R, N>(ux, lds, t, tw);
 #pragma unroll
     for (int j = 0; j < 8; ++j) ux[j] = csub(ux[j], iwx<R, N>(ex[j], t + TP * j));
-    store_row<R, N>(out[0], ux, t);
+    store_row<R, N>(out[0], ux, t, ro);
   } else {
     // Group A (FP64, where a parked row would cost a wave per SIMD of LDS
     // occupancy): the trace div u is formed in spectral space (i w_x U_x +
@@ -511,40 +519,40 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
     cplx<R> tr[8];
     row_c2r_terms<R, N>(tr, 3, trace_terms, a.in, soff, lds, t, tw);
     cplx<R> sx[8];
-    row_c2r<R, N>(sx, in[0], true, nullptr, lds, t, tw);
+    row_c2r<R, N>(sx, in[0], true, nullptr, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int p = t + TP * j;
-      const cplx<R> m = mu[p], l = lam[p];
+      const cplx<R> m = mu[ro + p], l = lam[ro + p];
       tr[j] = {tr[j].x * invV, tr[j].y * invV};
       sx[j] = {R(2) * m.x * sx[j].x * invV + l.x * tr[j].x, R(2) * m.y * sx[j].y * invV + l.y * tr[j].y};
     }
     row_r2c<R, N>(sx, lds, t, tw);
     {
       cplx<R> ux[8];
-      row_c2r<R, N>(ux, in[0], false, nullptr, lds, t, tw);
+      row_c2r<R, N>(ux, in[0], false, nullptr, lds, t, tw, ro);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const cplx<R> e = eta[t + TP * j];
+        const cplx<R> e = eta[ro + t + TP * j];
         ux[j] = {e.x * ux[j].x * invV, e.y * ux[j].y * invV};
       }
       row_r2c<R, N>(ux, lds, t, tw);
 #pragma unroll
       for (int j = 0; j < 8; ++j) ux[j] = csub(ux[j], iwx<R, N>(sx[j], t + TP * j));
-      store_row<R, N>(out[0], ux, t);
+      store_row<R, N>(out[0], ux, t, ro);
     }
 #pragma unroll 1
     for (int d = 0; d < 2; ++d) {
       cplx<R> sd[8];
-      row_c2r<R, N>(sd, d == 0 ? in[4] : in[7], false, nullptr, lds, t, tw);
+      row_c2r<R, N>(sd, d == 0 ? in[4] : in[7], false, nullptr, lds, t, tw, ro);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int p = t + TP * j;
-        const cplx<R> m = mu[p], l = lam[p];
+        const cplx<R> m = mu[ro + p], l = lam[ro + p];
         sd[j] = {R(2) * m.x * sd[j].x * invV + l.x * tr[j].x, R(2) * m.y * sd[j].y * invV + l.y * tr[j].y};
       }
       row_r2c<R, N>(sd, lds, t, tw);
-      store_row<R, N>(d == 0 ? out[4] : out[7], sd, t);
+      store_row<R, N>(d == 0 ? out[4] : out[7], sd, t, ro);
     }
   }
   // Groups B and C: shear in the xy and xz planes with eta u_y, eta u_z.
@@ -553,33 +561,33 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
     const cplx<R>* U = g == 0 ? in[1] : in[2];
     const cplx<R>* D = g == 0 ? in[3] : in[6];
     cplx<R> u[8], s[8];
-    row_c2r_two<R, N>(u, s, U, D, lds, t, tw);
+    row_c2r_two<R, N>(u, s, U, D, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int p = t + TP * j;
-      const cplx<R> m = sizeof(R) == 4 ? stash[j * RC::THREADS + threadIdx.x] : mu[p];
-      const cplx<R> e = eta[p];
+      const cplx<R> m = sizeof(R) == 4 ? stash[j * RC::THREADS + threadIdx.x] : mu[ro + p];
+      const cplx<R> e = eta[ro + p];
       s[j] = {m.x * s[j].x * invV, m.y * s[j].y * invV};
       u[j] = {e.x * u[j].x * invV, e.y * u[j].y * invV};
     }
     row_r2c<R, N>(s, lds, t, tw);
-    store_row<R, N>(g == 0 ? out[3] : out[6], s, t);
+    store_row<R, N>(g == 0 ? out[3] : out[6], s, t, ro);
     row_r2c<R, N>(u, lds, t, tw);
 #pragma unroll
     for (int j = 0; j < 8; ++j) u[j] = csub(u[j], iwx<R, N>(s[j], t + TP * j));
-    store_row<R, N>(g == 0 ? out[1] : out[2], u, t);
+    store_row<R, N>(g == 0 ? out[1] : out[2], u, t, ro);
   }
   // Group D: shear in the yz plane.
   {
     cplx<R> s[8];
-    row_c2r<R, N>(s, in[5], false, nullptr, lds, t, tw);
+    row_c2r<R, N>(s, in[5], false, nullptr, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const cplx<R> m = sizeof(R) == 4 ? stash[j * RC::THREADS + threadIdx.x] : mu[t + TP * j];
+      const cplx<R> m = sizeof(R) == 4 ? stash[j * RC::THREADS + threadIdx.x] : mu[ro + t + TP * j];
       s[j] = {m.x * s[j].x * invV, m.y * s[j].y * invV};
     }
     row_r2c<R, N>(s, lds, t, tw);
-    store_row<R, N>(out[5], s, t);
+    store_row<R, N>(out[5], s, t, ro);
   }
 }
 
@@ -588,20 +596,23 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdiff(XDiffArgs a, const
   if (a.skip && *a.skip) return;
   TUMOR_ROW_SETUP(N)
   const R invV = R(1.0) / (R(N) * R(N) * R(N));
-  const cplx<R>* K = reinterpret_cast<const cplx<R>*>(static_cast<const R*>(a.K) + poff);
-  const cplx<R>* C = static_cast<const cplx<R>*>(a.in[0]) + soff;
+  // block-uniform bases and a 32-bit lane offset, as in k_xelast
+  const long long bs = (long long)blockIdx.x * RC::RW * L;
+  const int ro = rl * L;
+  const cplx<R>* K = static_cast<const cplx<R>*>(a.K) + bs;
+  const cplx<R>* C = static_cast<const cplx<R>*>(a.in[0]) + bs;
   // K / N^3 for this row, loaded once for the three directions
   cplx<R> kr[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const cplx<R> k = K[t + TP * j];
+    const cplx<R> k = K[ro + t + TP * j];
     kr[j] = {k.x * invV, k.y * invV};
   }
 #pragma unroll 1
   for (int d = 0; d < 3; ++d) {
     cplx<R> g[8];
-    if (d == 0) row_c2r<R, N>(g, C, true, nullptr, lds, t, tw);
-    else row_c2r<R, N>(g, static_cast<const cplx<R>*>(a.in[d]) + soff, false, nullptr, lds, t, tw);
+    if (d == 0) row_c2r<R, N>(g, C, true, nullptr, lds, t, tw, ro);
+    else row_c2r<R, N>(g, static_cast<const cplx<R>*>(a.in[d]) + bs, false, nullptr, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) g[j] = {kr[j].x * g[j].x, kr[j].y * g[j].y};
     row_r2c<R, N>(g, lds, t, tw);
@@ -609,7 +620,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdiff(XDiffArgs a, const
 #pragma unroll
       for (int j = 0; j < 8; ++j) g[j] = iwx<R, N>(g[j], t + TP * j);
     }
-    store_row<R, N>(static_cast<cplx<R>*>(a.out[d]) + soff, g, t);
+    store_row<R, N>(static_cast<cplx<R>*>(a.out[d]) + bs, g, t, ro);
   }
 }
 
