@@ -290,7 +290,7 @@ template <typename R, int N>
 __device__ __forceinline__ void row_c2r_terms(cplx<R> (&v)[8], int nt, const ColTerm* terms,
                                               const void* const* in, long long rowoff,
                                               const LdsRowView<R>& lds, int t,
-                                              const cplx<R>* __restrict__ tw) {
+                                              const cplx<R>* __restrict__ tw, int off = 0) {
   constexpr int L = N / 2, TP = L / 8;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -301,7 +301,7 @@ __device__ __forceinline__ void row_c2r_terms(cplx<R> (&v)[8], int nt, const Col
       const ColTerm tm = terms[q];
       const cplx<R>* __restrict__ src = static_cast<const cplx<R>*>(in[tm.src]) + rowoff;
       const R cf = R(tm.coef);
-      cplx<R> a = src[k], b = src[kp];
+      cplx<R> a = src[off + k], b = src[off + kp];
       if (tm.sym == SYM_IW) {
         a = ciw(a, R(xwave<N>(k)));
         b = ciw(b, R(xwave<N>(kp)));
@@ -513,18 +513,34 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
     // Group A (FP64, where a parked row would cost a wave per SIMD of LDS
     // occupancy): the trace div u is formed in spectral space (i w_x U_x +
     // dy u_y + dz u_z, one transform), so that each diagonal stress is then
-    // built and transformed on its own: at most three rows are live at a time,
-    // which lets the kernel reach 2 waves per SIMD.
+    // built and transformed on its own, which lets the kernel reach 2 waves
+    // per SIMD without spills.
     const ColTerm trace_terms[3] = {{0, SYM_IW, 1.0}, {4, SYM_ONE, 1.0}, {7, SYM_ONE, 1.0}};
     cplx<R> tr[8];
-    row_c2r_terms<R, N>(tr, 3, trace_terms, a.in, soff, lds, t, tw);
+    row_c2r_terms<R, N>(tr, 3, trace_terms, a.in, bs, lds, t, tw, ro);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) tr[j] = {tr[j].x * invV, tr[j].y * invV};
+    // s_yy and s_zz first, then s_xx (the trace's last use), then eta u_x:
+    // never more than two rows live besides the one being transformed
+#pragma unroll 1
+    for (int d = 0; d < 2; ++d) {
+      cplx<R> sd[8];
+      row_c2r<R, N>(sd, d == 0 ? in[4] : in[7], false, nullptr, lds, t, tw, ro);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int p = t + TP * j;
+        const cplx<R> m = mu[ro + p], l = lam[ro + p];
+        sd[j] = {R(2) * m.x * sd[j].x * invV + l.x * tr[j].x, R(2) * m.y * sd[j].y * invV + l.y * tr[j].y};
+      }
+      row_r2c<R, N>(sd, lds, t, tw);
+      store_row<R, N>(d == 0 ? out[4] : out[7], sd, t, ro);
+    }
     cplx<R> sx[8];
     row_c2r<R, N>(sx, in[0], true, nullptr, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int p = t + TP * j;
       const cplx<R> m = mu[ro + p], l = lam[ro + p];
-      tr[j] = {tr[j].x * invV, tr[j].y * invV};
       sx[j] = {R(2) * m.x * sx[j].x * invV + l.x * tr[j].x, R(2) * m.y * sx[j].y * invV + l.y * tr[j].y};
     }
     row_r2c<R, N>(sx, lds, t, tw);
@@ -540,19 +556,6 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
 #pragma unroll
       for (int j = 0; j < 8; ++j) ux[j] = csub(ux[j], iwx<R, N>(sx[j], t + TP * j));
       store_row<R, N>(out[0], ux, t, ro);
-    }
-#pragma unroll 1
-    for (int d = 0; d < 2; ++d) {
-      cplx<R> sd[8];
-      row_c2r<R, N>(sd, d == 0 ? in[4] : in[7], false, nullptr, lds, t, tw, ro);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int p = t + TP * j;
-        const cplx<R> m = mu[ro + p], l = lam[ro + p];
-        sd[j] = {R(2) * m.x * sd[j].x * invV + l.x * tr[j].x, R(2) * m.y * sd[j].y * invV + l.y * tr[j].y};
-      }
-      row_r2c<R, N>(sd, lds, t, tw);
-      store_row<R, N>(d == 0 ? out[4] : out[7], sd, t, ro);
     }
   }
   // Groups B and C: shear in the xy and xz planes with eta u_y, eta u_z.
