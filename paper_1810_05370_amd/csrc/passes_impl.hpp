@@ -9,23 +9,30 @@
 namespace tumor {
 
 // ----------------------------------------------------------------- geometry
-// Column tiles: TC adjacent kxp columns, TP = N/8 threads per column.
-template <int N, typename R>
+// Column tiles: TC adjacent kxp columns, TP = N/8 threads per column.  SEG
+// is the width in bytes of the contiguous segment a tile reads per position
+// along the transformed axis.  Measured at
+// 256^3: z passes, whose positions lie a whole plane apart, run faster with
+// 256-byte segments; FP32 y passes with 128-byte segments (and twice the
+// blocks).
+template <int N, typename R, int SEG = 128>
 struct ColCfg {
   static constexpr int TP = N / 8;
   static constexpr int TCW = 256 / TP;
-  static constexpr int TCMIN = 128 / (2 * (int)sizeof(R));  // 128-byte contiguous segments
-  static constexpr int TC0 = TCW < TCMIN ? TCMIN : TCW;
+  static constexpr int TCMIN = SEG / (2 * (int)sizeof(R));
+  static constexpr int TC00 = TCW < TCMIN ? TCMIN : TCW;
+  // at most 1024 threads per block, 512 in FP64 (whose passes need more
+  // than the 128 VGPRs a 16-wave block leaves)
+  static constexpr int MAXT = sizeof(R) == 8 ? 512 : 1024;
+  static constexpr int TC0 = TC00 * TP > MAXT ? MAXT / TP : TC00;
   static constexpr int TC = (N / 2) < TC0 ? (N / 2) : TC0;
   static constexpr int THREADS = TC * TP;
   static constexpr int LDS = N * TC + N / 8 + 1;
 };
 
+// Segment width of a column pass: 256 bytes for z passes and for FP64.
 template <typename R>
-struct ColCfgOf {
-  template <int N>
-  using T = ColCfg<N, R>;
-};
+constexpr int col_seg(int axis) { return (axis == 2 || sizeof(R) == 8) ? 256 : 128; }
 
 // Copy the twiddle table into LDS (all threads), so butterflies read LDS.
 template <typename R, int N>
@@ -76,11 +83,11 @@ __device__ void store_dot_partial(double v, double* part) {
 // ---------------------------------------------------------------- col pass
 // The FP32 inner-product variant is held to 128 VGPRs (4 waves per SIMD) so
 // that two of its 8-wave blocks share a CU, like the other FP32 passes.
-template <typename R, int N, bool INV, bool DOT = false>
-__global__ void __launch_bounds__((ColCfg<N, R>::THREADS), ((DOT && sizeof(R) == 4) ? 4 : 1))
+template <typename R, int N, bool INV, bool DOT, int SEG>
+__global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(R) == 4) ? 4 : 1))
     k_col_pass(ColProg prog, long long fstride, long long astride, const cplx<R>* __restrict__ twg) {
   if (prog.skip && *prog.skip) return;
-  using Cfg = ColCfg<N, R>;
+  using Cfg = ColCfg<N, R, SEG>;
   constexpr int TP = Cfg::TP, TC = Cfg::TC;
   __shared__ cplx<R> sbuf[Cfg::LDS];
   __shared__ cplx<R> stw[N];
@@ -184,10 +191,10 @@ __global__ void __launch_bounds__((ColCfg<N, R>::THREADS), ((DOT && sizeof(R) ==
 }
 
 template <typename R, int N, int NC>
-__global__ void __launch_bounds__((ColCfg<N, R>::THREADS))
+__global__ void __launch_bounds__((ColCfg<N, R, 256>::THREADS))
     k_zinv_pupdate(ZPUpdateArgs a, const cplx<R>* __restrict__ twg) {
   if (a.sv->done) return;
-  using Cfg = ColCfg<N, R>;
+  using Cfg = ColCfg<N, R, 256>;
   constexpr int TP = Cfg::TP, TC = Cfg::TC;
   constexpr long long C = N / 2;
   constexpr long long S = (long long)N * N * C;
@@ -655,35 +662,42 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xforce(XForceArgs a, con
 }
 
 // ---------------------------------------------------------------- launchers
-#define TUMOR_DISPATCH_N(n, BODY)                                    \
-  switch (n) {                                                       \
-    case 16: { constexpr int NN = 16; BODY; } break;                 \
-    case 32: { constexpr int NN = 32; BODY; } break;                 \
-    case 64: { constexpr int NN = 64; BODY; } break;                 \
-    case 128: { constexpr int NN = 128; BODY; } break;               \
-    case 256: { constexpr int NN = 256; BODY; } break;               \
-    case 512: { constexpr int NN = 512; BODY; } break;               \
+#define TUMOR_DISPATCH_N(n, ...)                                                     \
+  switch (n) {                                                                       \
+    case 16: { constexpr int NN = 16; __VA_ARGS__; } break;                          \
+    case 32: { constexpr int NN = 32; __VA_ARGS__; } break;                          \
+    case 64: { constexpr int NN = 64; __VA_ARGS__; } break;                          \
+    case 128: { constexpr int NN = 128; __VA_ARGS__; } break;                        \
+    case 256: { constexpr int NN = 256; __VA_ARGS__; } break;                        \
+    case 512: { constexpr int NN = 512; __VA_ARGS__; } break;                        \
     default: throw std::runtime_error("unsupported grid size " + std::to_string(n)); \
   }
 
+template <typename R, int NN, int SEG>
+void launch_col_pass_seg(int axis, bool inverse, const ColProg& prog, const cplx<R>* twp, hipStream_t st) {
+  using Cfg = ColCfg<NN, R, SEG>;
+  const long long C = NN / 2;
+  const long long fstride = axis == 1 ? (long long)NN * C : C;
+  const long long astride = axis == 1 ? C : (long long)NN * C;
+  dim3 grid(C / Cfg::TC, NN);
+  if (inverse)
+    hipLaunchKernelGGL((k_col_pass<R, NN, true, false, SEG>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride,
+                       astride, twp);
+  else if (prog.dsv) {
+    hipLaunchKernelGGL((k_col_pass<R, NN, false, true, SEG>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride,
+                       astride, twp);
+    launch_fin_alpha(prog.dsv, prog.dpart, (int)(grid.x * grid.y), 1, st);
+  } else
+    hipLaunchKernelGGL((k_col_pass<R, NN, false, false, SEG>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride,
+                       astride, twp);
+}
+
 template <typename R>
 void launch_col_pass(int n, int axis, bool inverse, const ColProg& prog, const void* tw, hipStream_t st) {
-  const long long C = n / 2;
-  const long long fstride = axis == 1 ? (long long)n * C : C;
-  const long long astride = axis == 1 ? C : (long long)n * C;
   const cplx<R>* twp = static_cast<const cplx<R>*>(tw);
   TUMOR_DISPATCH_N(n, {
-    using Cfg = typename ColCfgOf<R>::template T<NN>;
-    dim3 grid(C / Cfg::TC, NN);
-    if (inverse)
-      hipLaunchKernelGGL((k_col_pass<R, NN, true>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride, astride, twp);
-    else if (prog.dsv) {
-      hipLaunchKernelGGL((k_col_pass<R, NN, false, true>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride, astride,
-                         twp);
-      launch_fin_alpha(prog.dsv, prog.dpart, (int)(grid.x * grid.y), 1, st);
-    }
-    else
-      hipLaunchKernelGGL((k_col_pass<R, NN, false>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride, astride, twp);
+    if (col_seg<R>(axis) == 256) launch_col_pass_seg<R, NN, 256>(axis, inverse, prog, twp, st);
+    else launch_col_pass_seg<R, NN, 128>(axis, inverse, prog, twp, st);
   });
 }
 
@@ -691,7 +705,7 @@ template <typename R>
 void launch_zinv_pupdate(int n, int ncomp, const ZPUpdateArgs& a, const void* tw, hipStream_t st) {
   const cplx<R>* twp = static_cast<const cplx<R>*>(tw);
   TUMOR_DISPATCH_N(n, {
-    using Cfg = typename ColCfgOf<R>::template T<NN>;
+    using Cfg = ColCfg<NN, R, 256>;
     dim3 grid((NN / 2) / Cfg::TC, NN);
     if (ncomp == 1)
       hipLaunchKernelGGL((k_zinv_pupdate<R, NN, 1>), grid, dim3(Cfg::THREADS), 0, st, a, twp);
