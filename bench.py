@@ -31,8 +31,10 @@ CLASSES = ("colinv64", "colfwd64", "colinv32", "colfwd32", "xelast64", "xelast32
            "xother", "sl", "react", "krylov64", "krylov32", "zinvp64", "zinvp32", "coldot64", "coldot32")
 # classes that time exactly one kernel instantiation (so that a rocprofv3 summary
 # line can be matched to them); the others group several kernels
-SINGLE_KERNEL = ("colinv64", "colfwd64", "colinv32", "colfwd32", "coldot64", "coldot32", "xelast64", "xelast32",
-                 "xdiff64", "xdiff32", "react")
+# classes that time one kernel symbol (FP32 y and z passes are separate
+# instances of the column pass, so colinv32 and colfwd32 are not listed)
+SINGLE_KERNEL = ("colinv64", "colfwd64", "coldot64", "coldot32", "xelast64", "xelast32", "xdiff64", "xdiff32",
+                 "react")
 
 
 def log(*a):

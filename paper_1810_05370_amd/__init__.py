@@ -42,10 +42,12 @@ KERNEL_CLASSES = {"colinv64": 0, "colfwd64": 1, "colinv32": 2, "colfwd32": 3, "x
                   "xdiff64": 6, "xdiff32": 7, "xother": 8, "sl": 9, "react": 10, "krylov64": 11, "krylov32": 12,
                   "zinvp64": 13, "zinvp32": 14, "coldot64": 15, "coldot32": 16}
 # rocprofv3 kernel names of each class (for cross-checking event timings against traces)
-KERNEL_NAMES = {"colinv64": "k_col_pass<double, {n}, true, false>",
-                "colfwd64": "k_col_pass<double, {n}, false, false>",
-                "colinv32": "k_col_pass<float, {n}, true, false>", "colfwd32": "k_col_pass<float, {n}, false, false>",
-                "coldot64": "k_col_pass<double, {n}, false, true>", "coldot32": "k_col_pass<float, {n}, false, true>",
+KERNEL_NAMES = {"colinv64": "k_col_pass<double, {n}, true, false, 256>",
+                "colfwd64": "k_col_pass<double, {n}, false, false, 256>",
+                "colinv32": "k_col_pass<float, {n}, true, false, 128|256>",
+                "colfwd32": "k_col_pass<float, {n}, false, false, 128|256>",
+                "coldot64": "k_col_pass<double, {n}, false, true, 256>",
+                "coldot32": "k_col_pass<float, {n}, false, true, 256>",
                 "zinvp64": "k_zinv_pupdate<double, {n}, 1|3>", "zinvp32": "k_zinv_pupdate<float, {n}, 1|3>",
                 "xelast64": "k_xelast<double, {n}>", "xelast32": "k_xelast<float, {n}>",
                 "xdiff64": "k_xdiff<double, {n}>", "xdiff32": "k_xdiff<float, {n}>", "sl": "k_sl",
