@@ -150,14 +150,19 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_256.json")
 def kernel_sources_digest():
     """SHA-256 over the library's device sources: every HIP source and header
     (sorted by name) except engine.hip, which holds host-side control only (no
-    kernel and no launch configuration)."""
+    kernel and no launch configuration).  Comments and blank space are
+    stripped first, so only code changes invalidate the counters."""
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1810_05370_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".hip", ".hpp")) and f != "engine.hip":
+            text = open(os.path.join(csrc, f), encoding="utf-8").read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
             h.update(f.encode())
-            h.update(open(os.path.join(csrc, f), "rb").read())
+            h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -11,10 +11,9 @@ namespace tumor {
 // ----------------------------------------------------------------- geometry
 // Column tiles: TC adjacent kxp columns, TP = N/8 threads per column.  SEG
 // is the width in bytes of the contiguous segment a tile reads per position
-// along the transformed axis.  Measured at
-// 256^3: z passes, whose positions lie a whole plane apart, run faster with
-// 256-byte segments; FP32 y passes with 128-byte segments (and twice the
-// blocks).
+// along the transformed axis.  Measured at 256^3: z passes, whose positions
+// lie a whole plane apart, run faster with 256-byte segments; FP32 y passes
+// with 128-byte segments (and twice the blocks).
 template <int N, typename R, int SEG = 128>
 struct ColCfg {
   static constexpr int TP = N / 8;
@@ -81,8 +80,8 @@ __device__ void store_dot_partial(double v, double* part) {
 }
 
 // ---------------------------------------------------------------- col pass
-// The FP32 inner-product variant is held to 128 VGPRs (4 waves per SIMD) so
-// that two of its 8-wave blocks share a CU, like the other FP32 passes.
+// The FP32 inner-product variant is held to 128 VGPRs (4 waves per SIMD),
+// the occupancy of the other FP32 passes.
 template <typename R, int N, bool INV, bool DOT, int SEG>
 __global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(R) == 4) ? 4 : 1))
     k_col_pass(ColProg prog, long long fstride, long long astride, const cplx<R>* __restrict__ twg) {
