@@ -138,7 +138,19 @@ struct LdsRowView {
   __device__ __forceinline__ cplx<R> get(int pos) const { return buf[addr(pos)]; }
 };
 
-template <typename R, int L, bool INV, int TWS, int r, int p, bool LAST, typename View>
+// Twiddle m of a table of NT entries.  HALF: only the first NT/2 entries are
+// stored, and entry m >= NT/2 is the negative of entry m - NT/2.
+template <typename R, int NT, bool HALF>
+__device__ __forceinline__ cplx<R> twiddle(const cplx<R>* __restrict__ tw, int m) {
+  if constexpr (!HALF) {
+    return tw[m];
+  } else {
+    const cplx<R> w = tw[m & (NT / 2 - 1)];
+    return m < NT / 2 ? w : cplx<R>{-w.x, -w.y};
+  }
+}
+
+template <typename R, int L, bool INV, int TWS, int r, int p, bool LAST, typename View, bool HALF = false>
 __device__ __forceinline__ void fft_stage(cplx<R> (&v)[8], const View& lds, int t,
                                           const cplx<R>* __restrict__ tw) {
   constexpr int TP = L / 8;
@@ -157,7 +169,7 @@ __device__ __forceinline__ void fft_stage(cplx<R> (&v)[8], const View& lds, int 
     const int k = i & (p - 1);
 #pragma unroll
     for (int j = 1; j < r; ++j) {
-      cplx<R> w = tw[(j * k * (L / (p * r))) * TWS];
+      cplx<R> w = twiddle<R, L * TWS, HALF>(tw, (j * k * (L / (p * r))) * TWS);
       if (INV) w.y = -w.y;
       u[b * r + j] = cmul(u[b * r + j], w);
     }
@@ -175,7 +187,7 @@ __device__ __forceinline__ void fft_stage(cplx<R> (&v)[8], const View& lds, int 
 
 // In-place transform of the 8 register elements (positions t + TP*j).
 // All threads of the block must call it (it synchronises the block).
-template <typename R, int L, bool INV, int TWS, typename View>
+template <typename R, int L, bool INV, int TWS, typename View, bool HALF = false>
 __device__ __forceinline__ void fft_block(cplx<R> (&v)[8], const View& lds, int t,
                                           const cplx<R>* __restrict__ tw) {
   dft8<R, INV>(v);
@@ -185,10 +197,10 @@ __device__ __forceinline__ void fft_block(cplx<R> (&v)[8], const View& lds, int 
     __syncthreads();
     constexpr int r2 = Radix<L>::r2;
     if constexpr (Radix<L>::S == 2) {
-      fft_stage<R, L, INV, TWS, r2, 8, true>(v, lds, t, tw);
+      fft_stage<R, L, INV, TWS, r2, 8, true, View, HALF>(v, lds, t, tw);
     } else {
-      fft_stage<R, L, INV, TWS, r2, 8, false>(v, lds, t, tw);
-      fft_stage<R, L, INV, TWS, Radix<L>::r3, 8 * r2, true>(v, lds, t, tw);
+      fft_stage<R, L, INV, TWS, r2, 8, false, View, HALF>(v, lds, t, tw);
+      fft_stage<R, L, INV, TWS, Radix<L>::r3, 8 * r2, true, View, HALF>(v, lds, t, tw);
     }
     __syncthreads();
   }

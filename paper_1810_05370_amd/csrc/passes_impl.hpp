@@ -264,11 +264,11 @@ __device__ __forceinline__ cplx<R> c2r_pre(cplx<R> A, cplx<R> B, int k, const cp
 }
 
 // Packed R2C of the row held as v[j] = (x[2p], x[2p+1]), p = t + TP*j.
-template <typename R, int N>
+template <typename R, int N, bool HALF = false>
 __device__ __forceinline__ void row_r2c(cplx<R> (&v)[8], const LdsRowView<R>& lds, int t,
                                         const cplx<R>* __restrict__ tw) {
   constexpr int L = N / 2, TP = L / 8;
-  fft_block<R, L, false, 2>(v, lds, t, tw);
+  fft_block<R, L, false, 2, LdsRowView<R>, HALF>(v, lds, t, tw);
 #pragma unroll
   for (int j = 0; j < 8; ++j) lds.put(t + TP * j, v[j]);
   __syncthreads();
@@ -292,7 +292,7 @@ __device__ __forceinline__ void row_r2c(cplx<R> (&v)[8], const LdsRowView<R>& ld
 
 // Packed C2R: gathers sum_t coef * s_t(kx) * in_t at k and L-k, pre-processes,
 // inverse transforms; on return v[j] = N * (x[2p], x[2p+1]).
-template <typename R, int N>
+template <typename R, int N, bool HALF = false>
 __device__ __forceinline__ void row_c2r_terms(cplx<R> (&v)[8], int nt, const ColTerm* terms,
                                               const void* const* in, long long rowoff,
                                               const LdsRowView<R>& lds, int t,
@@ -319,13 +319,13 @@ __device__ __forceinline__ void row_c2r_terms(cplx<R> (&v)[8], int nt, const Col
     }
     v[j] = c2r_pre<R, N>(A, B, k, tw);
   }
-  fft_block<R, L, true, 2>(v, lds, t, tw);
+  fft_block<R, L, true, 2, LdsRowView<R>, HALF>(v, lds, t, tw);
 }
 
 // Single-input C2R with an optional x-derivative and an optional added input.
 // `off`: the row's offset from a and b (lets a block-uniform base pointer
 // with a 32-bit lane offset address the row).
-template <typename R, int N>
+template <typename R, int N, bool HALF = false>
 __device__ __forceinline__ void row_c2r(cplx<R> (&v)[8], const cplx<R>* __restrict__ a, bool iw_a,
                                         const cplx<R>* __restrict__ b, const LdsRowView<R>& lds, int t,
                                         const cplx<R>* __restrict__ tw, int off = 0) {
@@ -345,11 +345,11 @@ __device__ __forceinline__ void row_c2r(cplx<R> (&v)[8], const cplx<R>* __restri
     }
     v[j] = c2r_pre<R, N>(A, B, k, tw);
   }
-  fft_block<R, L, true, 2>(v, lds, t, tw);
+  fft_block<R, L, true, 2, LdsRowView<R>, HALF>(v, lds, t, tw);
 }
 
 // u = C2R(U) and s = C2R(i w_x U + D) from a single read of U.
-template <typename R, int N>
+template <typename R, int N, bool HALF = false>
 __device__ __forceinline__ void row_c2r_two(cplx<R> (&u)[8], cplx<R> (&s)[8], const cplx<R>* __restrict__ U,
                                             const cplx<R>* __restrict__ D, const LdsRowView<R>& lds, int t,
                                             const cplx<R>* __restrict__ tw, int off = 0) {
@@ -363,8 +363,8 @@ __device__ __forceinline__ void row_c2r_two(cplx<R> (&u)[8], cplx<R> (&s)[8], co
     s[j] = c2r_pre<R, N>(cadd(ciw(A, R(xwave<N>(k))), D[off + k]), cadd(ciw(B, R(xwave<N>(kp))), D[off + kp]), k,
                          tw);
   }
-  fft_block<R, L, true, 2>(u, lds, t, tw);
-  fft_block<R, L, true, 2>(s, lds, t, tw);
+  fft_block<R, L, true, 2, LdsRowView<R>, HALF>(u, lds, t, tw);
+  fft_block<R, L, true, 2, LdsRowView<R>, HALF>(s, lds, t, tw);
 }
 
 template <typename R, int N>
@@ -442,7 +442,21 @@ template <typename R, int N>
 __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
     k_xelast(XElastArgs a, const cplx<R>* __restrict__ twg) {
   if (a.skip && *a.skip) return;
-  TUMOR_ROW_SETUP(N)
+  constexpr bool HALF = sizeof(R) == 8;
+  using RC = RowCfg<N>;
+  constexpr int L = RC::L, TP = RC::TP;
+  constexpr int LPR = RC::LP + 32 / (int)sizeof(cplx<R>);
+  __shared__ cplx<R> sbuf[RC::RW * LPR];
+  // FP64 stages half of the twiddle table (twiddle<HALF>), which leaves room
+  // for the parking space at 2 waves per SIMD
+  constexpr int NTW = HALF ? N / 2 : N;
+  __shared__ cplx<R> stw[NTW];
+  for (int k = threadIdx.x; k < NTW; k += blockDim.x) stw[k] = twg[k];
+  __syncthreads();
+  const cplx<R>* tw = stw;
+  const int t = threadIdx.x % TP;
+  const int rl = threadIdx.x / TP;
+  const LdsRowView<R> lds{sbuf + rl * LPR};
   const R invV = R(1.0) / (R(N) * R(N) * R(N));
   // Rows are addressed as a block-uniform base plus a 32-bit lane offset ro
   // (the physical coefficient rows hold N reals = L complex pairs), which
@@ -459,25 +473,24 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
 #pragma unroll
   for (int f = 0; f < 8; ++f) out[f] = static_cast<cplx<R>*>(a.out[f]) + bs;
 
-  // FP32: per-thread parking space for one row (each thread reads back only
-  // its own values, so no barrier is needed)
-  __shared__ cplx<R> stash[sizeof(R) == 4 ? RowCfg<N>::THREADS * 8 : 1];
-  (void)stash;
-  if constexpr (sizeof(R) == 4) {
-    // Group A (FP32): diagonal stresses and eta u_x.  d_x u_x, d_y u_y, d_z u_z
+  // Per-thread parking space for one row (each thread reads back only its
+  // own values, so no barrier is needed).
+  __shared__ cplx<R> stash[RowCfg<N>::THREADS * 8];
+  {
+    // Group A: diagonal stresses and eta u_x.  d_x u_x, d_y u_y, d_z u_z
     // are transformed once each and the trace and the three stresses are
     // formed in one pointwise step, so mu, lambda, d_y u_y and d_z u_z are read
     // once.  One row at a time is parked in LDS, which keeps at most two rows
     // in registers.
     cplx<R> ex[8], ey[8];
-    row_c2r<R, N>(ex, in[0], true, nullptr, lds, t, tw, ro);
+    row_c2r<R, N, HALF>(ex, in[0], true, nullptr, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) stash[j * RC::THREADS + threadIdx.x] = ex[j];
     asm volatile("" ::: "memory");  // reload from LDS: ex is not kept live in registers
-    row_c2r<R, N>(ey, in[4], false, nullptr, lds, t, tw, ro);
+    row_c2r<R, N, HALF>(ey, in[4], false, nullptr, lds, t, tw, ro);
     {
       cplx<R> ez[8];
-      row_c2r<R, N>(ez, in[7], false, nullptr, lds, t, tw, ro);
+      row_c2r<R, N, HALF>(ez, in[7], false, nullptr, lds, t, tw, ro);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int p = t + TP * j;
@@ -491,10 +504,10 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
         ez[j] = {R(2) * m.x * cz.x + lt.x, R(2) * m.y * cz.y + lt.y};
       }
       asm volatile("" ::: "memory");
-      row_r2c<R, N>(ez, lds, t, tw);
+      row_r2c<R, N, HALF>(ez, lds, t, tw);
       store_row<R, N>(out[7], ez, t, ro);
     }
-    row_r2c<R, N>(ey, lds, t, tw);
+    row_r2c<R, N, HALF>(ey, lds, t, tw);
     store_row<R, N>(out[4], ey, t, ro);
     // the parking space now takes mu for the three shear groups, which then
     // read it from LDS instead of global memory
@@ -503,66 +516,18 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
       ex[j] = stash[j * RC::THREADS + threadIdx.x];
       stash[j * RC::THREADS + threadIdx.x] = mu[ro + t + TP * j];
     }
-    row_r2c<R, N>(ex, lds, t, tw);
+    row_r2c<R, N, HALF>(ex, lds, t, tw);
     cplx<R> ux[8];
-    row_c2r<R, N>(ux, in[0], false, nullptr, lds, t, tw, ro);
+    row_c2r<R, N, HALF>(ux, in[0], false, nullptr, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const cplx<R> e = eta[ro + t + TP * j];
       ux[j] = {e.x * ux[j].x * invV, e.y * ux[j].y * invV};
     }
-    row_r2c<R, N>(ux, lds, t, tw);
+    row_r2c<R, N, HALF>(ux, lds, t, tw);
 #pragma unroll
     for (int j = 0; j < 8; ++j) ux[j] = csub(ux[j], iwx<R, N>(ex[j], t + TP * j));
     store_row<R, N>(out[0], ux, t, ro);
-  } else {
-    // Group A (FP64, where a parked row would cost a wave per SIMD of LDS
-    // occupancy): the trace div u is formed in spectral space (i w_x U_x +
-    // dy u_y + dz u_z, one transform), so that each diagonal stress is then
-    // built and transformed on its own, which lets the kernel reach 2 waves
-    // per SIMD without spills.
-    const ColTerm trace_terms[3] = {{0, SYM_IW, 1.0}, {4, SYM_ONE, 1.0}, {7, SYM_ONE, 1.0}};
-    cplx<R> tr[8];
-    row_c2r_terms<R, N>(tr, 3, trace_terms, a.in, bs, lds, t, tw, ro);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) tr[j] = {tr[j].x * invV, tr[j].y * invV};
-    // s_yy and s_zz first, then s_xx (the trace's last use), then eta u_x:
-    // never more than two rows live besides the one being transformed
-#pragma unroll 1
-    for (int d = 0; d < 2; ++d) {
-      cplx<R> sd[8];
-      row_c2r<R, N>(sd, d == 0 ? in[4] : in[7], false, nullptr, lds, t, tw, ro);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int p = t + TP * j;
-        const cplx<R> m = mu[ro + p], l = lam[ro + p];
-        sd[j] = {R(2) * m.x * sd[j].x * invV + l.x * tr[j].x, R(2) * m.y * sd[j].y * invV + l.y * tr[j].y};
-      }
-      row_r2c<R, N>(sd, lds, t, tw);
-      store_row<R, N>(d == 0 ? out[4] : out[7], sd, t, ro);
-    }
-    cplx<R> sx[8];
-    row_c2r<R, N>(sx, in[0], true, nullptr, lds, t, tw, ro);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int p = t + TP * j;
-      const cplx<R> m = mu[ro + p], l = lam[ro + p];
-      sx[j] = {R(2) * m.x * sx[j].x * invV + l.x * tr[j].x, R(2) * m.y * sx[j].y * invV + l.y * tr[j].y};
-    }
-    row_r2c<R, N>(sx, lds, t, tw);
-    {
-      cplx<R> ux[8];
-      row_c2r<R, N>(ux, in[0], false, nullptr, lds, t, tw, ro);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const cplx<R> e = eta[ro + t + TP * j];
-        ux[j] = {e.x * ux[j].x * invV, e.y * ux[j].y * invV};
-      }
-      row_r2c<R, N>(ux, lds, t, tw);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) ux[j] = csub(ux[j], iwx<R, N>(sx[j], t + TP * j));
-      store_row<R, N>(out[0], ux, t, ro);
-    }
   }
   // Groups B and C: shear in the xy and xz planes with eta u_y, eta u_z.
 #pragma unroll 1
@@ -570,18 +535,18 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
     const cplx<R>* U = g == 0 ? in[1] : in[2];
     const cplx<R>* D = g == 0 ? in[3] : in[6];
     cplx<R> u[8], s[8];
-    row_c2r_two<R, N>(u, s, U, D, lds, t, tw, ro);
+    row_c2r_two<R, N, HALF>(u, s, U, D, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int p = t + TP * j;
-      const cplx<R> m = sizeof(R) == 4 ? stash[j * RC::THREADS + threadIdx.x] : mu[ro + p];
+      const cplx<R> m = stash[j * RC::THREADS + threadIdx.x];
       const cplx<R> e = eta[ro + p];
       s[j] = {m.x * s[j].x * invV, m.y * s[j].y * invV};
       u[j] = {e.x * u[j].x * invV, e.y * u[j].y * invV};
     }
-    row_r2c<R, N>(s, lds, t, tw);
+    row_r2c<R, N, HALF>(s, lds, t, tw);
     store_row<R, N>(g == 0 ? out[3] : out[6], s, t, ro);
-    row_r2c<R, N>(u, lds, t, tw);
+    row_r2c<R, N, HALF>(u, lds, t, tw);
 #pragma unroll
     for (int j = 0; j < 8; ++j) u[j] = csub(u[j], iwx<R, N>(s[j], t + TP * j));
     store_row<R, N>(g == 0 ? out[1] : out[2], u, t, ro);
@@ -589,13 +554,13 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
   // Group D: shear in the yz plane.
   {
     cplx<R> s[8];
-    row_c2r<R, N>(s, in[5], false, nullptr, lds, t, tw, ro);
+    row_c2r<R, N, HALF>(s, in[5], false, nullptr, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const cplx<R> m = sizeof(R) == 4 ? stash[j * RC::THREADS + threadIdx.x] : mu[ro + t + TP * j];
+      const cplx<R> m = stash[j * RC::THREADS + threadIdx.x];
       s[j] = {m.x * s[j].x * invV, m.y * s[j].y * invV};
     }
-    row_r2c<R, N>(s, lds, t, tw);
+    row_r2c<R, N, HALF>(s, lds, t, tw);
     store_row<R, N>(out[5], s, t, ro);
   }
 }
