@@ -356,9 +356,16 @@ void colp(Ctx& c, int axis, bool inv, const Prog& pr) {
     for (int q = 0; q < pr.p.nterm[o]; ++q) used[pr.p.term[o][q].src] = true;
   int nin = 0;
   for (int k = 0; k < tumor::kMaxCol; ++k) nin += used[k] ? 1 : 0;
+  // each array once: a dot operand that is also an input is not counted again
   int ndot = 0;
   if (pr.p.dsv)
-    for (int o = 0; o < pr.p.nout; ++o) ndot += pr.p.dotp[o] ? 1 : 0;
+    for (int o = 0; o < pr.p.nout; ++o) {
+      const void* d = pr.p.dotp[o];
+      bool seen = d == nullptr;
+      for (int k = 0; k < tumor::kMaxCol && !seen; ++k) seen = used[k] && pr.p.in[k] == d;
+      for (int q = 0; q < o && !seen; ++q) seen = pr.p.dotp[q] == d;
+      ndot += seen ? 0 : 1;
+    }
   const double bytes = double(nin + pr.p.nout + ndot) * double(c.V) * sizeof(R);
   const int cls = inv ? kcls<R>(TUMOR_K_COLINV64, TUMOR_K_COLINV32)
                       : (pr.p.dsv ? kcls<R>(TUMOR_K_COLDOT64, TUMOR_K_COLDOT32) : kcls<R>(TUMOR_K_COLFWD64, TUMOR_K_COLFWD32));
@@ -439,7 +446,8 @@ void diff_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, double raw, double dcoe
           Prog().in(0, P.A[0]).in(1, P.A[1]).in(2, P.A[2]).out(P.B[0], {T1(0), TW(1)}).out(P.B[1], {T1(2)}).skip(skip));
   Prog z;
   z.in(0, P.B[0]).in(1, P.B[1]).in(2, in).skip(skip);
-  if (raw != 0.0) z.out(out, {TR(2, raw), T1(0, dcoef), TW(1, dcoef)});
+  // the untransformed term last: the inner-product pass takes p from it
+  if (raw != 0.0) z.out(out, {T1(0, dcoef), TW(1, dcoef), TR(2, raw)});
   else z.out(out, {T1(0, dcoef), TW(1, dcoef)});
   if (fz) {
     z.p.dotp[0] = in;

@@ -146,7 +146,12 @@ __global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(
     } else {
 #pragma unroll
       for (int j = 0; j < 8; ++j) acc[j] = czero<R>();
-      for (int q = 0; q < nt; ++q) {
+      // inner-product pass: a last untransformed term read from the operand p
+      // already holds p at the output positions, so it is taken after the loop
+      const ColTerm last = prog.term[o][nt - 1];
+      const bool rawlast = DOT && last.sym == SYM_RAW && prog.in[last.src] == prog.dotp[o];
+      const int nloop = rawlast ? nt - 1 : nt;
+      for (int q = 0; q < nloop; ++q) {
         const ColTerm tm = prog.term[o][q];
         const R cf = R(tm.coef);
         cplx<R> tmp[8];
@@ -163,13 +168,25 @@ __global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(
           acc[j].y += cf * v.y;
         }
       }
-    }
-    if constexpr (DOT) {
-      // the inner-product operand at the output positions, loaded after the
-      // transforms: held across them it would push the pass into spills
-      const cplx<R>* __restrict__ pp = static_cast<const cplx<R>*>(prog.dotp[o]);
+      if constexpr (DOT) {
+        if (rawlast) {
+          const R cf = R(last.coef);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) pdot[j] = pp[base + (long long)(t + TP * j) * astride];
+          for (int j = 0; j < 8; ++j) pdot[j] = nxt[j];
+          if (o + 1 < prog.nout) load_col(nxt, prog.term[o + 1][0].src);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            acc[j].x += cf * pdot[j].x;
+            acc[j].y += cf * pdot[j].y;
+          }
+        } else {
+          // the operand loaded after the transforms: held across them it
+          // would push the pass into spills
+          const cplx<R>* __restrict__ pp = static_cast<const cplx<R>*>(prog.dotp[o]);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) pdot[j] = pp[base + (long long)(t + TP * j) * astride];
+        }
+      }
     }
     cplx<R>* __restrict__ dst = static_cast<cplx<R>*>(prog.out[o]);
 #pragma unroll
