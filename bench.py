@@ -401,6 +401,12 @@ def main():
     extra["elasticity_outer_per_step"] = [s["outer_elast"] for s in main_run["stats"]]
     extra["diffusion_iterations_last_step"] = main_run["stats"][-1]["it_diff"]
     extra["warmup_kernel_ms"] = {c: round(v["ms"], 2) for c, v in main_run["warm_profile"].items() if v["ms"] > 0}
+    # algorithmic HBM rate of every kernel class over the warm-up steps (launches
+    # that exit early after convergence are not counted), against the 8 TB/s peak
+    extra["warmup_class_rates"] = {
+        c: dict(launches=v["launches"], gbs=round(v["bytes"] / v["ms"] / 1e6, 1),
+                frac=round(v["bytes"] / v["ms"] / 1e6 / HBM_PEAK_GBS, 3))
+        for c, v in main_run["warm_profile"].items() if v["ms"] > 0 and v["launches"] > 0}
     extra["wall_s"] = round(main_run["wall"], 4)
     extra["diagnostics"] = dict(ms=round(main_run["diag_ms"], 3), threshold_voxels=0.1,
                                 **{k: round(v, 6) for k, v in main_run["diag"].items()})
