@@ -421,12 +421,15 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xinv(XProg prog, const c
   if (prog.skip && *prog.skip) return;
   TUMOR_ROW_SETUP(N)
   const R scale = R(prog.scale);
+  // block-uniform bases and a 32-bit lane offset, as in k_xelast
+  const long long bs = (long long)blockIdx.x * RC::RW * L;
+  const int ro = rl * L;
   for (int o = 0; o < prog.nout; ++o) {
     cplx<R> v[8];
-    row_c2r_terms<R, N>(v, prog.nterm[o], prog.term[o], prog.in, soff, lds, t, tw);
-    cplx<R>* __restrict__ dst = reinterpret_cast<cplx<R>*>(static_cast<R*>(prog.out[o]) + poff);
+    row_c2r_terms<R, N>(v, prog.nterm[o], prog.term[o], prog.in, bs, lds, t, tw, ro);
+    cplx<R>* __restrict__ dst = static_cast<cplx<R>*>(prog.out[o]) + bs;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) dst[t + TP * j] = cscale(v[j], scale);
+    for (int j = 0; j < 8; ++j) dst[ro + t + TP * j] = cscale(v[j], scale);
   }
 }
 
