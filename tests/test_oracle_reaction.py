@@ -181,3 +181,68 @@ def test_force_matches_analytic_gradient():
     b = rx.elastic_force(g, 4e4, tau, np.zeros_like(tau))
     for a in range(3):
         assert np.max(np.abs(b[a] - 4e4 * np.tanh(tau) * grad[a])) < 1e-9
+
+
+# --- the i -> p transfer beta = beta0 H(sigma_b - p - i) o (e:beta), isolated ---
+# alpha0 = gamma = 0 removes the p -> i switch and the death term, and rho = 0
+# the logistic flows, so the transfer is the only reaction left.  The expected
+# values below are worked by hand from e:gog (p_t = ... + beta i, i_t = ... -
+# beta i) with one forward Euler step of length dt.
+
+def _beta_only(p, i, o, beta0=0.02, sigma_b=0.9, dt=0.01):
+    P = _P(alpha0=0.0, gamma=0.0, beta0=beta0, sigma_b=sigma_b)
+    one = np.ones_like(p)
+    z = np.zeros_like(p)
+    return rx.species_reaction(P, dt, p, i, z, 0.4 * one, 0.3 * one, o, z, z, z)
+
+
+def test_beta_transfer_below_the_carrying_threshold():
+    # p + i = 0.3 < sigma_b = 0.9: the smoothed Heaviside is 1 to 1e-52, so the
+    # rate is beta0 o.  beta0 = 0.02, dt = 0.01:
+    #   o = 0.8: dt beta i = 0.01 * 0.02 * 0.8 * 0.2 = 3.2e-5
+    #   o = 0.4: dt beta i = 0.01 * 0.02 * 0.4 * 0.2 = 1.6e-5
+    p = np.array([0.1, 0.1])
+    i = np.array([0.2, 0.2])
+    o = np.array([0.8, 0.4])
+    p1, i1, n1, g1, w1 = _beta_only(p, i, o)
+    assert np.allclose(i1, [0.2 - 3.2e-5, 0.2 - 1.6e-5], rtol=0, atol=1e-16)
+    assert np.allclose(p1, [0.1 + 3.2e-5, 0.1 + 1.6e-5], rtol=0, atol=1e-16)
+    assert np.array_equal(n1, [0.0, 0.0])
+    assert np.allclose(g1, 0.4, rtol=0, atol=1e-16) and np.allclose(w1, 0.3, rtol=0, atol=1e-16)
+
+
+def test_beta_transfer_switches_off_above_the_carrying_threshold():
+    # p + i = 1.2 > sigma_b: H(-0.3 / 0.01) = 1 / (1 + e^60) ~ 8.8e-27, so the
+    # invasive cells stay put (to ~1e-30 absolute).
+    p = np.array([0.7, 0.95])
+    i = np.array([0.5, 0.25])
+    o = np.array([0.9, 0.9])
+    p1, i1, _, _, _ = _beta_only(p, i, o)
+    assert np.allclose(i1, i, rtol=0, atol=1e-25)
+    assert np.allclose(p1, p, rtol=0, atol=1e-25)
+
+
+def test_beta_transfer_at_the_threshold_is_half_rate():
+    # p + i = sigma_b exactly: H(0) = 1/2, so dt beta i = 0.01 * 0.02 * 0.5 * 1.0 * 0.4 = 4e-5.
+    p = np.array([0.5])
+    i = np.array([0.4])
+    o = np.array([1.0])
+    p1, i1, _, _, _ = _beta_only(p, i, o)
+    assert i1[0] == pytest.approx(0.4 - 4e-5, rel=0, abs=1e-16)
+    assert p1[0] == pytest.approx(0.5 + 4e-5, rel=0, abs=1e-16)
+
+
+def test_beta_transfer_with_growth_on_is_additive_to_the_logistic_flow():
+    # With growth on and o above o_inv (kappa = 1), the invasive cells follow the
+    # logistic flow of rate rho_i and lose dt beta0 o i on top (frozen state):
+    #   i' = Lambda(i, rho_i, dt) - dt beta0 o i,  Lambda(y, r, t) = y e^{rt} / (1 + y (e^{rt} - 1)).
+    P = _P(alpha0=0.0, gamma=0.0, beta0=0.05)
+    dt, rho_i = 0.01, 1.0
+    i = np.array([0.3])
+    o = np.array([0.95])
+    one = np.ones(1)
+    z = np.zeros(1)
+    _, i1, _, _, _ = rx.species_reaction(P, dt, 0.2 * one, i, z, 0.5 * one, 0.5 * one, o, z, rho_i * one, z)
+    e = np.exp(0.01)
+    lam = 0.3 * e / (1.0 + 0.3 * (e - 1.0))
+    assert i1[0] == pytest.approx(lam - 0.01 * 0.05 * 0.95 * 0.3, rel=1e-14)

@@ -115,3 +115,121 @@ def test_sampled_nodes_equal_the_whole_grid_step():
     part = transport.advect(g, fields, v, dt, nodes=nodes)
     for k in full:
         assert np.array_equal(part[k], full[k][idx[2], idx[1], idx[0]]), k
+
+
+# --- variable velocity: the 1-D compressible flow v = c sin(x_a) along one axis ---
+# Its characteristics are exact: d/dt tan(x/2) = c tan(x/2), so the point that
+# arrives at x after a time dt left from X with tan(X/2) = tan(x/2) e^{-c dt}.
+# With q0 = 1 the conservative transport q_t + (q v)_x = 0 has the exact density
+# q(x, t) = dX/dx = e^{-ct} / (cos^2(x/2) + sin^2(x/2) e^{-2ct}).
+# One RK2 characteristic step and one Heun step of the source are both exact to
+# O(dt^3) locally (second order globally); a first-order slip in either (e.g.
+# X = x - dt v(X*), or the corrector's source taken at X instead of x) leaves an
+# O(dt^2) local error, which the convergence rates below reject.
+
+def _sine_flow(n, c, axis):
+    g = Grid(n)
+    coords = g.coords()           # (x, y, z)
+    v = np.zeros((3, n, n, n))
+    v[axis] = c * np.sin(coords[axis])
+    return g, v, coords[axis]
+
+
+def _exact_departure(x, c, t):
+    # X in [0, 2 pi) with tan(X/2) = tan(x/2) e^{-ct}; x/2 in [0, pi) keeps the branch
+    return 2.0 * np.arctan2(np.sin(0.5 * x) * np.exp(-c * t), np.cos(0.5 * x))
+
+
+def _exact_density(x, c, t):
+    return np.exp(-c * t) / (np.cos(0.5 * x) ** 2 + np.sin(0.5 * x) ** 2 * np.exp(-2.0 * c * t))
+
+
+def _pdiff(a, b):
+    d = a - b
+    return d - 2.0 * np.pi * np.round(d / (2.0 * np.pi))
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_rk2_departure_points_of_a_compressible_flow_are_third_order_locally(axis):
+    n, c = 32, 1.5
+    g, v, xa = _sine_flow(n, c, axis)
+    errs = []
+    for dt in (0.2, 0.1, 0.05):
+        X = transport.departure_points(g, v, dt)
+        err = np.max(np.abs(_pdiff(X[axis] * g.h, _exact_departure(xa, c, dt))))
+        # the other two coordinates do not move
+        for b in range(3):
+            if b != axis:
+                base = transport.grid_indices(n)[b]
+                assert np.array_equal(X[b], base)
+        errs.append(err)
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 2.7), (errs, rates)
+    assert errs[-1] < 1e-4
+
+
+def test_rk2_departure_points_converge_at_second_order_over_a_fixed_time():
+    # Compose k characteristic steps of dt = T / k backwards from the arrival
+    # points (the velocity is steady): global error O(dt^2).
+    n, c, T = 32, 1.5, 0.4
+    g, v, x = _sine_flow(n, c, 0)
+    jx = np.arange(n, dtype=np.float64)
+    nodes = (jx, np.zeros(n), np.zeros(n))
+    errs = []
+    for k in (2, 4, 8):
+        dt = T / k
+        # track the foot of each arrival node by re-evaluating the same
+        # two-stage scheme at the current foot (interpolated velocity)
+        pos = jx.copy()
+        for _ in range(k):
+            s = dt / g.h
+            v0 = transport.interp(v[0], pos, np.zeros(n), np.zeros(n))
+            xs = pos - s * v0
+            vs = transport.interp(v[0], xs, np.zeros(n), np.zeros(n))
+            pos = pos - 0.5 * s * (v0 + vs)
+        errs.append(np.max(np.abs(_pdiff(pos * g.h, _exact_departure(jx * g.h, c, T)))))
+        if k == 2:
+            # the first of the k steps is exactly departure_points at the nodes
+            X = transport.departure_points(g, v, dt, nodes=nodes)
+            s = dt / g.h
+            v0 = c * np.sin(jx * g.h)
+            vs = transport.interp(v[0], jx - s * v0, np.zeros(n), np.zeros(n))
+            assert np.allclose(X[0], jx - 0.5 * s * (v0 + vs), rtol=0, atol=1e-12)
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.8), (errs, rates)
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_heun_source_of_a_compressible_flow_is_third_order_locally(axis):
+    n, c = 32, 1.5
+    g, v, xa = _sine_flow(n, c, axis)
+    one = np.ones((n, n, n))
+    errs = []
+    for dt in (0.2, 0.1, 0.05):
+        out = transport.advect(g, {k: one for k in "pingwf"}, v, dt)
+        exact = _exact_density(xa, c, dt)
+        err = np.max(np.abs(out["p"] - exact))
+        errs.append(err)
+        # plain transport of a constant stays constant (cubic Lagrange reproduces it)
+        assert np.allclose(out["f"], 1.0, rtol=0, atol=1e-13)
+        # all conservative species follow the same update
+        for k in "ingw":
+            assert np.array_equal(out[k], out["p"])
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 2.7), (errs, rates)
+    assert errs[-1] < 1e-4
+
+
+def test_conservative_transport_of_a_constant_density_over_a_fixed_time_is_second_order():
+    # k full SL steps (departure points, interpolation of q and div v, Heun
+    # source) to T: the density approaches e^{-cT}/(cos^2 + sin^2 e^{-2cT}) at O(dt^2).
+    n, c, T = 32, 1.5, 0.4
+    g, v, x = _sine_flow(n, c, 0)
+    errs = []
+    for k in (2, 4, 8):
+        q = np.ones((n, n, n))
+        for _ in range(k):
+            q = transport.advect(g, {kk: q for kk in "pingwf"}, v, T / k)["p"]
+        errs.append(np.max(np.abs(q - _exact_density(x, c, T))))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.8), (errs, rates)
