@@ -27,52 +27,103 @@ if ROOT not in sys.path:
 
 METRIC = "split time steps/s at 256³ (fwd, fwd+adjoint), mixed vs FP64 on one GPU"
 HBM_PEAK_GBS = 8000.0
-CLASSES = ("colinv64", "colfwd64", "colinv32", "colfwd32", "xelast64", "xelast32", "xdiff64", "xdiff32",
-           "xother", "sl", "react", "krylov64", "krylov32", "zinvp64", "zinvp32", "coldot64", "coldot32")
-# classes that time exactly one kernel instantiation (so that a rocprofv3 summary
-# line can be matched to them); the others group several kernels
-# classes that time one kernel symbol (FP32 y and z passes are separate
-# instances of the column pass, so colinv32 and colfwd32 are not listed)
-SINGLE_KERNEL = ("colinv64", "colfwd64", "coldot64", "coldot32", "xelast64", "xelast32", "xdiff64", "xdiff32",
-                 "react")
+CLASSES = ("colinv64", "colfwd64", "colinv32", "colfwd32", "colinv32z", "colfwd32z", "xelast64", "xelast32",
+           "xdiff64", "xdiff32", "xother", "sl", "react", "krylov64", "krylov32", "zinvp64", "zinvp32",
+           "zinvp64c1", "zinvp32c1", "coldot64", "coldot32")
+# classes that time exactly one kernel symbol, so that the roofline's kernel can
+# be matched to a rocprofv3 summary line (xother, sl and krylov group several)
+SINGLE_KERNEL = ("colinv64", "colfwd64", "colinv32", "colfwd32", "colinv32z", "colfwd32z", "coldot64",
+                 "coldot32", "xelast64", "xelast32", "xdiff64", "xdiff32", "zinvp64", "zinvp32", "zinvp64c1",
+                 "zinvp32c1", "react")
+
+# Stable windows of the 256^3 forward workloads: (steps from t = 0 before the
+# window, longest run from the window's start).  The coupled transport /
+# elasticity of these synthetic inputs loses stability after about 18 steps
+# (seeds3_n256); every timed step lies in steps 4..13, where the trajectory is
+# smooth.  Each run of at most `span` steps starts from a device snapshot of the
+# state after step `start` (bit-exact restore, outside the timed region).
+WINDOWS = {"seeds3_n256": (3, 10), "seeds3_n128": (3, 10), "seed1_n32": (0, 10),
+           "lattice_n256": (0, 4), "lattice_n128": (0, 4)}
+
+
+def cycle_plan(total, span):
+    """Lengths of the runs that make up `total` steps, each at most `span` long
+    (every run restarts from the window snapshot, so no step leaves the window)."""
+    if span < 1 or total < 0:
+        raise ValueError("span must be >= 1 and total >= 0")
+    runs = []
+    while total > 0:
+        k = min(span, total)
+        runs.append(k)
+        total -= k
+    return runs
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(tm, torch, inp, P, precision, steps, warmup):
-    """Warm up, find the dominant kernel class, then time `steps` steps."""
+SPECIES = ("p", "i", "n", "o", "l", "g", "w", "f")
+
+
+def window_end_fields(sim, snap, span):
+    """State after a full window run (snapshot + span steps): species and u."""
+    sim.load_state(snap)
+    for _ in range(span):
+        sim.step(1)
+    return {k: sim.get(k) for k in SPECIES + ("u",)}
+
+
+def timed_cycles(torch, sim, snap, steps, span):
+    """Time `steps` steps in runs of at most `span` from the snapshot.  Returns
+    (event ms summed over the runs, wall s including the restores, stats)."""
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    stats, gpu_ms = [], 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for run in cycle_plan(steps, span):
+        sim.load_state(snap)                   # restore: outside the event-timed region
+        ev0.record(sim.stream)
+        for k in range(run):
+            stats.append(sim.step(1))
+        ev1.record(sim.stream)
+        ev1.synchronize()
+        gpu_ms += ev0.elapsed_time(ev1)
+    torch.cuda.synchronize()
+    return gpu_ms, time.perf_counter() - t0, stats
+
+
+def run_form(tm, torch, inp, P, precision, steps, warmup, window, keep_fields=False):
+    """Reach the window, warm up, find the dominant kernel class, then time
+    `steps` steps (all inside the window)."""
+    start, span = window
     sim = tm.from_inputs(inp, P, precision=precision)
+    for k in range(start):
+        sim.step(1)
+    snap = sim.save_state()
     for c in CLASSES:
         sim.kernel_timer(c, True)
+    # W warm-up steps in window runs; with W = 0 one untimed run of the window
+    # still profiles the kernel classes (to pick the roofline's kernel)
     wstats = []
-    for k in range(warmup):
-        wstats.append(sim.step(1))
-        log(f"[{precision}] warmup step {k + 1}/{warmup}: elast it {wstats[-1]['it_elast']}"
-            f" (outer {wstats[-1]['outer_elast']}), diff it {wstats[-1]['it_diff']}")
+    for run in cycle_plan(warmup, span) or [min(span, 3)]:
+        sim.load_state(snap)
+        for k in range(run):
+            wstats.append(sim.step(1))
+            log(f"[{precision}] warm-up step {len(wstats)} (window step {start + k + 1}): elast it "
+                f"{wstats[-1]['it_elast']} (outer {wstats[-1]['outer_elast']}), diff it {wstats[-1]['it_diff']}")
     prof = {c: sim.kernel_timer_read(c) for c in CLASSES}
     # the roofline is reported for the single kernel with the largest share of time
     dominant = max(SINGLE_KERNEL, key=lambda c: prof[c]["ms"])
     for c in CLASSES:
         sim.kernel_timer(c, c == dominant)       # only the dominant class inside the timed region
-    stream = sim.stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    t0 = time.perf_counter()
-    stats = []
-    for k in range(steps):
-        stats.append(sim.step(1))
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    gpu_ms, wall, stats = timed_cycles(torch, sim, snap, steps, span)
     dom = sim.kernel_timer_read(dominant)
-    log(f"[{precision}] {steps} steps: wall {wall:.3f} s, events {gpu_ms / 1e3:.3f} s;"
+    sim.kernel_timer(dominant, False)
+    log(f"[{precision}] {steps} steps in runs {cycle_plan(steps, span)}: events {gpu_ms / 1e3:.3f} s, wall {wall:.3f} s;"
         f" dominant {dominant}: {dom['launches']} launches, {dom['ms']:.1f} ms")
-    # mass-effect diagnostics (scalars) of the final displacement
+    # mass-effect diagnostics (scalars) of the displacement the timed runs ended with
     sim.diagnose(0.1)                                    # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -81,27 +132,27 @@ def run_form(tm, torch, inp, P, precision, steps, warmup):
         diag = sim.diagnose(0.1)
     torch.cuda.synchronize()
     diag_ms = (time.perf_counter() - t0) / reps * 1e3
+    fields = window_end_fields(sim, snap, span) if keep_fields else None
     sim.close()
     return dict(wall=wall, gpu_ms=gpu_ms, stats=stats, warm_profile=prof, dominant=dominant, dom=dom,
-                diag=diag, diag_ms=diag_ms)
+                diag=diag, diag_ms=diag_ms, fields=fields)
 
 
-def run_single(tm, torch, inp, P, precision, steps, warmup, model="single", flags=None):
+def run_single(tm, torch, inp, P, precision, steps, warmup, window, model="single", flags=None):
     """Split steps/s of a model variant (the single-species model, the
     multispecies model on masked inputs, or the symmetric step) on the 256^3
-    inputs."""
+    inputs, timed inside the same window as the main form."""
+    start, span = window
     sim = tm.from_inputs(inp, P, precision=precision, model=model,
                          flags=tm.F_DEFAULT if flags is None else flags)
-    for _ in range(warmup):
+    for _ in range(start):
         sim.step(1)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(sim.stream)
-    its = [sim.step(1) for _ in range(steps)]
-    ev1.record(sim.stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    snap = sim.save_state()
+    for run in cycle_plan(warmup, span):
+        sim.load_state(snap)
+        for _ in range(run):
+            sim.step(1)
+    ms, _, its = timed_cycles(torch, sim, snap, steps, span)
     sim.close()
     log(f"[{model} {precision} flags {flags}] {steps} steps: {ms / steps:.1f} ms/step, elasticity it {[s['it_elast'] for s in its]}")
     return dict(steps_per_s=round(steps / (ms / 1e3), 4), ms_per_step=round(ms / steps, 3),
@@ -111,7 +162,10 @@ def run_single(tm, torch, inp, P, precision, steps, warmup, model="single", flag
 def run_adjoint(tm, torch, inp, P, precision, steps, warmup, ckpt):
     """Forward + adjoint throughput: `steps` recorded steps then their reverse sweep."""
     import numpy as np
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
+    free0, total = torch.cuda.mem_get_info()
     sim = tm.from_inputs(inp, P, precision=precision, flags=tm.F_DEFAULT | tm.F_ADJOINT)
     for k in range(warmup):
         sim.step(1)
@@ -127,7 +181,9 @@ def run_adjoint(tm, torch, inp, P, precision, steps, warmup, ckpt):
     h3 = (2 * np.pi / n) ** 3
     for k in range(3):
         lam[k].copy_(h3 * 0.1 * tau)          # seed of 1/2 h^3 ||tau - 0.9 tau||^2
+    del tau
     grad = np.zeros(5 + len(inp["weights"]))
+    free1, _ = torch.cuda.mem_get_info()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for k in range(steps):
@@ -138,10 +194,48 @@ def run_adjoint(tm, torch, inp, P, precision, steps, warmup, ckpt):
     log(f"[{precision} adjoint] {steps} recorded steps {t1 - t0:.2f} s, reverse sweep {t3 - t2:.2f} s "
         f"(checkpoint every {ckpt}); peak allocated {peak:.1f} GiB")
     sim.close()
-    del sim
+    del sim, lam
     torch.cuda.empty_cache()
     return dict(fwd_s=t1 - t0, adj_s=t3 - t2, steps_per_s=steps / ((t1 - t0) + (t3 - t2)), peak_gib=peak,
-                grad_head=[float(v) for v in grad[:5]])
+                device_used_gib=(free0 - free1) / 2 ** 30, grad_head=[float(v) for v in grad[:5]])
+
+
+def copy_ceiling(torch, mib=1024, reps=10):
+    """Achievable HBM bandwidth of plain device copies of `mib` MiB: a
+    device-to-device copy and a one-read-one-write elementwise kernel, each
+    timed with events; bytes moved = read + written."""
+    n = mib * 2 ** 20 // 8
+    src = torch.empty(n, dtype=torch.float64, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    out = {}
+    for name, fn in (("copy", lambda: dst.copy_(src)), ("scale", lambda: torch.mul(src, 2.0, out=dst))):
+        for _ in range(3):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        ms = sorted(a.elapsed_time(b) for a, b in ev)
+        gbs = 2 * n * 8 / (ms[len(ms) // 2] * 1e-3) / 1e9
+        out[name] = round(gbs, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+    best = max(out.values())
+    return dict(gbs=best, frac_of_peak=round(best / HBM_PEAK_GBS, 4), mib=mib, by_kernel=out,
+                note="median of %d event-timed launches, bytes = read + written" % reps)
+
+
+def rel_l2_errors(mixed, ref):
+    """Relative L2 error of each field of the mixed form against the FP64 form."""
+    out = {}
+    for k in ref:
+        d = (mixed[k] - ref[k]).double().norm().item()
+        r = ref[k].double().norm().item()
+        out[k] = d / r if r > 0 else d
+    return out
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_256.json")
@@ -323,7 +417,8 @@ def cpu_baseline(inp, P, iters_e, iters_d):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=10,
+                    help="timed steps, in runs of at most the window length from the window snapshot")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="seeds3_n256", help="synthetic workload name (default: the 256^3 case)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 form")
@@ -346,6 +441,9 @@ def main():
                     help="checkpoint interval of the forward+adjoint form; 1 keeps every state and the step "
                          "intermediates on the tape (about 14 GB at 256^3 for 4 steps), so the reverse sweep "
                          "recomputes no forward step")
+    ap.add_argument("--ckpt-steps", type=int, default=8,
+                    help="recorded steps of the checkpointed forward+adjoint form (0 skips it)")
+    ap.add_argument("--ckpt-k", type=int, default=4, help="checkpoint interval of that form")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_MIB"),
                     help="no GPU work: write the HBM counter summary from two rocprofv3 --pmc output folders")
     args = ap.parse_args()
@@ -384,19 +482,38 @@ def main():
     log(f"inputs {args.workload} n={n} generated in {time.perf_counter() - t:.1f} s")
     precision = inp["precision"]
 
-    main_run = run_form(tm, torch, inp, P, precision, args.steps, args.warmup)
+    if args.workload not in WINDOWS:
+        raise SystemExit(f"bench.py: no stable window is known for workload {args.workload!r}")
+    window = WINDOWS[args.workload]
+    start, span = window
+    extra = {}
+    # achievable HBM bandwidth of a plain device copy, the practical ceiling
+    extra["copy_ceiling"] = copy_ceiling(torch)
+    log(f"copy ceiling: {extra['copy_ceiling']}")
+    compare = not args.no_fp64 and precision != "fp64"
+    main_run = run_form(tm, torch, inp, P, precision, args.steps, args.warmup, window, keep_fields=compare)
     ms_per_step = main_run["gpu_ms"] / args.steps
     value = args.steps / (main_run["gpu_ms"] / 1e3)
-    extra = {}
     fp64_run = None
-    if not args.no_fp64 and precision != "fp64":
+    if compare:
         torch.cuda.empty_cache()
-        fp64_run = run_form(tm, torch, inp, P, "fp64", args.steps, args.warmup)
+        fp64_run = run_form(tm, torch, inp, P, "fp64", args.steps, args.warmup, window, keep_fields=True)
         v64 = args.steps / (fp64_run["gpu_ms"] / 1e3)
         extra["fp64_steps_per_s"] = round(v64, 4)
         extra["mixed_speedup_over_fp64"] = round(value / v64, 3)
         extra["fp64_roofline"] = roofline(fp64_run["dom"], fp64_run["dominant"], n)
+        # error of the mixed form against the FP64 form (itself held to the FP64
+        # oracle at 1e-10 by the parity tests), both after step start + span from t = 0
+        errs = rel_l2_errors(main_run["fields"], fp64_run["fields"])
+        extra["mixed_vs_fp64_rel_l2"] = dict(after_step=start + span,
+                                             **{k: float(f"{v:.3e}") for k, v in errs.items()})
+        log(f"mixed vs FP64 relative L2 after step {start + span}: {extra['mixed_vs_fp64_rel_l2']}")
+        main_run["fields"] = fp64_run["fields"] = None
+        torch.cuda.empty_cache()
     it_e = [s["it_elast"] for s in main_run["stats"]]
+    extra["timed_runs"] = dict(window_steps=[start + 1, start + span], runs=cycle_plan(args.steps, span),
+                               note="each run restarts from a device snapshot of the state after step "
+                                    f"{start} (restore outside the timed region)")
     extra["elasticity_iterations_per_step"] = it_e
     extra["elasticity_outer_per_step"] = [s["outer_elast"] for s in main_run["stats"]]
     extra["diffusion_iterations_last_step"] = main_run["stats"][-1]["it_diff"]
@@ -411,20 +528,23 @@ def main():
     extra["diagnostics"] = dict(ms=round(main_run["diag_ms"], 3), threshold_voxels=0.1,
                                 **{k: round(v, 6) for k, v in main_run["diag"].items()})
     rl = roofline(main_run["dom"], main_run["dominant"], n)
+    if rl is not None:
+        rl["frac_of_copy_ceiling"] = round(rl["achieved"] / extra["copy_ceiling"]["gbs"], 4)
 
     if not args.no_single:
-        extra["single_species"] = {prec: run_single(tm, torch, inp, P, prec, args.steps, args.warmup)
+        extra["single_species"] = {prec: run_single(tm, torch, inp, P, prec, args.steps, args.warmup, window)
                                    for prec in (("mixed", "fp64") if not args.no_fp64 else ("mixed",))}
 
     if not args.no_strang:
-        extra["strang"] = {prec: run_single(tm, torch, inp, P, prec, args.steps, args.warmup, "multispecies",
+        extra["strang"] = {prec: run_single(tm, torch, inp, P, prec, args.steps, args.warmup, window, "multispecies",
                                             tm.F_DEFAULT | tm.F_STRANG)
                            for prec in (("mixed", "fp64") if not args.no_fp64 else ("mixed",))}
 
     if not args.no_masked:
         minp = synthetic.workload_inputs(args.workload, masked=True)
         extra["masked"] = dict(workload=f"{args.workload} with the brain mask and background material",
-                               **run_single(tm, torch, minp, P, precision, args.steps, args.warmup, "multispecies"))
+                               **run_single(tm, torch, minp, P, precision, args.steps, args.warmup, window,
+                                            "multispecies"))
 
     if not args.no_adjoint:
         ainp = synthetic.workload_inputs(args.adjoint_workload)
@@ -436,7 +556,15 @@ def main():
                 workload=f"{args.adjoint_workload}: {ainp['n']}^3, {len(ainp['weights'])} initial-condition weights",
                 recorded_steps=args.adjoint_steps, ckpt_every=args.ckpt_every, forward_s=round(r["fwd_s"], 3),
                 reverse_s=round(r["adj_s"], 3), peak_allocated_gib=round(r["peak_gib"], 2),
-                grad_rho_kw_kg_kf_scale=r["grad_head"])
+                device_used_gib=round(r["device_used_gib"], 2), grad_rho_kw_kg_kf_scale=r["grad_head"])
+        if args.ckpt_steps > 0:
+            # the checkpointed tape: a checkpoint every K steps, each reversed step
+            # recomputes its window from the nearest checkpoint
+            r = run_adjoint(tm, torch, ainp, P, precision, args.ckpt_steps, 0, args.ckpt_k)
+            extra["fwd_adjoint_checkpointed"] = dict(
+                precision=precision, recorded_steps=args.ckpt_steps, ckpt_every=args.ckpt_k,
+                steps_per_s=round(r["steps_per_s"], 4), forward_s=round(r["fwd_s"], 3), reverse_s=round(r["adj_s"], 3),
+                peak_allocated_gib=round(r["peak_gib"], 2), device_used_gib=round(r["device_used_gib"], 2))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -459,7 +587,11 @@ def main():
         "dtype": "f32+f64" if precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {n}^3 periodic grid, {precision} precision, full multispecies "
-                               f"split step (transport, CN diffusion of i/o/l, reaction, oxygen, edema, elasticity)",
+                               f"split step (transport, CN diffusion of i/o/l, reaction, oxygen, edema, elasticity); "
+                               f"timed steps lie in steps {start + 1}-{start + span} of the trajectory from t = 0, in "
+                               f"runs of at most {span} steps that each restart from a device snapshot of the state "
+                               f"after step {start}",
+                   "window": [start + 1, start + span],
                    "n": n, "precision": precision, "dt": inp["dt"], "rtol": inp["rtol"],
                    "tumour_seeds": int(len(inp["weights"])), "forward_only": True},
         "roofline": rl,

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define TUMOR_ABI_VERSION 2
+#define TUMOR_ABI_VERSION 3
 
 typedef enum {
   TUMOR_OK = 0,
@@ -260,6 +260,22 @@ int tumor_tape_bytes(const tumor_config* cfg, int32_t nsteps, int32_t ckpt_every
 int tumor_record(tumor_ctx* ctx, int32_t nsteps, int32_t ckpt_every, void* tape, size_t tape_bytes);
 int tumor_adjoint_step(tumor_ctx* ctx, double* adj, double* grad);
 
+/* State snapshots (checkpoint and restore of the time-stepping state of
+ * Sec. 3: the species p, i, n, o, l, g, w, f and the displacements u^n,
+ * u^{n-1} that define the backward-difference velocity).  The snapshot holds
+ * the library's internal representation, so a restored context steps exactly
+ * as the saved one would have (bit for bit).
+ *   tumor_state_bytes: size of one snapshot for cfg (host arguments).
+ *   tumor_save_state: copy the current state into dst (device, >= bytes).
+ *   tumor_load_state: replace the current state by the snapshot in src
+ *     (device) and refresh the coefficients from it.  The snapshot must come
+ *     from a context with the same n (and precision).  TUMOR_ESTATE while a
+ *     recording (tumor_record) or its reverse sweep is unfinished; a finished
+ *     recording is released.  Buffers are caller-owned, unaligned is fine. */
+int tumor_state_bytes(const tumor_config* cfg, size_t* bytes);
+int tumor_save_state(tumor_ctx* ctx, void* dst, size_t bytes);
+int tumor_load_state(tumor_ctx* ctx, const void* src, size_t bytes);
+
 /* Copy a field out of / into the state (device arrays of N^3, or 3 N^3 for
  * TUMOR_FIELD_U and TUMOR_FIELD_UPREV).  Coefficient fields are read only;
  * setting a species or the background refreshes nothing (call tumor_refresh
@@ -296,7 +312,8 @@ int tumor_interp(tumor_ctx* ctx, const double* q, const double* jx, const double
  * array of 4 values, or NULL to clear.  TUMOR_EINVAL in the mixed precision. */
 int tumor_force_iterations(tumor_ctx* ctx, const int32_t* iters);
 
-/* Measurement hook: bracket every launch of one kernel class with HIP events
+/* Measurement hook: bracket every launch of one kernel class (each class is
+ * one kernel symbol, except XOTHER, SL, KRYLOV64/32) with HIP events
  * on the context's stream and accumulate launches, elapsed milliseconds and
  * the algorithmic HBM bytes of those launches (each input and output array
  * counted once).  enable = 1 resets and starts, 0 stops.  Reading flushes
@@ -305,8 +322,11 @@ enum {
   TUMOR_K_COLINV64 = 0, TUMOR_K_COLFWD64, TUMOR_K_COLINV32, TUMOR_K_COLFWD32, TUMOR_K_XELAST64,
   TUMOR_K_XELAST32, TUMOR_K_XDIFF64, TUMOR_K_XDIFF32, TUMOR_K_XOTHER, TUMOR_K_SL, TUMOR_K_REACT,
   TUMOR_K_KRYLOV64, TUMOR_K_KRYLOV32,
-  TUMOR_K_ZINVP64, TUMOR_K_ZINVP32,      /* first pass with the fused direction update  */
+  TUMOR_K_ZINVP64, TUMOR_K_ZINVP32,      /* first pass with the fused direction update
+                                            (elasticity, 3 components)                 */
   TUMOR_K_COLDOT64, TUMOR_K_COLDOT32,    /* last pass with the fused inner product      */
+  TUMOR_K_COLINV32Z, TUMOR_K_COLFWD32Z,  /* FP32 z passes (COLINV32/COLFWD32: y passes)  */
+  TUMOR_K_ZINVP64_1, TUMOR_K_ZINVP32_1,  /* fused first pass of the CN solves (1 comp.)  */
   TUMOR_K_COUNT
 };
 int tumor_kernel_timer(tumor_ctx* ctx, int32_t kernel_class, int32_t enable);

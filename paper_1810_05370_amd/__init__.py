@@ -40,15 +40,19 @@ OPS = {"deriv_x": 0, "deriv_y": 1, "deriv_z": 2, "diffusion": 3, "elasticity": 4
 VECTOR_OPS = ("elasticity", "elast_precond", "force")
 KERNEL_CLASSES = {"colinv64": 0, "colfwd64": 1, "colinv32": 2, "colfwd32": 3, "xelast64": 4, "xelast32": 5,
                   "xdiff64": 6, "xdiff32": 7, "xother": 8, "sl": 9, "react": 10, "krylov64": 11, "krylov32": 12,
-                  "zinvp64": 13, "zinvp32": 14, "coldot64": 15, "coldot32": 16}
+                  "zinvp64": 13, "zinvp32": 14, "coldot64": 15, "coldot32": 16, "colinv32z": 17,
+                  "colfwd32z": 18, "zinvp64c1": 19, "zinvp32c1": 20}
 # rocprofv3 kernel names of each class (for cross-checking event timings against traces)
 KERNEL_NAMES = {"colinv64": "k_col_pass<double, {n}, true, false, 256>",
                 "colfwd64": "k_col_pass<double, {n}, false, false, 256>",
-                "colinv32": "k_col_pass<float, {n}, true, false, 128|256>",
-                "colfwd32": "k_col_pass<float, {n}, false, false, 128|256>",
+                "colinv32": "k_col_pass<float, {n}, true, false, 128>",
+                "colfwd32": "k_col_pass<float, {n}, false, false, 128>",
+                "colinv32z": "k_col_pass<float, {n}, true, false, 256>",
+                "colfwd32z": "k_col_pass<float, {n}, false, false, 256>",
                 "coldot64": "k_col_pass<double, {n}, false, true, 256>",
                 "coldot32": "k_col_pass<float, {n}, false, true, 256>",
-                "zinvp64": "k_zinv_pupdate<double, {n}, 1|3>", "zinvp32": "k_zinv_pupdate<float, {n}, 1|3>",
+                "zinvp64": "k_zinv_pupdate<double, {n}, 3>", "zinvp32": "k_zinv_pupdate<float, {n}, 3>",
+                "zinvp64c1": "k_zinv_pupdate<double, {n}, 1>", "zinvp32c1": "k_zinv_pupdate<float, {n}, 1>",
                 "xelast64": "k_xelast<double, {n}>", "xelast32": "k_xelast<float, {n}>",
                 "xdiff64": "k_xdiff<double, {n}>", "xdiff32": "k_xdiff<float, {n}>", "sl": "k_sl",
                 "react": "k_react"}
@@ -118,6 +122,9 @@ def load_library(path: Optional[str] = None):
         "tumor_tape_bytes": (ctypes.c_int, [ctypes.POINTER(TumorConfig), ctypes.c_int32, ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_size_t)]),
         "tumor_record": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_size_t]),
+        "tumor_state_bytes": (ctypes.c_int, [ctypes.POINTER(TumorConfig), ctypes.POINTER(ctypes.c_size_t)]),
+        "tumor_save_state": (ctypes.c_int, [P, P, ctypes.c_size_t]),
+        "tumor_load_state": (ctypes.c_int, [P, P, ctypes.c_size_t]),
         "tumor_get_field": (ctypes.c_int, [P, ctypes.c_int32, P]),
         "tumor_set_field": (ctypes.c_int, [P, ctypes.c_int32, P]),
         "tumor_refresh": (ctypes.c_int, [P]),
@@ -283,6 +290,27 @@ class Tumor:
         _check(self.lib.tumor_diagnose(self.ctx, float(threshold), _ptr(f) if fields else None, ctypes.byref(out)))
         d = {k: getattr(out, k) for k, _ in TumorDiagnostics._fields_}
         return (d, f) if fields else d
+
+    def state_bytes(self):
+        out = ctypes.c_size_t(0)
+        _check(self.lib.tumor_state_bytes(ctypes.byref(self.cfg), ctypes.byref(out)))
+        return out.value
+
+    def save_state(self, dst=None):
+        """Snapshot of the time-stepping state (species, u^n, u^{n-1}) in a
+        device uint8 tensor (``dst`` if given)."""
+        nb = self.state_bytes()
+        if dst is None:
+            dst = self._torch.empty(nb, dtype=self._torch.uint8, device=self.device)
+        if dst.numel() * dst.element_size() < nb or not dst.is_contiguous():
+            raise ValueError("snapshot buffer too small or not contiguous")
+        _check(self.lib.tumor_save_state(self.ctx, _ptr(dst), nb))
+        return dst
+
+    def load_state(self, src):
+        """Restore a snapshot taken by save_state (the coefficients are refreshed)."""
+        nb = src.numel() * src.element_size()
+        _check(self.lib.tumor_load_state(self.ctx, _ptr(src.contiguous()), nb))
 
     def get(self, name):
         torch = self._torch

@@ -367,8 +367,12 @@ void colp(Ctx& c, int axis, bool inv, const Prog& pr) {
       ndot += seen ? 0 : 1;
     }
   const double bytes = double(nin + pr.p.nout + ndot) * double(c.V) * sizeof(R);
-  const int cls = inv ? kcls<R>(TUMOR_K_COLINV64, TUMOR_K_COLINV32)
-                      : (pr.p.dsv ? kcls<R>(TUMOR_K_COLDOT64, TUMOR_K_COLDOT32) : kcls<R>(TUMOR_K_COLFWD64, TUMOR_K_COLFWD32));
+  // FP32 y and z passes are separate kernel instances (segment widths differ),
+  // so they are timed as separate classes; every class is one kernel symbol
+  const bool z32 = sizeof(R) == 4 && axis == 2;
+  const int cls = inv ? (z32 ? TUMOR_K_COLINV32Z : kcls<R>(TUMOR_K_COLINV64, TUMOR_K_COLINV32))
+                      : (pr.p.dsv ? kcls<R>(TUMOR_K_COLDOT64, TUMOR_K_COLDOT32)
+                                  : (z32 ? TUMOR_K_COLFWD32Z : kcls<R>(TUMOR_K_COLFWD64, TUMOR_K_COLFWD32)));
   timed(c, cls, bytes,
         [&] { tumor::launch_col_pass<R>(c.n, axis, inv, pr.p, pb<R>(c).tw, c.st); });
 }
@@ -413,7 +417,8 @@ void zinv_pupdate(Ctx& c, int ncomp, const Fuse& f, cplx<R>* p, void* const* out
   za.cs = c.cs;
   za.pc = f.pc;
   // reads r, p, x; writes p, x and the two transformed outputs
-  timed(c, kcls<R>(TUMOR_K_ZINVP64, TUMOR_K_ZINVP32), 7.0 * ncomp * double(c.V) * sizeof(R),
+  const int cls = ncomp == 3 ? kcls<R>(TUMOR_K_ZINVP64, TUMOR_K_ZINVP32) : kcls<R>(TUMOR_K_ZINVP64_1, TUMOR_K_ZINVP32_1);
+  timed(c, cls, 7.0 * ncomp * double(c.V) * sizeof(R),
         [&] { tumor::launch_zinv_pupdate<R>(c.n, ncomp, za, pb<R>(c).tw, c.st); });
 }
 
@@ -1973,6 +1978,42 @@ int tumor_kernel_timer_read(tumor_ctx* ctx, int32_t kernel_class, int64_t* launc
     if (launches) *launches = t ? t->launches : 0;
     if (ms) *ms = t ? t->ms : 0.0;
     if (bytes) *bytes = t ? t->bytes : 0.0;
+    return TUMOR_OK;
+  });
+}
+
+int tumor_state_bytes(const tumor_config* cfg, size_t* bytes) {
+  if (!bytes) return einval("bytes is NULL");
+  if (check_cfg(cfg) != TUMOR_OK) return einval("invalid tumor_config");
+  *bytes = slot_bytes((long long)cfg->n * cfg->n * cfg->n);
+  return TUMOR_OK;
+}
+
+int tumor_save_state(tumor_ctx* ctx, void* dst, size_t bytes) {
+  if (!ctx) return einval("ctx is NULL");
+  if (!dst) return einval("dst is NULL");
+  if (bytes < slot_bytes(ctx->V)) return einval("snapshot buffer smaller than tumor_state_bytes");
+  return guarded([&]() -> int {
+    save_state(*ctx, static_cast<double*>(dst));
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(ctx->st));
+    return TUMOR_OK;
+  });
+}
+
+int tumor_load_state(tumor_ctx* ctx, const void* src, size_t bytes) {
+  if (!ctx) return einval("ctx is NULL");
+  if (!src) return einval("src is NULL");
+  if (bytes < slot_bytes(ctx->V)) return einval("snapshot buffer smaller than tumor_state_bytes");
+  if (ctx->rec_active && (ctx->rec_steps < ctx->rec_nsteps || ctx->rev_done < ctx->rec_steps)) {
+    g_err = "a recording or its reverse sweep is in progress; loading a state would invalidate its tape";
+    return TUMOR_ESTATE;
+  }
+  return guarded([&]() -> int {
+    ctx->rec_active = 0;
+    load_state(*ctx, static_cast<const double*>(src));
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(ctx->st));
     return TUMOR_OK;
   });
 }

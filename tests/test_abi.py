@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.tumor_abi_version() == 2
+    assert lib.tumor_abi_version() == 3
 
 
 def test_struct_layouts_match_the_header(tmp_path):

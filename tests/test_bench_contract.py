@@ -72,3 +72,117 @@ def test_source_digest_ignores_comments_and_layout(tmp_path, monkeypatch):
     assert bench.kernel_sources_digest() == d0
     (src / "a.hip").write_text("int f(int x) { return x + 2; }\n")
     assert bench.kernel_sources_digest() != d0
+
+
+def test_cycle_plan_splits_into_runs_no_longer_than_the_window():
+    assert bench.cycle_plan(20, 10) == [10, 10]
+    assert bench.cycle_plan(25, 10) == [10, 10, 5]
+    assert bench.cycle_plan(5, 10) == [5]
+    assert bench.cycle_plan(0, 10) == []
+    for total in range(0, 60):
+        runs = bench.cycle_plan(total, 7)
+        assert sum(runs) == total and all(1 <= r <= 7 for r in runs)
+    with pytest.raises(ValueError):
+        bench.cycle_plan(3, 0)
+
+
+class _FakeEvent:
+    def __init__(self, **kw):
+        pass
+
+    def record(self, stream=None):
+        pass
+
+    def synchronize(self):
+        pass
+
+    def elapsed_time(self, other):
+        return 1.0
+
+
+class _FakeCuda:
+    Event = _FakeEvent
+
+    @staticmethod
+    def synchronize():
+        pass
+
+
+class _FakeTorch:
+    cuda = _FakeCuda
+
+
+class _FakeSim:
+    """Counts the trajectory step each call reaches: steps since t = 0 for the
+    prefix, then since the snapshot the window restarts from."""
+
+    def __init__(self, limit):
+        self.limit = limit
+        self.pos = 0
+        self.snap_pos = None
+        self.max_pos = 0
+        self.steps = 0
+        self.stream = None
+
+    def step(self, k=1):
+        assert k == 1
+        self.pos += 1
+        self.steps += 1
+        self.max_pos = max(self.max_pos, self.pos)
+        if self.pos > self.limit:
+            raise AssertionError(f"step {self.pos} lies past the stable window (last step {self.limit})")
+        return dict(it_elast=30, outer_elast=2, it_diff=[1, 1, 1])
+
+    def save_state(self):
+        self.snap_pos = self.pos
+        return "snapshot"
+
+    def load_state(self, snap):
+        assert snap == "snapshot"
+        self.pos = self.snap_pos
+
+    def kernel_timer(self, name, enable=True):
+        pass
+
+    def kernel_timer_read(self, name):
+        return dict(launches=1, ms=1.0 if name == "xelast32" else 0.5, bytes=1e9)
+
+    def diagnose(self, thr):
+        return dict(max_disp=1.0)
+
+    def get(self, name):
+        return name
+
+    def close(self):
+        pass
+
+
+@pytest.mark.parametrize("steps,warmup", [(20, 5), (10, 3), (1, 0), (37, 11)])
+def test_the_timed_steps_never_leave_the_stable_window(steps, warmup):
+    """The driver's --steps 20 --warmup 5 (and any other counts) queue no step
+    past the last step of the window; the timed count is exact."""
+    start, span = bench.WINDOWS["seeds3_n256"]
+    sims = []
+
+    class _TM:
+        F_DEFAULT = 0x7
+
+        @staticmethod
+        def from_inputs(inp, P, **kw):
+            sims.append(_FakeSim(start + span))
+            return sims[-1]
+
+    r = bench.run_form(_TM, _FakeTorch, {}, {}, "mixed", steps, warmup, (start, span), keep_fields=True)
+    sim = sims[0]
+    assert sim.max_pos <= start + span
+    assert len(r["stats"]) == steps
+    assert r["dominant"] == "xelast32"
+    s = bench.run_single(_TM, _FakeTorch, {}, {}, "mixed", steps, warmup, (start, span))
+    assert sims[1].max_pos <= start + span and len(s["elasticity_iterations"]) == steps
+
+
+def test_every_workload_the_benchmark_can_time_has_a_window():
+    import synthetic
+    for name in synthetic.WORKLOADS:
+        start, span = bench.WINDOWS[name]
+        assert start >= 0 and span >= 1

@@ -195,3 +195,30 @@ def test_max_it_reports_no_convergence():
     s = sim.step(1, allow_noconv=True)
     assert s["it_elast"] == 2
     sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_state_snapshot_restores_the_trajectory_bit_for_bit(precision):
+    """tumor_save_state / tumor_load_state: steps taken after a restore repeat
+    the saved trajectory exactly (the benchmark's timed runs rely on this)."""
+    torch = need_gpu()
+    P = synthetic.params()
+    inp = synthetic.workload_inputs("seeds3_n128", n=32)
+    say(f"snapshot case n=32 precision={precision}")
+    sim = tm.from_inputs(inp, P, precision=precision)
+    sim.step(2)
+    snap = sim.save_state()
+    assert snap.numel() == sim.state_bytes() >= 14 * 32 ** 3 * 8
+    a_stats = [sim.step(1) for _ in range(3)]
+    a = {k: sim.get(k) for k in SPECIES + ("u", "u_prev", "mu")}
+    sim.load_state(snap)
+    b_stats = [sim.step(1) for _ in range(3)]
+    b = {k: sim.get(k) for k in SPECIES + ("u", "u_prev", "mu")}
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+    assert [s["it_elast"] for s in a_stats] == [s["it_elast"] for s in b_stats]
+    assert [s["it_diff"] for s in a_stats] == [s["it_diff"] for s in b_stats]
+    # a snapshot too small for the state is refused before any device work
+    with pytest.raises(tm.TumorError):
+        sim.load_state(snap[:-1])
+    sim.close()
