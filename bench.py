@@ -228,6 +228,28 @@ def copy_ceiling(torch, mib=1024, reps=10):
                 note="median of %d event-timed launches, bytes = read + written" % reps)
 
 
+def lockstep_differences(tm, torch, inp, P, steps, form_a, form_b):
+    """Two contexts stepped side by side from t = 0; the relative L2 difference
+    of every species and of u after each step.  form = (precision, weight
+    factor of the initial condition)."""
+    sims = []
+    for prec, wfac in (form_a, form_b):
+        d = dict(inp)
+        d["weights"] = [w * wfac for w in inp["weights"]]
+        sims.append(tm.from_inputs(d, P, precision=prec))
+    out = []
+    for k in range(steps):
+        for sim in sims:
+            sim.step(1)
+        errs = rel_l2_errors({f: sims[0].get(f) for f in SPECIES + ("u",)},
+                             {f: sims[1].get(f) for f in SPECIES + ("u",)})
+        out.append({f: float(f"{v:.3e}") for f, v in errs.items()})
+    for sim in sims:
+        sim.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def rel_l2_errors(mixed, ref):
     """Relative L2 error of each field of the mixed form against the FP64 form."""
     out = {}
@@ -491,25 +513,29 @@ def main():
     extra["copy_ceiling"] = copy_ceiling(torch)
     log(f"copy ceiling: {extra['copy_ceiling']}")
     compare = not args.no_fp64 and precision != "fp64"
-    main_run = run_form(tm, torch, inp, P, precision, args.steps, args.warmup, window, keep_fields=compare)
+    main_run = run_form(tm, torch, inp, P, precision, args.steps, args.warmup, window)
     ms_per_step = main_run["gpu_ms"] / args.steps
     value = args.steps / (main_run["gpu_ms"] / 1e3)
     fp64_run = None
     if compare:
         torch.cuda.empty_cache()
-        fp64_run = run_form(tm, torch, inp, P, "fp64", args.steps, args.warmup, window, keep_fields=True)
+        fp64_run = run_form(tm, torch, inp, P, "fp64", args.steps, args.warmup, window)
         v64 = args.steps / (fp64_run["gpu_ms"] / 1e3)
         extra["fp64_steps_per_s"] = round(v64, 4)
         extra["mixed_speedup_over_fp64"] = round(value / v64, 3)
         extra["fp64_roofline"] = roofline(fp64_run["dom"], fp64_run["dominant"], n)
         # error of the mixed form against the FP64 form (itself held to the FP64
-        # oracle at 1e-10 by the parity tests), both after step start + span from t = 0
-        errs = rel_l2_errors(main_run["fields"], fp64_run["fields"])
-        extra["mixed_vs_fp64_rel_l2"] = dict(after_step=start + span,
-                                             **{k: float(f"{v:.3e}") for k, v in errs.items()})
-        log(f"mixed vs FP64 relative L2 after step {start + span}: {extra['mixed_vs_fp64_rel_l2']}")
-        main_run["fields"] = fp64_run["fields"] = None
-        torch.cuda.empty_cache()
+        # oracle at 1e-10 by the parity tests), after every step from t = 0 to the
+        # window's end; beside it, how far two FP64 runs whose initial tumour
+        # differs by 1e-12 (relative) drift apart over the same steps: the
+        # trajectory's own amplification of a small perturbation
+        by_step = lockstep_differences(tm, torch, inp, P, start + span, ("mixed", 1.0), ("fp64", 1.0))
+        extra["mixed_vs_fp64_rel_l2"] = dict(after_step=start + span, **by_step[-1])
+        extra["mixed_vs_fp64_rel_l2_by_step"] = {f: [e[f] for e in by_step] for f in ("p", "i", "o", "u")}
+        pert = lockstep_differences(tm, torch, inp, P, start + span, ("fp64", 1.0 + 1e-12), ("fp64", 1.0))
+        extra["fp64_ic_perturbation_1e-12_rel_l2_by_step"] = {f: [e[f] for e in pert] for f in ("p", "i", "o", "u")}
+        log(f"mixed vs FP64 relative L2 by step: {extra['mixed_vs_fp64_rel_l2_by_step']}")
+        log(f"FP64 1e-12 IC perturbation by step: {extra['fp64_ic_perturbation_1e-12_rel_l2_by_step']}")
     it_e = [s["it_elast"] for s in main_run["stats"]]
     extra["timed_runs"] = dict(window_steps=[start + 1, start + span], runs=cycle_plan(args.steps, span),
                                note="each run restarts from a device snapshot of the state after step "
