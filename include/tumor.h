@@ -186,6 +186,31 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
                int32_t n_ic, const double* ic_centers, const double* ic_sigmas,
                const double* ic_weights, void* hip_stream);
 
+/* Allocation-free context, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same as tumor_init, with the same arguments except the
+ * workspace: the context carves a fixed array of TUMOR_STATIC_WS_BYTES that the
+ * library itself holds on each GPU it runs on (reserved with the code object,
+ * kept until the process ends), and its host storage (scalar read-back, the
+ * initial-condition table) is static too.  The call allocates no device or
+ * pinned host memory and calls no allocating routine on success (an error
+ * message is a host string).
+ *   Limits: tumor_workspace_bytes(cfg) <= TUMOR_STATIC_WS_BYTES (every n <= 32,
+ *   both precisions, with or without TUMOR_F_ADJOINT), n_ic <= 256; otherwise
+ *   TUMOR_EINVAL with a message, before any device work.
+ *   One such context per GPU at a time: while one is live on the current device
+ *   a second call returns TUMOR_ESTATE.  tumor_destroy releases the array.  The
+ *   array keeps the last context's contents; tumor_init_static clears whatever
+ *   must start at zero.  Contexts of the same GPU created on different threads
+ *   would race on the array, which is why a second live one is refused.
+ *   Every other entry point works on such a context as on any other; a tape
+ *   for the adjoint (tumor_record) is still caller memory. */
+#define TUMOR_STATIC_WS_BYTES (32u << 20)
+int tumor_init_static(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm,
+                      const double* wm, const double* gm, const double* csf,
+                      int32_t n_ic, const double* ic_centers, const double* ic_sigmas,
+                      const double* ic_weights, void* hip_stream);
+
 /* Advance nsteps split steps (Sec. 3, multispecies splitting).  `last` (host,
  * nullable) receives the statistics of the final step.  TUMOR_ENOCONV: a solve
  * hit max_it (the step still completed with the last iterate). */

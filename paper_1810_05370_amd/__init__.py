@@ -113,6 +113,8 @@ def load_library(path: Optional[str] = None):
         "tumor_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(TumorConfig), ctypes.POINTER(ctypes.c_size_t)]),
         "tumor_init": (ctypes.c_int, [ctypes.POINTER(P), ctypes.POINTER(TumorConfig), ctypes.POINTER(TumorParams),
                                       P, ctypes.c_size_t, P, P, P, ctypes.c_int32, P, P, P, P]),
+        "tumor_init_static": (ctypes.c_int, [ctypes.POINTER(P), ctypes.POINTER(TumorConfig),
+                                             ctypes.POINTER(TumorParams), P, P, P, ctypes.c_int32, P, P, P, P]),
         "tumor_step": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(TumorStepStats)]),
         "tumor_solve_elasticity": (ctypes.c_int, [P, P, P, ctypes.POINTER(ctypes.c_int32),
                                                   ctypes.POINTER(ctypes.c_double)]),
@@ -190,11 +192,14 @@ class Tumor:
 
     wm, gm, csf: float64 device tensors of shape (n, n, n), [z][y][x].
     centers (k, 3) as (x, y, z), sigmas (k,), weights (k,): host arrays.
+    no_alloc: create the context with tumor_init_static (the library's own
+    fixed workspace on the device, n <= 32; one such context per GPU at a time)
+    instead of a workspace tensor.
     """
 
     def __init__(self, n, params: dict, wm, gm, csf, centers=(), sigmas=(), weights=(),
                  precision="fp64", dt=0.01, rtol_diff=1e-8, rtol_elast=1e-8, max_it=1000,
-                 flags=F_DEFAULT, stream=None, model="multispecies"):
+                 flags=F_DEFAULT, stream=None, model="multispecies", no_alloc=False):
         import torch
         self._torch = torch
         lib = load_library()
@@ -202,14 +207,17 @@ class Tumor:
         self.n = int(n)
         self.cfg = make_config(n, precision, dt, rtol_diff, rtol_elast, max_it, flags, model)
         self.prm = make_params(params)
-        nb = workspace_bytes(self.cfg)
         dev = wm.device
         self.device = dev
-        self.workspace = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
-        base = self.workspace.data_ptr()
-        off = (-base) % 256
-        self._ws_ptr = ctypes.c_void_p(base + off)
-        self._ws_bytes = nb
+        if no_alloc:
+            self.workspace = None
+        else:
+            nb = workspace_bytes(self.cfg)
+            self.workspace = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+            base = self.workspace.data_ptr()
+            off = (-base) % 256
+            self._ws_ptr = ctypes.c_void_p(base + off)
+            self._ws_bytes = nb
         for t in (wm, gm, csf):
             if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != (n, n, n):
                 raise ValueError("tissue maps must be contiguous float64 (n, n, n) device tensors")
@@ -222,10 +230,15 @@ class Tumor:
             raise ValueError("centers must be (k, 3), sigmas and weights (k,)")
         ctx = ctypes.c_void_p()
         torch.cuda.synchronize(dev)
-        code = lib.tumor_init(ctypes.byref(ctx), ctypes.byref(self.cfg), ctypes.byref(self.prm),
-                              self._ws_ptr, nb, _ptr(wm), _ptr(gm), _ptr(csf), nic,
-                              cp if nic else None, sp if nic else None, wp if nic else None,
-                              ctypes.c_void_p(self.stream.cuda_stream))
+        ic = (cp if nic else None, sp if nic else None, wp if nic else None)
+        if no_alloc:
+            code = lib.tumor_init_static(ctypes.byref(ctx), ctypes.byref(self.cfg), ctypes.byref(self.prm),
+                                         _ptr(wm), _ptr(gm), _ptr(csf), nic, *ic,
+                                         ctypes.c_void_p(self.stream.cuda_stream))
+        else:
+            code = lib.tumor_init(ctypes.byref(ctx), ctypes.byref(self.cfg), ctypes.byref(self.prm),
+                                  self._ws_ptr, self._ws_bytes, _ptr(wm), _ptr(gm), _ptr(csf), nic, *ic,
+                                  ctypes.c_void_p(self.stream.cuda_stream))
         _check(code)
         self.ctx = ctx
         self.n_ic = nic

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -158,6 +159,7 @@ struct tumor_ctx {
   tumor::ReactConsts rc;
   KTimer* timers[TUMOR_K_COUNT];
   int cur_tag;  // PCG iteration index of the launches being queued (-1 outside loops)
+  int static_dev;  // device of an allocation-free context (tumor_init_static), else -1
 };
 
 namespace {
@@ -931,15 +933,17 @@ int check_params(const tumor_params* p) {
 
 void twiddles(Ctx& c) {
   const int n = c.n;
-  std::vector<cplx<double>> t64(n);
-  std::vector<cplx<float>> t32(n);
+  // n <= 512 (check_cfg): the tables live on the stack, so that context set-up
+  // needs no host heap either
+  cplx<double> t64[512];
+  cplx<float> t32[512];
   for (int m = 0; m < n; ++m) {
     const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
     t64[m] = {(double)cosl(ang), (double)sinl(ang)};
     t32[m] = {(float)cosl(ang), (float)sinl(ang)};
   }
-  HIPCHECK(hipMemcpyAsync(c.p64.tw, t64.data(), n * sizeof(cplx<double>), hipMemcpyHostToDevice, c.st));
-  HIPCHECK(hipMemcpyAsync(c.p32.tw, t32.data(), n * sizeof(cplx<float>), hipMemcpyHostToDevice, c.st));
+  HIPCHECK(hipMemcpyAsync(c.p64.tw, t64, n * sizeof(cplx<double>), hipMemcpyHostToDevice, c.st));
+  HIPCHECK(hipMemcpyAsync(c.p32.tw, t32, n * sizeof(cplx<float>), hipMemcpyHostToDevice, c.st));
   HIPCHECK(hipStreamSynchronize(c.st));
 }
 
@@ -1477,15 +1481,23 @@ int tumor_workspace_bytes(const tumor_config* cfg, size_t* bytes) {
   return TUMOR_OK;
 }
 
-int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm, void* workspace,
-               size_t ws_bytes, const double* wm, const double* gm, const double* csf, int32_t n_ic,
-               const double* ic_centers, const double* ic_sigmas, const double* ic_weights, void* hip_stream) {
-  if (!out) return einval("out is NULL");
-  *out = nullptr;
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free contexts
+// One fixed workspace per GPU for tumor_init_static, in device memory that the
+// code object itself reserves (held until the process ends).  In host code its
+// name is only a stand-in: the device address comes from hipGetSymbolAddress,
+// once per device, and only that address is ever passed on.
+static __device__ __align__(256) unsigned char scratch[TUMOR_STATIC_WS_BYTES];
+
+namespace {
+
+// Argument checks shared by tumor_init and tumor_init_static.
+int check_init(const tumor_config* cfg, const tumor_params* prm, const double* wm, const double* gm,
+               const double* csf, int32_t n_ic, const double* ic_centers, const double* ic_sigmas,
+               const double* ic_weights) {
   if (check_cfg(cfg) != TUMOR_OK) return einval("invalid tumor_config");
   if (check_params(prm) != TUMOR_OK) return einval("invalid tumor_params");
-  if (!workspace) return einval("workspace is NULL");
-  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return einval("workspace is not 256-byte aligned");
   if (!wm || !gm || !csf) return einval("tissue map pointer is NULL");
   if (n_ic < 0) return einval("n_ic < 0");
   if (n_ic > 0 && (!ic_centers || !ic_sigmas || !ic_weights)) return einval("initial-condition array is NULL");
@@ -1495,20 +1507,19 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
     for (int a = 0; a < 3; ++a)
       if (!std::isfinite(ic_centers[3 * k + a])) return einval("ic_centers must be finite");
   }
-  const size_t need = workspace_size(*cfg);
-  if (ws_bytes < need) {
-    g_err = "workspace too small: need " + std::to_string(need) + " bytes";
-    return TUMOR_ENOMEM;
-  }
   const long long V = (long long)cfg->n * cfg->n * cfg->n;
   if (5LL * n_ic > V) return einval("too many initial-condition centres for this grid");
-  tumor_ctx* c = new (std::nothrow) tumor_ctx;
-  if (!c) {
-    g_err = "host allocation failed";
-    return TUMOR_ENOMEM;
-  }
-  std::memset(c, 0, sizeof(*c));
-  int rc = guarded([&]() -> int {
+  return TUMOR_OK;
+}
+
+// Set up a context whose host storage (c itself, c->hsv, c->hcs and c->ic_host
+// with room for 5 n_ic + 1 doubles) the caller provides, on `workspace`.
+// Allocates nothing: device work is copies, fills and kernels.
+int init_context(Ctx* c, const tumor_config* cfg, const tumor_params* prm, void* workspace, const double* wm,
+                 const double* gm, const double* csf, int32_t n_ic, const double* ic_centers,
+                 const double* ic_sigmas, const double* ic_weights, void* hip_stream) {
+  return guarded([&]() -> int {
+    const long long V = (long long)cfg->n * cfg->n * cfg->n;
     c->cfg = *cfg;
     c->prm = *prm;
     c->st = static_cast<hipStream_t>(hip_stream);
@@ -1525,12 +1536,6 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
     if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) throw Fail(TUMOR_EDEVICE, "no HIP device");
     Carver cv{static_cast<char*>(workspace), 0, false};
     layout(*c, cv);
-    void* h1 = nullptr;
-    void* h2 = nullptr;
-    HIPCHECK(hipHostMalloc(&h1, sizeof(tumor::SolveScalars), hipHostMallocDefault));
-    HIPCHECK(hipHostMalloc(&h2, sizeof(tumor::CoefScalars), hipHostMallocDefault));
-    c->hsv = static_cast<tumor::SolveScalars*>(h1);
-    c->hcs = static_cast<tumor::CoefScalars*>(h2);
     c->pred[0] = c->pred[1] = c->pred[2] = c->pred[4] = c->pred[5] = c->pred[6] = 6;
     c->pred[3] = c->pred[7] = 30;
     for (int w = 0; w < 8; ++w) {
@@ -1552,25 +1557,19 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
     HIPCHECK(hipMemsetAsync(c->F[N], 0, fb, c->st));
     HIPCHECK(hipMemsetAsync(c->F[L], 0, fb, c->st));
     HIPCHECK(hipMemsetAsync(c->BG, 0, fb, c->st));
-    {
-      std::vector<double> o(V, prm->o_heal);
-      HIPCHECK(hipMemcpyAsync(c->F[O], o.data(), fb, hipMemcpyHostToDevice, c->st));
-      std::vector<double> ic(5 * (size_t)n_ic);
-      for (int k = 0; k < n_ic; ++k) {
-        ic[5 * k + 0] = ic_centers[3 * k + 0];
-        ic[5 * k + 1] = ic_centers[3 * k + 1];
-        ic[5 * k + 2] = ic_centers[3 * k + 2];
-        ic[5 * k + 3] = ic_sigmas[k];
-        ic[5 * k + 4] = ic_weights[k];
-      }
-      if (n_ic > 0)
-        HIPCHECK(hipMemcpyAsync(c->G[0], ic.data(), ic.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
-      tumor::launch_ic(c->n, c->G[0], n_ic, c->F[P], c->st);
-      HIPCHECK(hipStreamSynchronize(c->st));  // host vectors go out of scope
-      c->n_ic = n_ic;
-      c->ic_host = new double[5 * (size_t)n_ic + 1];
-      std::memcpy(c->ic_host, ic.data(), ic.size() * sizeof(double));
+    tumor::launch_fill(c->F[O], prm->o_heal, V, c->st);
+    double* ic = c->ic_host;
+    for (int k = 0; k < n_ic; ++k) {
+      ic[5 * k + 0] = ic_centers[3 * k + 0];
+      ic[5 * k + 1] = ic_centers[3 * k + 1];
+      ic[5 * k + 2] = ic_centers[3 * k + 2];
+      ic[5 * k + 3] = ic_sigmas[k];
+      ic[5 * k + 4] = ic_weights[k];
     }
+    if (n_ic > 0)
+      HIPCHECK(hipMemcpyAsync(c->G[0], ic, 5 * (size_t)n_ic * sizeof(double), hipMemcpyHostToDevice, c->st));
+    tumor::launch_ic(c->n, c->G[0], n_ic, c->F[P], c->st);
+    c->n_ic = n_ic;
     const size_t ub = 3 * c->S * sizeof(cplx<double>);
     HIPCHECK(hipMemsetAsync(c->U, 0, ub, c->st));
     HIPCHECK(hipMemsetAsync(c->Up, 0, ub, c->st));
@@ -1580,13 +1579,115 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
     HIPCHECK(hipStreamSynchronize(c->st));
     return TUMOR_OK;
   });
+}
+
+constexpr int kStaticDevices = 64;
+constexpr int kStaticMaxIC = 256;
+
+struct StaticSlot {
+  void* ws;      // device address of `scratch` on this device (null until looked up)
+  bool in_use;   // a live context holds the array
+  tumor_ctx ctx;
+  tumor::SolveScalars hsv;
+  tumor::CoefScalars hcs;
+  double ic[5 * kStaticMaxIC + 1];
+};
+StaticSlot g_static[kStaticDevices];
+std::mutex g_static_mu;
+
+}  // namespace
+
+extern "C" {
+
+int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm, void* workspace,
+               size_t ws_bytes, const double* wm, const double* gm, const double* csf, int32_t n_ic,
+               const double* ic_centers, const double* ic_sigmas, const double* ic_weights, void* hip_stream) {
+  if (!out) return einval("out is NULL");
+  *out = nullptr;
+  int rc = check_init(cfg, prm, wm, gm, csf, n_ic, ic_centers, ic_sigmas, ic_weights);
+  if (rc != TUMOR_OK) return rc;
+  if (!workspace) return einval("workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return einval("workspace is not 256-byte aligned");
+  const size_t need = workspace_size(*cfg);
+  if (ws_bytes < need) {
+    g_err = "workspace too small: need " + std::to_string(need) + " bytes";
+    return TUMOR_ENOMEM;
+  }
+  tumor_ctx* c = new (std::nothrow) tumor_ctx;
+  if (!c) {
+    g_err = "host allocation failed";
+    return TUMOR_ENOMEM;
+  }
+  std::memset(c, 0, sizeof(*c));
+  c->static_dev = -1;
+  c->ic_host = new (std::nothrow) double[5 * (size_t)n_ic + 1];
+  void* h1 = nullptr;
+  void* h2 = nullptr;
+  if (c->ic_host && hipHostMalloc(&h1, sizeof(tumor::SolveScalars), hipHostMallocDefault) == hipSuccess &&
+      hipHostMalloc(&h2, sizeof(tumor::CoefScalars), hipHostMallocDefault) == hipSuccess) {
+    c->hsv = static_cast<tumor::SolveScalars*>(h1);
+    c->hcs = static_cast<tumor::CoefScalars*>(h2);
+    rc = init_context(c, cfg, prm, workspace, wm, gm, csf, n_ic, ic_centers, ic_sigmas, ic_weights, hip_stream);
+  } else {
+    g_err = "host allocation failed";
+    rc = TUMOR_ENOMEM;
+  }
   if (rc != TUMOR_OK) {
-    if (c->hsv) (void)hipHostFree(c->hsv);
-    if (c->hcs) (void)hipHostFree(c->hcs);
+    if (h1) (void)hipHostFree(h1);
+    if (h2) (void)hipHostFree(h2);
     delete[] c->ic_host;
     delete c;
     return rc;
   }
+  *out = c;
+  return TUMOR_OK;
+}
+
+int tumor_init_static(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm, const double* wm,
+                      const double* gm, const double* csf, int32_t n_ic, const double* ic_centers,
+                      const double* ic_sigmas, const double* ic_weights, void* hip_stream) {
+  if (!out) return einval("out is NULL");
+  *out = nullptr;
+  int rc = check_init(cfg, prm, wm, gm, csf, n_ic, ic_centers, ic_sigmas, ic_weights);
+  if (rc != TUMOR_OK) return rc;
+  const size_t need = workspace_size(*cfg);
+  if (need > (size_t)TUMOR_STATIC_WS_BYTES) {
+    g_err = "configuration needs " + std::to_string(need) + " bytes of workspace; the allocation-free context holds " +
+            std::to_string((size_t)TUMOR_STATIC_WS_BYTES) + " (n <= 32)";
+    return TUMOR_EINVAL;
+  }
+  if (n_ic > kStaticMaxIC) return einval("the allocation-free context holds at most 256 initial-condition centres");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+    g_err = "no current HIP device";
+    return TUMOR_EDEVICE;
+  }
+  if (dev >= kStaticDevices) return einval("device index beyond the allocation-free context table");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticSlot& s = g_static[dev];
+  if (s.in_use) {
+    g_err = "the allocation-free workspace of this device is held by a live context";
+    return TUMOR_ESTATE;
+  }
+  if (!s.ws) {
+    // once per device, with that device current (hipGetDevice above)
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      g_err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+      return TUMOR_EDEVICE;
+    }
+    s.ws = ptr;
+  }
+  tumor_ctx* c = &s.ctx;
+  std::memset(c, 0, sizeof(*c));
+  c->static_dev = dev;
+  c->hsv = &s.hsv;
+  c->hcs = &s.hcs;
+  c->ic_host = s.ic;
+  rc = init_context(c, cfg, prm, s.ws, wm, gm, csf, n_ic, ic_centers, ic_sigmas, ic_weights, hip_stream);
+  if (rc != TUMOR_OK) return rc;
+  s.in_use = true;
   *out = c;
   return TUMOR_OK;
 }
@@ -2025,6 +2126,13 @@ void tumor_destroy(tumor_ctx* ctx) {
     if (!ctx->timers[k]) continue;
     for (int e = 0; e < 2 * kMaxPend; ++e) (void)hipEventDestroy(ctx->timers[k]->ev[e]);
     delete ctx->timers[k];
+  }
+  for (int k = 0; k < TUMOR_K_COUNT; ++k) ctx->timers[k] = nullptr;
+  if (ctx->static_dev >= 0) {
+    // allocation-free context: its storage is the device's static slot
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static[ctx->static_dev].in_use = false;
+    return;
   }
   if (ctx->hsv) (void)hipHostFree(ctx->hsv);
   if (ctx->hcs) (void)hipHostFree(ctx->hcs);

@@ -81,6 +81,8 @@ void launch_react(const ReactArgs& a, hipStream_t st);
 
 // p0 = sum_k w_k exp(-|x - c_k|_per^2 / (2 s_k^2)); ic = n_ic x (cx, cy, cz, s, w)
 void launch_ic(int n, const double* ic, int n_ic, double* p0, hipStream_t st);
+// p[0 .. count) = value
+void launch_fill(double* p, double value, long long count, hipStream_t st);
 
 // Semi-Lagrangian step (Sec. 3).  v: velocity components and divergence
 // (physical).  RC: arithmetic type of the interpolation weights and sums.

@@ -358,6 +358,18 @@ __global__ void k_ic(int n, const double* __restrict__ ic, int n_ic, double* __r
   }
 }
 
+__global__ void k_fill(double* __restrict__ p, double value, long long count) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < count;
+       v += (long long)gridDim.x * blockDim.x)
+    p[v] = value;
+}
+
+void launch_fill(double* p, double value, long long count, hipStream_t st) {
+  long long blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks > 0) hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, value, count);
+}
+
 void launch_ic(int n, const double* ic, int n_ic, double* p0, hipStream_t st) {
   const long long V = (long long)n * n * n;
   long long blocks = (V + 255) / 256;

@@ -137,3 +137,31 @@ def test_init_validates_arguments_before_the_device(lib):
                           fake, fake, fake, 1, ctypes.cast(c3, ctypes.c_void_p), ctypes.cast(s, ctypes.c_void_p),
                           ctypes.cast(w, ctypes.c_void_p), None) == tm.EINVAL
     assert not ctx.value
+
+
+def test_static_init_rejects_oversize_configurations_before_the_device(lib):
+    """tumor_init_static: a workspace beyond TUMOR_STATIC_WS_BYTES (n > 32) or
+    more than 256 seeds is refused with a message, before any device call."""
+    import synthetic
+    prm = tm.make_params(synthetic.params())
+    ctx = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    for n, prec in ((64, "fp64"), (64, "mixed"), (128, "fp64")):
+        cfg = tm.make_config(n, prec)
+        assert lib.tumor_init_static(ctypes.byref(ctx), ctypes.byref(cfg), ctypes.byref(prm), fake, fake, fake,
+                                     0, None, None, None, None) == tm.EINVAL
+        assert b"allocation-free" in lib.tumor_last_error()
+    # every n <= 32 fits, in both precisions and with the adjoint scratch
+    for prec in ("fp64", "mixed"):
+        assert tm.workspace_bytes(tm.make_config(32, prec, flags=tm.F_DEFAULT | tm.F_ADJOINT)) <= 32 << 20
+    k = 257
+    c3 = (ctypes.c_double * (3 * k))(*([1.0] * 3 * k))
+    s = (ctypes.c_double * k)(*([0.2] * k))
+    w = (ctypes.c_double * k)(*([0.1] * k))
+    cfg = tm.make_config(32)
+    assert lib.tumor_init_static(ctypes.byref(ctx), ctypes.byref(cfg), ctypes.byref(prm), fake, fake, fake, k,
+                                 ctypes.cast(c3, ctypes.c_void_p), ctypes.cast(s, ctypes.c_void_p),
+                                 ctypes.cast(w, ctypes.c_void_p), None) == tm.EINVAL
+    assert lib.tumor_init_static(None, ctypes.byref(cfg), ctypes.byref(prm), fake, fake, fake, 0,
+                                 None, None, None, None) == tm.EINVAL
+    assert not ctx.value
