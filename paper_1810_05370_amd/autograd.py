@@ -53,12 +53,18 @@ class _Simulate(torch.autograd.Function):
         sim = Tumor(n, P, t(inp["wm"]), t(inp["gm"]), t(inp["csf"]), inp["centers"], inp["sigmas"], weights,
                     precision=spec.precision, rtol_diff=spec.rtol, rtol_elast=spec.rtol, max_it=spec.max_it,
                     flags=spec.flags | F_ADJOINT)
-        sim.record(spec.steps, spec.ckpt_every)
-        spec.last["stats"] = sim.step(spec.steps)
-        tau = sim.get("p") + sim.get("i") + sim.get("n")
+        try:
+            sim.record(spec.steps, spec.ckpt_every)
+            spec.last["stats"] = sim.step(spec.steps)
+            tau = sim.get("p") + sim.get("i") + sim.get("n")
+        except BaseException:
+            sim.close()          # frees the context; the tape and workspace go with the tensors
+            raise
         ctx.sim = sim
         ctx.spec = spec
         ctx.n_theta = th.size
+        ctx.theta_device = theta.device
+        ctx.theta_dtype = theta.dtype
         return tau
 
     @staticmethod
@@ -70,11 +76,14 @@ class _Simulate(torch.autograd.Function):
         for k in range(3):
             lam[k].copy_(tb)
         grad = np.zeros(ctx.n_theta)
-        for s in range(spec.steps):
-            sim.adjoint_step(lam, grad)
-        sim.close()
-        ctx.sim = None
-        return torch.as_tensor(grad, dtype=torch.float64), None
+        try:
+            for s in range(spec.steps):
+                sim.adjoint_step(lam, grad)
+        finally:
+            sim.close()
+            ctx.sim = None
+        # the gradient lives where theta lives, in theta's dtype
+        return torch.as_tensor(grad, dtype=torch.float64).to(device=ctx.theta_device, dtype=ctx.theta_dtype), None
 
 
 def simulate(theta: torch.Tensor, spec: SimSpec) -> torch.Tensor:

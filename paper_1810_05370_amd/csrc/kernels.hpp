@@ -12,8 +12,9 @@ constexpr int kRedThreads = 256;
 constexpr int kRedBlocksMax = 1024;
 constexpr int kPartialsPerBlock = 16;
 
-// Device scalars of one PCG solve.  Written by the last block of each
-// reduction kernel, read by the following kernels and by the host.
+// Device scalars of one PCG solve.  Written by a one-block totalling kernel
+// (k_fin_*) from the reduction kernels' per-block partials, read by the
+// following kernels and by the host.
 struct SolveScalars {
   double bb;      // ||b||^2 (spectral, Parseval-weighted)
   double rr;      // ||r||^2 of the current residual

@@ -222,3 +222,27 @@ def test_autograd_function_gradient_and_directional_fd():
         fd = (loss_of(th + e * d).item() - loss_of(th - e * d).item()) / (2 * e)
     say("directional", fd, float(g @ d.numpy()))
     assert abs(fd - g @ d.numpy()) < 1e-6 * abs(fd)
+
+
+def test_autograd_gradient_lands_on_the_device_and_dtype_of_theta():
+    """theta on the GPU (float64 and float32): backward returns the gradient
+    there, equal to the host-theta gradient."""
+    torch = need_gpu()
+    from paper_1810_05370_amd.autograd import SimSpec, simulate, theta_from
+    steps = 2
+    P, inp, target = _case("lattice_n128", 16, steps, dict(delta_p=60.0))
+    spec = SimSpec(inputs=inp, params=P, steps=steps, ckpt_every=1, rtol=1e-12, max_it=2000)
+    h3 = (2 * np.pi / 16) ** 3
+    tgt = torch.as_tensor(target).cuda()
+    grads = {}
+    for dev, dt in (("cpu", torch.float64), ("cuda", torch.float64), ("cuda", torch.float32)):
+        say(f"autograd theta on {dev} {dt}")
+        theta = theta_from(P, inp["weights"]).to(device=dev, dtype=dt).requires_grad_(True)
+        L = 0.5 * h3 * ((simulate(theta, spec) - tgt) ** 2).sum()
+        L.backward()
+        assert theta.grad.device.type == dev and theta.grad.dtype == dt
+        grads[(dev, dt)] = theta.grad.detach().double().cpu().numpy()
+    ref = grads[("cpu", torch.float64)]
+    assert rel_l2(grads[("cuda", torch.float64)], ref) < 1e-12
+    # float32 theta rounds the parameters themselves, so the bar is float32's
+    assert rel_l2(grads[("cuda", torch.float32)], ref) < 1e-5
