@@ -222,8 +222,7 @@ void layout(Ctx& c, Carver& cv) {
   c.eta = cv.take<double>(V);
   for (int k = 0; k < 4; ++k) c.vel[k] = cv.take<double>(V);
   c.b64 = cv.take<cplx<double>>(3 * S);
-  // The 16 FP64 pass buffers are one contiguous block: during transport it
-  // holds the node-interleaved gather copies (12 V values, see launch_sl).
+  // The 16 FP64 pass buffers are one contiguous block.
   cplx<double>* ab = cv.take<cplx<double>>(16 * S);
   for (int k = 0; k < 8; ++k) c.p64.A[k] = ab + k * S;
   for (int k = 0; k < 8; ++k) c.p64.B[k] = ab + (8 + k) * S;
@@ -975,12 +974,12 @@ void transport(Ctx& c, const double* const (&ins)[6], double* const (&outs)[6], 
   s.n_grid = c.n;
   s.dt = frac * c.cfg.dt;
   s.s = frac * c.cfg.dt / (2.0 * M_PI / c.n);
-  // pack: 10 FP64 reads, 12 RC writes; gather: 4 FP64 + 12 RC reads, 6 FP64
-  // writes; FP32 adds the scan for the scales (6 FP64 reads).
+  // the tiled step reads v (3), div v and the six fields once and writes six
+  // fields (16 FP64 arrays); FP32 adds the scan for the scales (6 FP64 reads)
   HIPCHECK(hipMemsetAsync(&c.cs->cfl_bits, 0, 7 * sizeof(unsigned long long), c.st));  // cfl + qmax[6]
-  timed(c, TUMOR_K_SL, (c.mixed ? 26.0 * 8.0 + 24.0 * 4.0 : 44.0 * 8.0) * c.V, [&] {
-    if (c.mixed) tumor::launch_sl<float>(s, c.p64.A[0], c.cs, c.st);
-    else tumor::launch_sl<double>(s, c.p64.A[0], c.cs, c.st);
+  timed(c, TUMOR_K_SL, (c.mixed ? 22.0 : 16.0) * 8.0 * c.V, [&] {
+    if (c.mixed) tumor::launch_sl_tile<float>(s, c.cs, c.st);
+    else tumor::launch_sl_tile<double>(s, c.cs, c.st);
   });
 }
 

@@ -94,11 +94,12 @@ struct SLArgs {
   int n_grid;
   double dt, s;  // s = dt / h
 };
-// Packs the gathered fields into `packed` (12 V values of RC: v4 then q8),
-// then runs the step.  cs->cfl_bits and cs->qmax_bits must be zero on entry;
-// max |dt v| / h is max-combined into cfl_bits.
+// The semi-Lagrangian step (RK2 characteristics, tricubic values from LDS halo
+// tiles, Heun source) in the interpolation type RC.  cs->cfl_bits and
+// cs->qmax_bits must be zero on entry; max |dt v| / h is max-combined into
+// cfl_bits.
 template <typename RC>
-void launch_sl(const SLArgs& a, void* packed, CoefScalars* cs, hipStream_t st);
+void launch_sl_tile(const SLArgs& a, CoefScalars* cs, hipStream_t st);
 
 // Tricubic Lagrange interpolation at arbitrary grid-index points.
 void launch_interp(int n, const double* q, const double* jx, const double* jy, const double* jz,

@@ -6,6 +6,7 @@
 // read.  The grid size of a reduction kernel is a fixed function of the
 // problem size, so results do not depend on timing.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -466,115 +467,226 @@ __device__ __forceinline__ void block_max_cfl(double c, CoefScalars* cs) {
   }
 }
 
-// Node-interleaved copies of the gathered fields (the interpolation type RC):
-//   v4[node] = (v_x, v_y, v_z, 0)                       gathered at X*
-//   q8[node] = (s_p p, s_i i, s_n n, s_g g, s_w w, s_f f, div v, 0)   at X
-// with s_q = 1 in FP64 and the power-of-two scale of max |q| in FP32.
-// Scaling by a power of two and rounding commute, and the interpolation and
-// the Heun update are linear in q, so the packed copies change no result
-// while FP32 values stay in range; fields far below it (the necrotic cells
-// early on, say) keep FP32's relative precision instead of flushing to zero.
-// The copies turn the ten separate gathers of every stencil node into one
-// (v4) and one (q8) contiguous load.  The same pass publishes
-// max |dt v| / h with one atomic max per block.
-// Grid-stride over the nodes with at most kPackBlocks blocks: one atomic max
-// per block on a single address serialises, so the block count is kept small.
-constexpr int kPackBlocks = 2048;
-template <typename RC>
-__global__ void __launch_bounds__(256) k_sl_pack(SLArgs a, RC* __restrict__ v4, RC* __restrict__ q8,
-                                                 CoefScalars* cs) {
-  const long long V = (long long)a.n_grid * a.n_grid * a.n_grid;
-  double sc[6];
-#pragma unroll
-  for (int f = 0; f < 6; ++f) sc[f] = sizeof(RC) == sizeof(double) ? 1.0 : pow2_scale(cs->qmax_bits[f]);
-  const double* const src[6] = {a.p, a.i, a.n, a.g, a.w, a.f};
-  double vmax = 0.0;
-  for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < V; v += (long long)gridDim.x * 256) {
-    const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v];
-    RC* o = v4 + 4 * v;
-    o[0] = RC(vx);
-    o[1] = RC(vy);
-    o[2] = RC(vz);
-    o[3] = RC(0);
-    RC* q = q8 + 8 * v;
-#pragma unroll
-    for (int f = 0; f < 6; ++f) q[f] = RC(sc[f] * src[f][v]);
-    q[6] = RC(a.div[v]);
-    q[7] = RC(0);
-    const double c = a.s * sqrt(vx * vx + vy * vy + vz * vz);
-    vmax = (c >= 0.0 && vmax >= 0.0) ? fmax(vmax, c) : -1.0;  // -1: a NaN was seen
-  }
-  block_max_cfl(vmax, cs);
-}
-
-
-// W consecutive RC values of one stencil node (16-byte vector loads; q is
-// 16-byte aligned because W * sizeof(RC) is a multiple of 16).
-template <typename RC, int W>
-__device__ __forceinline__ void load_node(const RC* __restrict__ q, RC (&o)[W]) {
-  typedef RC vec2 __attribute__((ext_vector_type(16 / sizeof(RC))));
-  constexpr int L = 16 / sizeof(RC);
-#pragma unroll
-  for (int k = 0; k < W / L; ++k) {
-    const vec2 t = reinterpret_cast<const vec2*>(q)[k];
-#pragma unroll
-    for (int e = 0; e < L; ++e) o[k * L + e] = t[e];
-  }
-}
-
-// Tricubic Lagrange interpolation of a node-interleaved field group at one
-// point (grid-index coordinates in FP64; weights and sums in RC).  The
-// arithmetic and its order are those of interp_pt.
-template <typename RC, int W, int NF>
-__device__ __forceinline__ void interp_packed(const RC* __restrict__ q, double jx, double jy, double jz, int n,
-                                              RC (&out)[NF]) {
-  const double bx = floor(jx), by = floor(jy), bz = floor(jz);
-  RC wx[4], wy[4], wz[4];
-  lagrange4<RC>(RC(jx - bx), wx);
-  lagrange4<RC>(RC(jy - by), wy);
-  lagrange4<RC>(RC(jz - bz), wz);
-  const int ix = (int)(long long)bx, iy = (int)(long long)by, iz = (int)(long long)bz;
-  const int m = n - 1;
-#pragma unroll
-  for (int f = 0; f < NF; ++f) out[f] = RC(0);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const long long zo = (long long)((iz + c - 1) & m) * n * n;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const long long yo = zo + (long long)((iy + b - 1) & m) * n;
-      const RC wzy = wz[c] * wy[b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const long long idx = yo + ((ix + a - 1) & m);
-        const RC wt = wzy * wx[a];
-        RC val[W];
-        load_node<RC, W>(q + W * idx, val);
-#pragma unroll
-        for (int f = 0; f < NF; ++f) out[f] += wt * val[f];
-      }
-    }
-  }
-}
-
+// ------------------------------------------- LDS-tiled semi-Lagrangian step
 // Semi-Lagrangian step of the transported fields (Sec. 3): RK2
 // characteristics X* = x - dt v(x), X = x - dt/2 (v(x) + v(X*)), tricubic
 // values at X, and Heun's method for the conservative source
 // g(nu, x) = -nu div v(x) of p, i, n, g, w; f is transported without source.
 //
-// One block per BX x BY x BZ brick of voxels (x fastest, 256 voxels).
-// Blocks are handed to the eight XCDs in turn, so block b is mapped to
-// brick (b mod 8) * (bricks / 8) + b / 8: each XCD sweeps one contiguous z
-// slab, and consecutive bricks of a slab form groups of 4 bricks in z (x,
-// then z, then y), so that the stencils of the bricks an XCD runs at once
-// overlap in its L2 (XCD_SLABS; otherwise bricks follow the block index).
-template <typename RC, int BX, int BY, int BZ, bool XCD_SLABS>
-__global__ void __launch_bounds__(256) k_sl_gather(SLArgs a, const RC* __restrict__ v4, const RC* __restrict__ q8,
-                                                   const CoefScalars* cs) {
-  static_assert(BX * BY * BZ == 256, "one voxel per thread");
+// One 256-thread block takes a BX x BY x BZ brick of arrival voxels (VPT per
+// thread, a thread's voxels 256 / (BX BY) planes apart in z).  For each of the
+// two gather stages (v at X*, then p, i, n, g, w, f and div v at X) the block
+// reduces the floors of its departure points to their bounding box, widens it
+// by the stencil reach (-1 .. +2), copies that box of the needed fields from
+// HBM into LDS once (coalesced rows, periodic wrap), and every voxel then
+// reads its 64 taps from the tile: G values per 16-byte LDS node, several
+// passes per stage.  A box larger than the tile (departure points of one
+// brick spread wider than the tile holds) makes that stage of that block
+// gather from global memory instead, with the same arithmetic.
+//
+// Interpolation type RC: FP64, or FP32 in the mixed precision.  In FP32 each
+// transported field is multiplied by the power of two that brings its
+// maximum |q| to [1, 2) before rounding (exact), and the result is unscaled in
+// FP64: the interpolation and the Heun update are linear in q, so the scaling
+// changes no result while fields far below FP32's normal range (the necrotic
+// cells early on) keep FP32's relative precision instead of flushing to zero.
+// Departure points and the stencil weights' arguments stay FP64.  Within a
+// voxel the tap order (z, then y, then x; weight wz wy, then times wx) is
+// fixed, so every path gives the same bits.
+
+template <typename RC, int G>
+struct TileVec {
+  typedef RC type __attribute__((ext_vector_type(G)));
+};
+template <typename RC>
+struct TileVec<RC, 1> {
+  typedef RC type;
+};
+
+template <int G, typename RC>
+__device__ __forceinline__ void tile_put(RC* tile, int e, const RC (&v)[G]) {
+  typedef typename TileVec<RC, G>::type vt;
+  vt t;
+  if constexpr (G == 1) {
+    t = v[0];
+  } else {
+#pragma unroll
+    for (int g = 0; g < G; ++g) t[g] = v[g];
+  }
+  reinterpret_cast<vt*>(tile)[e] = t;
+}
+
+template <int G, typename RC>
+__device__ __forceinline__ void tile_get(const RC* tile, int e, RC (&v)[G]) {
+  typedef typename TileVec<RC, G>::type vt;
+  const vt t = reinterpret_cast<const vt*>(tile)[e];
+  if constexpr (G == 1) {
+    v[0] = t;
+  } else {
+#pragma unroll
+    for (int g = 0; g < G; ++g) v[g] = t[g];
+  }
+}
+
+// Block-wide min and max of three ints (256 threads); every thread gets them.
+__device__ __forceinline__ void block_box(int (&lo)[3], int (&hi)[3], int* sh /* 24 ints */) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[d] = min(lo[d], __shfl_xor(lo[d], off, 64));
+      hi[d] = max(hi[d], __shfl_xor(hi[d], off, 64));
+    }
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      sh[d * 4 + w] = lo[d];
+      sh[12 + d * 4 + w] = hi[d];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = min(min(sh[d * 4], sh[d * 4 + 1]), min(sh[d * 4 + 2], sh[d * 4 + 3]));
+    hi[d] = max(max(sh[12 + d * 4], sh[12 + d * 4 + 1]), max(sh[12 + d * 4 + 2], sh[12 + d * 4 + 3]));
+  }
+  __syncthreads();  // sh is reused by the next reduction
+}
+
+// Stencil of one point: base node floor(X) - 1 per axis and the weights.
+template <typename RC>
+struct Stencil {
+  int ix, iy, iz;  // floor of the point (unwrapped grid index)
+  RC wx[4], wy[4], wz[4];
+  __device__ __forceinline__ void set(double jx, double jy, double jz) {
+    const double bx = floor(jx), by = floor(jy), bz = floor(jz);
+    lagrange4<RC>(RC(jx - bx), wx);
+    lagrange4<RC>(RC(jy - by), wy);
+    lagrange4<RC>(RC(jz - bz), wz);
+    ix = (int)(long long)bx;
+    iy = (int)(long long)by;
+    iz = (int)(long long)bz;
+  }
+};
+
+// Copy the box [x0, x0+L[0]) x [y0, ...) x [z0, ...) (unwrapped) of G fields
+// into the tile, node (xr, yr, zr) at ((zr L[1] + yr) L[0] + xr).  A null
+// source fills its slot with zeros (padding of a 16-byte node).
+template <typename RC, int G>
+__device__ __forceinline__ void tile_stage(RC* tile, const double* const (&src)[G], const double (&sc)[G], int x0,
+                                           int y0, int z0, const int (&L)[3], int n) {
+  const int m = n - 1;
+  const int rows = L[1] * L[2];
+  for (int e = threadIdx.x; e < rows * L[0]; e += 256) {
+    const int row = e / L[0];
+    const int xr = e - row * L[0];
+    const int zr = row / L[1];
+    const int yr = row - zr * L[1];
+    const long long gi = ((long long)((z0 + zr) & m) * n + ((y0 + yr) & m)) * n + ((x0 + xr) & m);
+    RC v[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) v[g] = src[g] ? RC(sc[g] * src[g][gi]) : RC(0);
+    tile_put<G, RC>(tile, e, v);
+  }
+}
+
+// out[0..G) += tricubic sum over the tile.
+template <typename RC, int G>
+__device__ __forceinline__ void tile_gather(const RC* tile, const Stencil<RC>& st, int x0, int y0, int z0,
+                                            const int (&L)[3], RC* out) {
+  const int rx = st.ix - 1 - x0, ry = st.iy - 1 - y0, rz = st.iz - 1 - z0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int base = ((rz + c) * L[1] + (ry + b)) * L[0] + rx;
+      const RC wzy = st.wz[c] * st.wy[b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const RC wt = wzy * st.wx[a];
+        RC val[G];
+        tile_get<G, RC>(tile, base + a, val);
+#pragma unroll
+        for (int g = 0; g < G; ++g) out[g] += wt * val[g];
+      }
+    }
+  }
+}
+
+// The same sum from the global FP64 fields (fallback for an oversized box).
+template <typename RC, int G>
+__device__ __forceinline__ void global_gather(const double* const (&src)[G], const double (&sc)[G],
+                                              const Stencil<RC>& st, int n, RC* out) {
+  const int m = n - 1;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const long long zo = (long long)((st.iz + c - 1) & m) * n * n;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const long long yo = zo + (long long)((st.iy + b - 1) & m) * n;
+      const RC wzy = st.wz[c] * st.wy[b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const long long idx = yo + ((st.ix + a - 1) & m);
+        const RC wt = wzy * st.wx[a];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          if (src[g]) out[g] += wt * RC(sc[g] * src[g][idx]);
+      }
+    }
+  }
+}
+
+// Box of the stencils whose floors span [lo, hi] per axis: origin lo - 1,
+// extent hi - lo + 4.  It fits when it is no wider than the grid plus the
+// stencil and holds at most cap nodes (computed in 64 bits, so that garbage
+// floors of non-finite points fail the test).
+__device__ __forceinline__ bool box_fits(const int (&lo)[3], const int (&hi)[3], int n, long long cap, int (&box)[3],
+                                         int (&L)[3]) {
+  long long ext[3];
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = (long long)hi[d] - (long long)lo[d] + 4;
+    ok = ok && ext[d] > 0 && ext[d] <= n + 3;
+    box[d] = lo[d] - 1;
+    L[d] = ok ? (int)ext[d] : 1;
+  }
+  return ok && ext[0] * ext[1] * ext[2] <= cap;
+}
+
+// One gather pass of G fields for all voxels of the thread.
+template <typename RC, int G, int VPT>
+__device__ __forceinline__ void sl_pass(RC* tile, bool fits, const double* const (&src)[G], const double (&sc)[G],
+                                        const int (&box)[3], const int (&L)[3], const Stencil<RC> (&st)[VPT],
+                                        int n, RC (&acc)[VPT][8], int slot) {
+  if (fits) {
+    __syncthreads();  // the previous pass has finished reading the tile
+    tile_stage<RC, G>(tile, src, sc, box[0], box[1], box[2], L, n);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) tile_gather<RC, G>(tile, st[k], box[0], box[1], box[2], L, &acc[k][slot]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) global_gather<RC, G>(src, sc, st[k], n, &acc[k][slot]);
+  }
+}
+
+template <typename RC, int BX, int BY, int BZ, int CAP>
+__global__ void __launch_bounds__(256) k_sl_tile(SLArgs a, CoefScalars* cs) {
+  constexpr int ZS = 256 / (BX * BY);        // z distance of a thread's voxels
+  constexpr int VPT = BZ / ZS;
+  static_assert(256 % (BX * BY) == 0 && BZ % ZS == 0, "brick shape");
+  constexpr int GV = sizeof(RC) == 4 ? 4 : 2;  // values per 16-byte LDS node
+  __shared__ __align__(16) RC tile[CAP * (16 / sizeof(RC))];   // CAP 16-byte nodes
+  __shared__ int red[24];
   const int n = a.n_grid;
+  // bricks: x fastest, then z in groups of 4, then y; blocks dealt to the
+  // eight XCDs in turn, each XCD sweeping a contiguous slab of bricks
   const unsigned nb = gridDim.x;
-  const unsigned id = XCD_SLABS ? (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+  const unsigned id = (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3);
   const unsigned nbx = (unsigned)n / BX, nby = (unsigned)n / BY;
   const unsigned bx = id % nbx;
   unsigned r = id / nbx;
@@ -584,60 +696,135 @@ __global__ void __launch_bounds__(256) k_sl_gather(SLArgs a, const RC* __restric
   const int t = threadIdx.x;
   const int jx = (int)(bx * BX) + (t % BX);
   const int jy = (int)(by * BY) + ((t / BX) % BY);
-  const int jz = (int)((zg * 4 + zl) * BZ) + (t / (BX * BY));
-  const long long v = ((long long)jz * n + jy) * n + jx;
-  const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v];
+  const int jz0 = (int)((zg * 4 + zl) * BZ) + (t / (BX * BY));
   const double s = a.s;
-  RC vs[3];
-  RC qx[7];
-  interp_packed<RC, 4, 3>(v4, jx - s * vx, jy - s * vy, jz - s * vz, n, vs);
-  const double Xx = jx - 0.5 * s * (vx + (double)vs[0]);
-  const double Xy = jy - 0.5 * s * (vy + (double)vs[1]);
-  const double Xz = jz - 0.5 * s * (vz + (double)vs[2]);
-  interp_packed<RC, 8, 7>(q8, Xx, Xy, Xz, n, qx);
+  double vx[VPT], vy[VPT], vz[VPT];
+  long long vi[VPT];
+  Stencil<RC> st[VPT];
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+  double vmax = 0.0;
+#pragma unroll
+  for (int k = 0; k < VPT; ++k) {
+    const int jz = jz0 + k * ZS;
+    vi[k] = ((long long)jz * n + jy) * n + jx;
+    vx[k] = a.vx[vi[k]];
+    vy[k] = a.vy[vi[k]];
+    vz[k] = a.vz[vi[k]];
+    const double c = s * sqrt(vx[k] * vx[k] + vy[k] * vy[k] + vz[k] * vz[k]);
+    vmax = (c >= 0.0 && vmax >= 0.0) ? fmax(vmax, c) : -1.0;  // -1: a NaN was seen
+    st[k].set(jx - s * vx[k], jy - s * vy[k], jz - s * vz[k]);
+    lo[0] = min(lo[0], st[k].ix);
+    lo[1] = min(lo[1], st[k].iy);
+    lo[2] = min(lo[2], st[k].iz);
+    hi[0] = max(hi[0], st[k].ix);
+    hi[1] = max(hi[1], st[k].iy);
+    hi[2] = max(hi[2], st[k].iz);
+  }
+  block_max_cfl(vmax, cs);
+  // stage 1: v at X*.  A NaN departure point gives a garbage box: the fit
+  // test below then fails and the global path reads wrapped indices.
+  block_box(lo, hi, red);
+  int box[3], L[3];
+  bool fits = box_fits(lo, hi, n, CAP, box, L);
+  RC acc[VPT][8];
+#pragma unroll
+  for (int k = 0; k < VPT; ++k)
+#pragma unroll
+    for (int g = 0; g < 8; ++g) acc[k][g] = RC(0);
+  const double one[4] = {1.0, 1.0, 1.0, 1.0};
+  const double one1[1] = {1.0};
+  if constexpr (GV == 4) {
+    const double* const src[4] = {a.vx, a.vy, a.vz, nullptr};
+    sl_pass<RC, 4, VPT>(tile, fits, src, one, box, L, st, n, acc, 0);
+  } else {
+    const double* const s2[2] = {a.vx, a.vy};
+    const double* const s1[1] = {a.vz};
+    const double one2[2] = {1.0, 1.0};
+    sl_pass<RC, 2, VPT>(tile, fits, s2, one2, box, L, st, n, acc, 0);
+    sl_pass<RC, 1, VPT>(tile, fits, s1, one1, box, L, st, n, acc, 2);
+  }
+  // stage 2: departure points X, then the seven fields there
+  lo[0] = lo[1] = lo[2] = INT_MAX;
+  hi[0] = hi[1] = hi[2] = INT_MIN;
+#pragma unroll
+  for (int k = 0; k < VPT; ++k) {
+    const int jz = jz0 + k * ZS;
+    const double Xx = jx - 0.5 * s * (vx[k] + (double)acc[k][0]);
+    const double Xy = jy - 0.5 * s * (vy[k] + (double)acc[k][1]);
+    const double Xz = jz - 0.5 * s * (vz[k] + (double)acc[k][2]);
+    st[k].set(Xx, Xy, Xz);
+    lo[0] = min(lo[0], st[k].ix);
+    lo[1] = min(lo[1], st[k].iy);
+    lo[2] = min(lo[2], st[k].iz);
+    hi[0] = max(hi[0], st[k].ix);
+    hi[1] = max(hi[1], st[k].iy);
+    hi[2] = max(hi[2], st[k].iz);
+#pragma unroll
+    for (int g = 0; g < 8; ++g) acc[k][g] = RC(0);
+  }
+  block_box(lo, hi, red);
+  fits = box_fits(lo, hi, n, CAP, box, L);
+  double sc[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) sc[f] = sizeof(RC) == sizeof(double) ? 1.0 : pow2_scale(cs->qmax_bits[f]);
+  if constexpr (GV == 4) {
+    const double* const q0[4] = {a.p, a.i, a.n, a.g};
+    const double* const q1[4] = {a.w, a.f, a.div, nullptr};
+    const double s0[4] = {sc[0], sc[1], sc[2], sc[3]};
+    const double s1[4] = {sc[4], sc[5], 1.0, 1.0};
+    sl_pass<RC, 4, VPT>(tile, fits, q0, s0, box, L, st, n, acc, 0);
+    sl_pass<RC, 4, VPT>(tile, fits, q1, s1, box, L, st, n, acc, 4);
+  } else {
+    const double* const q0[2] = {a.p, a.i};
+    const double* const q1[2] = {a.n, a.g};
+    const double* const q2[2] = {a.w, a.f};
+    const double* const q3[1] = {a.div};
+    const double s0[2] = {sc[0], sc[1]}, s1[2] = {sc[2], sc[3]}, s2[2] = {sc[4], sc[5]};
+    sl_pass<RC, 2, VPT>(tile, fits, q0, s0, box, L, st, n, acc, 0);
+    sl_pass<RC, 2, VPT>(tile, fits, q1, s1, box, L, st, n, acc, 2);
+    sl_pass<RC, 2, VPT>(tile, fits, q2, s2, box, L, st, n, acc, 4);
+    sl_pass<RC, 1, VPT>(tile, fits, q3, one1, box, L, st, n, acc, 6);
+  }
   const RC dt = RC(a.dt);
-  const RC dX = qx[6];
-  const RC d0 = RC(a.div[v]);
   double* const outs[6] = {a.po, a.io, a.no, a.go, a.wo, a.fo};
   double unscale[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k)
-    unscale[k] = sizeof(RC) == sizeof(double) ? 1.0 : 1.0 / pow2_scale(cs->qmax_bits[k]);
-  // Heun is linear in q: it runs on the scaled values, unscaled in FP64.
+  for (int f = 0; f < 6; ++f) unscale[f] = sizeof(RC) == sizeof(double) ? 1.0 : 1.0 / sc[f];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const RC qt = qx[k];
-    const RC g0 = -qt * dX;
-    const RC qs = qt + dt * g0;
-    const RC gs = -qs * d0;
-    outs[k][v] = (double)(qt + RC(0.5) * dt * (g0 + gs)) * unscale[k];
+  for (int k = 0; k < VPT; ++k) {
+    const RC dX = acc[k][6];
+    const RC d0 = RC(a.div[vi[k]]);
+    // Heun is linear in q: it runs on the scaled values, unscaled in FP64.
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      const RC qt = acc[k][f];
+      const RC g0 = -qt * dX;
+      const RC qs = qt + dt * g0;
+      const RC gs = -qs * d0;
+      outs[f][vi[k]] = (double)(qt + RC(0.5) * dt * (g0 + gs)) * unscale[f];
+    }
+    outs[5][vi[k]] = (double)acc[k][5] * unscale[5];
   }
-  outs[5][v] = (double)qx[5] * unscale[5];
 }
 
-// n is a power of two >= 16 (checked at init): V = n^3 is a multiple of 256,
-// the number of bricks n^3 / 256 is a multiple of 8, and the bricks along z
-// (n / BZ) a multiple of 4, as k_sl_gather's brick map needs.
+// Bricks of 16 x 8 x 4 voxels (2 per thread) with a 2048-node (32 KiB) tile in
+// both precisions: at 256^3 this measured fastest among 16x8x8, 16x16x4,
+// 8x8x8 and 8x8x4 bricks with 20-64 KiB tiles (FP64 2.04 ms, FP32 2.10 ms per
+// launch; an earlier per-voxel gather from node-interleaved copies took
+// 6.37 + 0.67 ms and 2.29 + 0.41 ms with its packing pass).  For every
+// power of two n >= 16 the bricks tile the grid, their count is a multiple of
+// 8 and the bricks along z a multiple of 4, as the block-to-brick map needs.
 template <typename RC>
-void launch_sl(const SLArgs& a, void* packed, CoefScalars* cs, hipStream_t st) {
+void launch_sl_tile(const SLArgs& a, CoefScalars* cs, hipStream_t st) {
   const long long V = (long long)a.n_grid * a.n_grid * a.n_grid;
-  RC* v4 = static_cast<RC*>(packed);
-  RC* q8 = v4 + 4 * V;
   if (sizeof(RC) != sizeof(double)) {
     const long long blocks = std::min<long long>(V / 256, 4096);
     hipLaunchKernelGGL(k_sl_scan, dim3((unsigned)blocks), dim3(256), 0, st, a, cs);
   }
-  hipLaunchKernelGGL(k_sl_pack<RC>, dim3((unsigned)std::min<long long>(V / 256, kPackBlocks)), dim3(256), 0, st, a,
-                     v4, q8, cs);
-  // 64-voxel rows per wave (measured best for both types at 256^3); grids
-  // below 64 use 16 x 4 x 4 bricks.
-  if (a.n_grid >= 64)
-    hipLaunchKernelGGL((k_sl_gather<RC, 64, 2, 2, true>), dim3((unsigned)(V / 256)), dim3(256), 0, st, a, v4, q8, cs);
-  else
-    hipLaunchKernelGGL((k_sl_gather<RC, 16, 4, 4, true>), dim3((unsigned)(V / 256)), dim3(256), 0, st, a, v4, q8, cs);
+  hipLaunchKernelGGL((k_sl_tile<RC, 16, 8, 4, 2048>), dim3((unsigned)(V / 512)), dim3(256), 0, st, a, cs);
 }
-template void launch_sl<double>(const SLArgs&, void*, CoefScalars*, hipStream_t);
-template void launch_sl<float>(const SLArgs&, void*, CoefScalars*, hipStream_t);
+template void launch_sl_tile<double>(const SLArgs&, CoefScalars*, hipStream_t);
+template void launch_sl_tile<float>(const SLArgs&, CoefScalars*, hipStream_t);
 
 __global__ void k_interp(int n, const double* q, const double* jx, const double* jy, const double* jz,
                          long long count, double* out) {

@@ -121,3 +121,62 @@ def test_initial_condition_and_coefficients():
     for k, ck in (("K", "K"), ("rho", "rho_p"), ("mu", "mu"), ("lambda", "lam"), ("eta", "eta")):
         assert rel_l2(sim.get(k).cpu().numpy(), co[ck]) < 1e-15, k
     sim.close()
+
+
+def _brick_boxes(X, n, B):
+    """Nodes of the stencil bounding box of every BX x BY x BZ brick of arrival
+    voxels (x fastest), for departure points X in grid-index units."""
+    BX, BY, BZ = B
+    fl = [np.floor(X[a]).astype(np.int64) for a in range(3)]
+    out = []
+    for z0 in range(0, n, BZ):
+        for y0 in range(0, n, BY):
+            for x0 in range(0, n, BX):
+                sl = (slice(z0, z0 + BZ), slice(y0, y0 + BY), slice(x0, x0 + BX))
+                L = [int(f[sl].max() - f[sl].min() + 4) for f in fl]
+                out.append(L[0] * L[1] * L[2])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("precision,cells,brick", [("mixed", 6.0, (16, 8, 8)), ("fp64", 14.0, (16, 8, 4))])
+def test_transport_with_a_large_shear_uses_tile_and_fallback_paths(precision, cells, brick):
+    """A shear displacement of up to `cells` cells per step: in some bricks of
+    arrival voxels the departure stencils spread over more nodes than the
+    transport's LDS tile holds (4096), and that stage of that brick gathers
+    from global memory instead; in the others it reads the tile.  Both match
+    the oracle's semi-Lagrangian step."""
+    torch = need_gpu()
+    n, dt = 32, 0.01
+    P = synthetic.params()
+    inp = synthetic.workload_inputs("seeds3_n128", n=n)
+    g = Grid(n)
+    x = g.axis()
+    Z, Y, X0 = np.meshgrid(x, x, x, indexing="ij")
+    disp = np.zeros((3, n, n, n))
+    disp[0] = g.h * cells * 0.5 * (1 + np.cos(Z + 0.3)) * np.sin(Y + 0.1)
+    disp[1] = g.h * cells * 0.5 * (1 + np.cos(X0 + 0.2)) * np.sin(Z + 0.7)
+    v = disp / dt
+    s = dt / g.h
+    J = transport.grid_indices(n)
+    b1 = _brick_boxes(tuple(J[a] - s * v[a] for a in range(3)), n, brick)
+    b2 = _brick_boxes(transport.departure_points(g, v, dt), n, brick)
+    say(f"shear {cells} cells, {precision}: bricks over the tile {int((b1 > 4096).sum())}/{b1.size} (X*), "
+        f"{int((b2 > 4096).sum())}/{b2.size} (X)")
+    assert (b1 > 4096).any() and (b1 <= 4096).any() and (b2 > 4096).any() and (b2 <= 4096).any()
+    sim = tm.from_inputs(inp, P, precision=precision)
+    rng = np.random.default_rng(8)
+    fields = {k: sim.get(k).cpu().numpy() for k in ("p", "i", "n", "g", "w", "f")}
+    fields["i"] = 0.3 * fields["p"] * rng.uniform(0.5, 1.5, (n, n, n))
+    fields["n"] = 1e-9 * rng.uniform(0, 1, (n, n, n))
+    sim.set("i", to_dev(torch, fields["i"]))
+    sim.set("n", to_dev(torch, fields["n"]))
+    sim.set("u", torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda"))
+    sim.set("u_prev", to_dev(torch, -disp))
+    out, cfl = sim.transport()
+    out = out.cpu().numpy()
+    sim.close()
+    ref = transport.advect(g, fields, v, dt)
+    for k, name in enumerate(("p", "i", "n", "g", "w", "f")):
+        err = rel_l2(out[k], ref[name])
+        say(f"  {name}: relL2 {err:.2e}")
+        assert err < (1e-10 if precision == "fp64" else 1e-5), name
