@@ -358,6 +358,14 @@ int tumor_kernel_timer(tumor_ctx* ctx, int32_t kernel_class, int32_t enable);
 int tumor_kernel_timer_read(tumor_ctx* ctx, int32_t kernel_class, int64_t* launches, double* ms,
                             double* bytes);
 
+/* Measurement hook: copy `bytes` (a multiple of 16, below 2^42) from src to
+ * dst (device pointers, 16-byte aligned, not overlapping) with a streaming
+ * kernel of one 16-byte load and store per thread, queued on hip_stream (NULL =
+ * the null stream); returns without waiting.  Its rate (2 bytes moved per byte
+ * copied) is the achievable HBM bandwidth that the other kernels' rates are
+ * set against.  TUMOR_EINVAL for a bad argument, before any device work. */
+int tumor_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
+
 void tumor_destroy(tumor_ctx* ctx);
 const char* tumor_last_error(void);
 int tumor_abi_version(void);

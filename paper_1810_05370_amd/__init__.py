@@ -137,6 +137,7 @@ def load_library(path: Optional[str] = None):
         "tumor_kernel_timer_read": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                                    ctypes.POINTER(ctypes.c_double),
                                                    ctypes.POINTER(ctypes.c_double)]),
+        "tumor_stream_copy": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
         "tumor_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
@@ -396,6 +397,17 @@ class Tumor:
             return
         arr = (ctypes.c_int32 * 4)(*[int(v) for v in iters])
         _check(self.lib.tumor_force_iterations(self.ctx, ctypes.cast(arr, ctypes.c_void_p)))
+
+
+def stream_copy(src, dst, stream=None):
+    """Copy the bytes of device tensor src into dst with the library's streaming
+    copy kernel (measurement hook; queued on `stream`, torch's current if None)."""
+    import torch
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nb or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("dst must be contiguous and hold src")
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    _check(load_library().tumor_stream_copy(_ptr(src), _ptr(dst), nb, ctypes.c_void_p(st.cuda_stream)))
 
 
 def from_inputs(inputs: dict, params: dict, device="cuda", **kw) -> Tumor:

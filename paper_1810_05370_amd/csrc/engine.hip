@@ -2082,6 +2082,20 @@ int tumor_kernel_timer_read(tumor_ctx* ctx, int32_t kernel_class, int64_t* launc
   });
 }
 
+int tumor_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream) {
+  if (!src || !dst) return einval("src/dst is NULL");
+  if ((bytes & 15u) != 0) return einval("bytes must be a multiple of 16");
+  if ((reinterpret_cast<uintptr_t>(src) & 15u) || (reinterpret_cast<uintptr_t>(dst) & 15u))
+    return einval("src and dst must be 16-byte aligned");
+  if (bytes >= (size_t(1) << 42)) return einval("bytes out of range");
+  return guarded([&]() -> int {
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    tumor::launch_stream_copy(src, dst, (long long)bytes, st);
+    HIPCHECK(hipGetLastError());
+    return TUMOR_OK;
+  });
+}
+
 int tumor_state_bytes(const tumor_config* cfg, size_t* bytes) {
   if (!bytes) return einval("bytes is NULL");
   if (check_cfg(cfg) != TUMOR_OK) return einval("invalid tumor_config");

@@ -84,6 +84,8 @@ void launch_react(const ReactArgs& a, hipStream_t st);
 void launch_ic(int n, const double* ic, int n_ic, double* p0, hipStream_t st);
 // p[0 .. count) = value
 void launch_fill(double* p, double value, long long count, hipStream_t st);
+// dst[0 .. bytes) = src[0 .. bytes); bytes a multiple of 16, both 16-byte aligned
+void launch_stream_copy(const void* src, void* dst, long long bytes, hipStream_t st);
 
 // Semi-Lagrangian step (Sec. 3).  v: velocity components and divergence
 // (physical).  RC: arithmetic type of the interpolation weights and sums.

@@ -165,3 +165,10 @@ def test_static_init_rejects_oversize_configurations_before_the_device(lib):
     assert lib.tumor_init_static(None, ctypes.byref(cfg), ctypes.byref(prm), fake, fake, fake, 0,
                                  None, None, None, None) == tm.EINVAL
     assert not ctx.value
+
+
+def test_stream_copy_validates_before_the_device(lib):
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.tumor_stream_copy(None, fake, 16, None) == tm.EINVAL
+    assert lib.tumor_stream_copy(fake, fake, 24, None) == tm.EINVAL             # not a multiple of 16
+    assert lib.tumor_stream_copy(ctypes.c_void_p(0x1008), fake, 32, None) == tm.EINVAL   # misaligned

@@ -180,3 +180,13 @@ def test_transport_with_a_large_shear_uses_tile_and_fallback_paths(precision, ce
         err = rel_l2(out[k], ref[name])
         say(f"  {name}: relL2 {err:.2e}")
         assert err < (1e-10 if precision == "fp64" else 1e-5), name
+
+
+def test_stream_copy_is_exact_including_a_partial_last_block():
+    torch = need_gpu()
+    for nbytes in (16, 4096 + 16, (1 << 22) + 48):
+        src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros_like(src)
+        tm.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst), nbytes
