@@ -452,6 +452,8 @@ def main():
     ap.add_argument("--no-strang", action="store_true", help="skip the symmetric (Strang) form of the step")
     ap.add_argument("--no-masked", action="store_true",
                     help="skip the fictitious-domain form (brain mask and background material)")
+    ap.add_argument("--no-lockstep", action="store_true",
+                    help="skip the step-by-step mixed-vs-FP64 and perturbation comparisons")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel that calibrates "
                          "the HBM byte counters of a rocprofv3 --pmc run)")
@@ -514,18 +516,19 @@ def main():
     # achievable HBM bandwidth of a plain device copy, the practical ceiling
     extra["copy_ceiling"] = copy_ceiling(torch, tm)
     log(f"copy ceiling: {extra['copy_ceiling']}")
-    compare = not args.no_fp64 and precision != "fp64"
+    compare = not args.no_fp64 and precision != "fp64" and not args.no_lockstep
     main_run = run_form(tm, torch, inp, P, precision, args.steps, args.warmup, window)
     ms_per_step = main_run["gpu_ms"] / args.steps
     value = args.steps / (main_run["gpu_ms"] / 1e3)
     fp64_run = None
-    if compare:
+    if not args.no_fp64 and precision != "fp64":
         torch.cuda.empty_cache()
         fp64_run = run_form(tm, torch, inp, P, "fp64", args.steps, args.warmup, window)
         v64 = args.steps / (fp64_run["gpu_ms"] / 1e3)
         extra["fp64_steps_per_s"] = round(v64, 4)
         extra["mixed_speedup_over_fp64"] = round(value / v64, 3)
         extra["fp64_roofline"] = roofline(fp64_run["dom"], fp64_run["dominant"], n)
+    if compare:
         # error of the mixed form against the FP64 form (itself held to the FP64
         # oracle at 1e-10 by the parity tests), after every step from t = 0 to the
         # window's end; beside it, how far two FP64 runs whose initial tumour
