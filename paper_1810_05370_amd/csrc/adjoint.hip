@@ -6,10 +6,12 @@
 //   k_s0_adj    : step coefficients K, rho -> w, g, f and d/d(k_w, k_g, k_f, rho)
 //   k_force_adj : pointwise part of the force b = zeta tanh(tau) G tau
 //   k_sl_adj    : semi-Lagrangian transport (interpolation transpose summed
-//                 per brick in LDS, then FP64 atomics; velocity sensitivity
-//                 through X and X*)
+//                 per brick in LDS, then added to global memory, both in 64-bit
+//                 fixed point so that the sums do not depend on the order of the
+//                 atomics; velocity sensitivity through X and X*)
 //   k_ic_adj    : projections onto the Gaussian initial-condition basis
 // Parameter sums use deterministic block partials totalled by a one-block kernel.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <stdexcept>
@@ -295,8 +297,26 @@ __device__ __forceinline__ void gather_grad(const Stencil& s, const double* cons
   }
 }
 
+// ---- fixed-point accumulation of the transposed interpolation
+// Every contribution w * val to a node is rounded to a 64-bit integer at a
+// per-field power-of-two scale and summed with integer atomics, which are
+// exact and commutative: the result does not depend on the order in which
+// threads and blocks add, so the transpose is bitwise reproducible.  The
+// scale puts an a-priori bound B of |w * val| (|w| <= 1 for the cubic Lagrange
+// weights on [0, 1)) at 2^47, so a node can take 2^16 contributions of the
+// bound without overflow; the rounding error of one contribution is at most
+// 2^-48 B.
+constexpr int kFixBits = 47;
+
+__device__ __forceinline__ long long to_fix(double v, double scale) { return __double2ll_rn(v * scale); }
+
+__device__ __forceinline__ void fix_add(double* acc, long long q) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(acc), static_cast<unsigned long long>(q));
+}
+
 template <int NF>
-__device__ __forceinline__ void scatter(const Stencil& s, double* const (&out)[NF], const double (&val)[NF], int n) {
+__device__ __forceinline__ void scatter(const Stencil& s, double* const (&out)[NF], const double (&val)[NF], int n,
+                                        const double (&scale)[NF]) {
   const int m = n - 1;
 #pragma unroll 1
   for (int c = 0; c < 4; ++c) {
@@ -310,7 +330,7 @@ __device__ __forceinline__ void scatter(const Stencil& s, double* const (&out)[N
         const long long idx = yo + ((s.ix + a - 1) & m);
         const double w = wzy * s.wx[a];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) unsafeAtomicAdd(out[f] + idx, w * val[f]);
+        for (int f = 0; f < NF; ++f) fix_add(out[f] + idx, to_fix(w * val[f], scale[f]));
       }
     }
   }
@@ -320,7 +340,7 @@ __device__ __forceinline__ void scatter(const Stencil& s, double* const (&out)[N
 // bricks tile the grid), bricks laid out x fastest, and consecutive block
 // indices spread over the 8 XCDs so that each XCD sweeps a contiguous slab.
 constexpr int kSlAdjBX = 16, kSlAdjBY = 4, kSlAdjBZ = 4;
-// LDS accumulation tile for the transposed interpolation (doubles).  A brick's
+// LDS accumulation tile for the transposed interpolation (64-bit fixed point).  A brick's
 // stencils span (16 + 3 + dx) x (4 + 3 + dy) x (4 + 3 + dz) nodes, dx, dy, dz
 // the spread of its departure cells; 2048 covers a spread of 2 cells per axis.
 constexpr int kSlAdjTile = 2048;
@@ -330,11 +350,12 @@ constexpr int kSlAdjTile = 2048;
 // are first summed in an LDS tile over the bounding box of the block's
 // stencils (LDS atomics), then each tile node is added to global memory with
 // one atomic, one field at a time.  A block whose box exceeds the tile adds
-// every contribution with a global atomic instead.  Called by all threads of
-// the block (block-uniform control flow).
+// every contribution with a global atomic instead.  All sums are 64-bit fixed
+// point (scale[f] per field), so both paths give the same integers.  Called by
+// all threads of the block (block-uniform control flow).
 template <int NF>
 __device__ void scatter_tiled(const Stencil& s, double* const (&out)[NF], const double (&val)[NF], int n,
-                              double* tile, int* box) {
+                              const double (&scale)[NF], long long* tile, int* box) {
   __syncthreads();  // every thread is done with box from a previous call
   if (threadIdx.x == 0) {
     box[0] = box[1] = box[2] = INT_MAX;
@@ -351,7 +372,7 @@ __device__ void scatter_tiled(const Stencil& s, double* const (&out)[NF], const 
   const int x0 = box[0], y0 = box[1], z0 = box[2];
   const long long DX = (long long)box[3] - x0 + 4, DY = (long long)box[4] - y0 + 4, DZ = (long long)box[5] - z0 + 4;
   if (DX * DY * DZ > kSlAdjTile) {
-    scatter<NF>(s, out, val, n);
+    scatter<NF>(s, out, val, n, scale);
     return;
   }
   const int m = n - 1;
@@ -359,7 +380,7 @@ __device__ void scatter_tiled(const Stencil& s, double* const (&out)[NF], const 
   // tile coordinates of the stencil's first node (x0 - 1, y0 - 1, z0 - 1 is the tile origin)
   const int bx = s.ix - x0, by = s.iy - y0, bz = s.iz - z0;
   for (int f = 0; f < NF; ++f) {
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x) tile[k] = 0.0;
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) tile[k] = 0;
     __syncthreads();
 #pragma unroll 1
     for (int c = 0; c < 4; ++c) {
@@ -368,26 +389,135 @@ __device__ void scatter_tiled(const Stencil& s, double* const (&out)[NF], const 
         const double wzy = s.wz[c] * s.wy[b];
         const int row = ((bz + c) * dyn + (by + b)) * dxn + bx;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) atomicAdd(&tile[row + a], wzy * s.wx[a] * val[f]);
+        for (int a = 0; a < 4; ++a)
+          atomicAdd(reinterpret_cast<unsigned long long*>(&tile[row + a]),
+                    static_cast<unsigned long long>(to_fix(wzy * s.wx[a] * val[f], scale[f])));
       }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-      const double t = tile[k];
-      if (t != 0.0) {
+      const long long t = tile[k];
+      if (t != 0) {
         const int tx = k % dxn, ty = (k / dxn) % dyn, tz = k / (dxn * dyn);
         const long long idx =
             ((long long)((z0 - 1 + tz) & m) * n + ((y0 - 1 + ty) & m)) * n + ((x0 - 1 + tx) & m);
-        unsafeAtomicAdd(out[f] + idx, t);
+        fix_add(out[f] + idx, t);
       }
     }
     __syncthreads();
   }
 }
 
-__global__ void __launch_bounds__(256) k_sl_adj(SLAdjArgs a) {
-  __shared__ double tile[kSlAdjTile];
+// Maxima that bound the transpose's contributions (one atomic max per block
+// and quantity on the bits of the non-negative doubles; NaN reads as +inf).
+__global__ void __launch_bounds__(256) k_sl_adj_bounds(SLAdjArgs a, GradScalars* gs) {
+  const long long V = (long long)a.n_grid * a.n_grid * a.n_grid;
+  double m[14];
+#pragma unroll
+  for (int k = 0; k < 14; ++k) m[k] = 0.0;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < V; v += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      m[k] = fmax(m[k], fabs(a.lam[k][v]));
+      m[6 + k] = fmax(m[6 + k], fabs(a.q[k][v]));
+    }
+    m[12] = fmax(m[12], fabs(a.div[v]));
+    m[13] = fmax(m[13], fmax(fabs(a.vx[v]), fmax(fabs(a.vy[v]), fabs(a.vz[v]))));
+  }
+  __shared__ double sh[14][4];
+#pragma unroll
+  for (int k = 0; k < 14; ++k) {
+    double t = m[k];
+    if (!(t >= 0.0)) t = INFINITY;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t = fmax(t, __shfl_xor(t, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 14) {
+    const int k = threadIdx.x;
+    const double t = fmax(fmax(sh[k][0], sh[k][1]), fmax(sh[k][2], sh[k][3]));
+    atomicMax(&gs->slb[k], (unsigned long long)__double_as_longlong(t));
+  }
+}
+
+// Fixed-point scales of the ten accumulated fields (out[0..5], divb, vb[0..2])
+// from a-priori bounds of their contributions (grid-index units).  With A_k,
+// Q_k the maxima of |lam_k| and |q_k|, D of |div v|, Vm of |v|, and the
+// Lebesgue constants of tricubic Lagrange interpolation, Lam = 1.25^3 for
+// values and Ld = 2.334 * 1.25^2 for one first derivative (the maxima over a
+// cell of sum |l_i| and sum |l_i'| in 1-D are 1.25 and 7/3):
+//   |cfac| <= Cf = 1 + dt/2 (Lam + 1) D + dt^2/2 Lam D^2,
+//   |bar_k| <= A_k Cf (k < 5), |bar_5| <= A_5,
+//   |cbar| <= Cb = Lam sum_{k<5} A_k Q_k, |bar_6| <= Cb (dt/2 + dt^2/2 D),
+//   |ddirect| <= Cb (dt/2 + dt^2/2 Lam D),
+//   |Jb| <= J = Ld (sum_{k<6} |bar_k| Q_k + |bar_6| D), |vsb| <= s J / 2,
+//   |vown| <= s J / 2 + 3 s (s J / 2) Ld Vm.
+// scale = 2^(kFixBits - e) with 2^e >= bound.  A non-finite bound leaves
+// finite = false (the finishing pass then writes NaN).
+__device__ __forceinline__ void sl_adj_scales(const GradScalars* gs, double dt, double s, double (&scale)[10],
+                                              bool& finite) {
+  double mx[14];
+#pragma unroll
+  for (int k = 0; k < 14; ++k) mx[k] = __longlong_as_double((long long)gs->slb[k]);
+  const double Lam = 1.953125, Ld = 3.6459, D = mx[12], Vm = mx[13];
+  const double Cf = 1.0 + 0.5 * dt * (Lam + 1.0) * D + 0.5 * dt * dt * Lam * D * D;
+  double bnd[10], barm[7];
+  double Cb = 0.0;
+  for (int k = 0; k < 5; ++k) {
+    barm[k] = mx[k] * Cf;
+    Cb += mx[k] * mx[6 + k];
+  }
+  Cb *= Lam;
+  barm[5] = mx[5];
+  barm[6] = Cb * (0.5 * dt + 0.5 * dt * dt * D);
+  const double dd = Cb * (0.5 * dt + 0.5 * dt * dt * Lam * D);
+  double J = barm[6] * D;
+  for (int k = 0; k < 6; ++k) J += barm[k] * mx[6 + k];
+  J *= Ld;
+  const double vsb = 0.5 * s * J;
+  for (int k = 0; k < 6; ++k) bnd[k] = barm[k];
+  bnd[6] = fmax(barm[6], dd);
+  const double vown = vsb + 3.0 * s * vsb * Ld * Vm;
+  for (int k = 7; k < 10; ++k) bnd[k] = fmax(vsb, vown);
+  finite = true;
+  for (int k = 0; k < 10; ++k) {
+    const double b = bnd[k];
+    if (!(b < INFINITY)) {
+      finite = false;
+      scale[k] = 1.0;
+    } else if (b > 0.0) {
+      const int e = max(ilogb(b) + 1, -900);  // 2^e > b
+      scale[k] = ldexp(1.0, kFixBits - e);
+    } else {
+      scale[k] = 1.0;  // every contribution is zero
+    }
+  }
+}
+
+// Fixed point back to FP64 in place (ten fields of V values).
+__global__ void __launch_bounds__(256) k_sl_adj_finish(SLAdjArgs a, const GradScalars* gs) {
+  double scale[10];
+  bool finite;
+  sl_adj_scales(gs, a.dt, a.s, scale, finite);
+  double* const f[10] = {a.out[0], a.out[1], a.out[2], a.out[3], a.out[4], a.out[5], a.divb,
+                         a.vb[0], a.vb[1], a.vb[2]};
+  const long long V = (long long)a.n_grid * a.n_grid * a.n_grid;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < V; v += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+      const long long q = __double_as_longlong(f[k][v]);
+      f[k][v] = finite ? (double)q / scale[k] : NAN;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sl_adj(SLAdjArgs a, const GradScalars* gs) {
+  __shared__ long long tile[kSlAdjTile];
   __shared__ int box[6];
+  double scale[10];
+  bool finite;
+  sl_adj_scales(gs, a.dt, a.s, scale, finite);
   const int n = a.n_grid;
   const int nbx = n / kSlAdjBX, nby = n / kSlAdjBY;
   const int nb = (int)gridDim.x;
@@ -431,8 +561,9 @@ __global__ void __launch_bounds__(256) k_sl_adj(SLAdjArgs a) {
     Jb[2] += bar[k] * qz[k];
   }
   double* const outs[7] = {a.out[0], a.out[1], a.out[2], a.out[3], a.out[4], a.out[5], a.divb};
-  scatter_tiled<7>(st, outs, bar, n, tile, box);
-  unsafeAtomicAdd(a.divb + v, ddirect);
+  const double sc7[7] = {scale[0], scale[1], scale[2], scale[3], scale[4], scale[5], scale[6]};
+  scatter_tiled<7>(st, outs, bar, n, sc7, tile, box);
+  fix_add(a.divb + v, to_fix(ddirect, scale[6]));
   // X = x - s/2 (v + v*), v* = I[v](X*), X* = x - s v
   double vsb[3], vown[3];
 #pragma unroll
@@ -450,9 +581,10 @@ __global__ void __launch_bounds__(256) k_sl_adj(SLAdjArgs a) {
 #pragma unroll
   for (int b = 0; b < 3; ++b) vown[b] += -s * Jsb[b];
   double* const vb[3] = {a.vb[0], a.vb[1], a.vb[2]};
-  scatter_tiled<3>(st_s, vb, vsb, n, tile, box);
+  const double sc3[3] = {scale[7], scale[8], scale[9]};
+  scatter_tiled<3>(st_s, vb, vsb, n, sc3, tile, box);
 #pragma unroll
-  for (int b = 0; b < 3; ++b) unsafeAtomicAdd(a.vb[b] + v, vown[b]);
+  for (int b = 0; b < 3; ++b) fix_add(a.vb[b] + v, to_fix(vown[b], scale[7 + b]));
 }
 
 // ------------------------------------------------------ initial condition
@@ -518,12 +650,17 @@ void launch_axpy(long long V, double coef, const double* x, double* out, hipStre
 void launch_xpay(long long V, const double* x, double coef, const double* y, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_xpay, dim3(pw_blocks(V)), dim3(256), 0, st, V, x, coef, y, out);
 }
-void launch_sl_adj(const SLAdjArgs& a, hipStream_t st) {
+void launch_sl_adj(const SLAdjArgs& a, GradScalars* gs, hipStream_t st) {
   const int n = a.n_grid;
   if (n < 16 || (n & (n - 1)) != 0) throw std::runtime_error("k_sl_adj: grid size must be a power of two >= 16");
+  const long long V = (long long)n * n * n;
+  const unsigned pw = (unsigned)std::min<long long>(V / 256, 2048);
+  hipLaunchKernelGGL(k_sl_adj_bounds, dim3(pw), dim3(256), 0, st, a, gs);
   // one 16 x 4 x 4 brick per block; n^3 / 256 is a multiple of 8 for n >= 16
-  const long long nb = (long long)n * n * n / (kSlAdjBX * kSlAdjBY * kSlAdjBZ);
-  hipLaunchKernelGGL(k_sl_adj, dim3((unsigned)nb), dim3(kSlAdjBX * kSlAdjBY * kSlAdjBZ), 0, st, a);
+  const long long nb = V / (kSlAdjBX * kSlAdjBY * kSlAdjBZ);
+  hipLaunchKernelGGL(k_sl_adj, dim3((unsigned)nb), dim3(kSlAdjBX * kSlAdjBY * kSlAdjBZ), 0, st, a,
+                     static_cast<const GradScalars*>(gs));
+  hipLaunchKernelGGL(k_sl_adj_finish, dim3(pw), dim3(256), 0, st, a, static_cast<const GradScalars*>(gs));
 }
 int ic_adj_blocks(int n) { return rblocks((long long)n * n * n); }
 void launch_ic_adj(int n, const double* ic, int n_ic, const double* lam_p, double* part, double* out,

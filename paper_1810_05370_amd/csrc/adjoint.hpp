@@ -12,6 +12,10 @@ namespace tumor {
 struct GradScalars {
   double g[8];
   int32_t pad[4];
+  // maxima (bits of non-negative doubles, combined by atomic max) that bound the
+  // transposed transport's contributions: |lam_k|, |q_k| (k = 0..5), |div v|,
+  // |v| (largest component)
+  unsigned long long slb[14];
 };
 
 struct ReactAdjArgs {
@@ -67,7 +71,10 @@ void launch_force_adj(long long V, double zeta, const double* p, const double* n
 void launch_acc_prod(long long V, double coef, const double* x, const double* y, double* out, hipStream_t st);
 void launch_axpy(long long V, double coef, const double* x, double* out, hipStream_t st);
 void launch_xpay(long long V, const double* x, double coef, const double* y, double* out, hipStream_t st);
-void launch_sl_adj(const SLAdjArgs& a, hipStream_t st);
+// Transposed transport: bounds pass, scatter into 64-bit fixed-point
+// accumulators (out, divb, vb, zeroed by the caller), conversion back to FP64.
+// gs->slb must be zero on entry.
+void launch_sl_adj(const SLAdjArgs& a, GradScalars* gs, hipStream_t st);
 int ic_adj_blocks(int n);
 void launch_ic_adj(int n, const double* ic, int n_ic, const double* lam_p, double* part, double* out,
                    hipStream_t st);

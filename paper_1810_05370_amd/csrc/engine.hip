@@ -1386,7 +1386,7 @@ void adjoint_core(Ctx& c, const double* x0, double* adj, int m, double* grad) {
     sa.n_grid = c.n;
     sa.dt = c.cfg.dt;
     sa.s = c.cfg.dt / (2.0 * M_PI / c.n);
-    tumor::launch_sl_adj(sa, c.st);
+    tumor::launch_sl_adj(sa, c.gs, c.st);
     fwd3<double>(c, c.DB, nullptr, PB.r);
     for (int a = 0; a < 3; ++a) {
       inv3<double>(c, PB.r, c.T[0], iV, a);

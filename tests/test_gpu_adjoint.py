@@ -246,3 +246,30 @@ def test_autograd_gradient_lands_on_the_device_and_dtype_of_theta():
     assert rel_l2(grads[("cuda", torch.float64)], ref) < 1e-12
     # float32 theta rounds the parameters themselves, so the bar is float32's
     assert rel_l2(grads[("cuda", torch.float32)], ref) < 1e-5
+
+
+@pytest.mark.parametrize("name,n,steps", [("seed1_n32", 32, 3), ("lattice_n128", 128, 3)])
+def test_adjoint_is_bitwise_reproducible(name, n, steps):
+    """Two identical reverse sweeps give the same bits: every sum of the
+    transposed transport is a 64-bit fixed-point integer sum (order-free), and
+    every other reduction uses fixed-order block partials."""
+    torch = need_gpu()
+    P = synthetic.params(delta_p=60.0)
+    inp = synthetic.workload_inputs(name, n=n)
+    say(f"bitwise reproducibility {name} n={n} steps={steps}")
+    outs = []
+    for rep in range(2):
+        sim = tm.from_inputs(inp, P, flags=tm.F_DEFAULT | tm.F_ADJOINT)
+        sim.record(steps, 1)
+        sim.step(steps)
+        tau = sim.get("p") + sim.get("i") + sim.get("n")
+        lam = torch.zeros((14, n, n, n), dtype=torch.float64, device="cuda")
+        for k in range(3):
+            lam[k].copy_(1e-3 * tau)
+        grad = np.zeros(5 + len(inp["weights"]))
+        for _ in range(steps):
+            sim.adjoint_step(lam, grad)
+        outs.append((lam.clone(), grad.copy()))
+        sim.close()
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
