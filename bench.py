@@ -197,7 +197,7 @@ def run_adjoint(tm, torch, inp, P, precision, steps, warmup, ckpt):
     del sim, lam
     torch.cuda.empty_cache()
     return dict(fwd_s=t1 - t0, adj_s=t3 - t2, steps_per_s=steps / ((t1 - t0) + (t3 - t2)), peak_gib=peak,
-                device_used_gib=(free0 - free1) / 2 ** 30, grad_head=[float(v) for v in grad[:5]])
+                device_used_gib=(free0 - free1) / 2 ** 30, grad_head=[float(v) for v in grad[:5]], grad=grad)
 
 
 def copy_ceiling(torch, tm, mib=1024, reps=10):
@@ -579,8 +579,10 @@ def main():
 
     if not args.no_adjoint:
         ainp = synthetic.workload_inputs(args.adjoint_workload)
+        grads = {}
         for prec in (("mixed", "fp64") if not args.no_fp64 else ("mixed",)):
             r = run_adjoint(tm, torch, ainp, P, prec, args.adjoint_steps, 0, args.ckpt_every)
+            grads[prec] = r["grad"]
             key = "fwd_adjoint_steps_per_s" if prec == "mixed" else "fwd_adjoint_fp64_steps_per_s"
             extra[key] = round(r["steps_per_s"], 4)
             extra[key.replace("steps_per_s", "detail")] = dict(
@@ -588,6 +590,11 @@ def main():
                 recorded_steps=args.adjoint_steps, ckpt_every=args.ckpt_every, forward_s=round(r["fwd_s"], 3),
                 reverse_s=round(r["adj_s"], 3), peak_allocated_gib=round(r["peak_gib"], 2),
                 device_used_gib=round(r["device_used_gib"], 2), grad_rho_kw_kg_kf_scale=r["grad_head"])
+        if len(grads) == 2:
+            import numpy as np
+            g64 = grads["fp64"]
+            extra["fwd_adjoint_mixed_vs_fp64_grad_rel_l2"] = float(
+                f"{np.linalg.norm(grads['mixed'] - g64) / np.linalg.norm(g64):.3e}")
         if args.ckpt_steps > 0:
             # the checkpointed tape: a checkpoint every K steps, each reversed step
             # recomputes its window from the nearest checkpoint
