@@ -118,9 +118,13 @@ def run_form(tm, torch, inp, P, precision, steps, warmup, window, keep_fields=Fa
     dominant = max(SINGLE_KERNEL, key=lambda c: prof[c]["ms"])
     for c in CLASSES:
         sim.kernel_timer(c, c == dominant)       # only the dominant class inside the timed region
+    sim.substep_timer(True)                      # six events per step at the sub-step boundaries
     gpu_ms, wall, stats = timed_cycles(torch, sim, snap, steps, span)
     dom = sim.kernel_timer_read(dominant)
     sim.kernel_timer(dominant, False)
+    nsub, sub = sim.substep_timer_read()
+    sim.substep_timer(False)
+    substeps = {k: round(v / max(nsub, 1), 3) for k, v in sub.items()}
     log(f"[{precision}] {steps} steps in runs {cycle_plan(steps, span)}: events {gpu_ms / 1e3:.3f} s, wall {wall:.3f} s;"
         f" dominant {dominant}: {dom['launches']} launches, {dom['ms']:.1f} ms")
     # mass-effect diagnostics (scalars) of the displacement the timed runs ended with
@@ -135,7 +139,7 @@ def run_form(tm, torch, inp, P, precision, steps, warmup, window, keep_fields=Fa
     fields = window_end_fields(sim, snap, span) if keep_fields else None
     sim.close()
     return dict(wall=wall, gpu_ms=gpu_ms, stats=stats, warm_profile=prof, dominant=dominant, dom=dom,
-                diag=diag, diag_ms=diag_ms, fields=fields)
+                diag=diag, diag_ms=diag_ms, fields=fields, substeps=substeps)
 
 
 def run_single(tm, torch, inp, P, precision, steps, warmup, window, model="single", flags=None):
@@ -528,6 +532,8 @@ def main():
         extra["fp64_steps_per_s"] = round(v64, 4)
         extra["mixed_speedup_over_fp64"] = round(value / v64, 3)
         extra["fp64_roofline"] = roofline(fp64_run["dom"], fp64_run["dominant"], n)
+        extra["fp64_substep_ms_per_step"] = fp64_run["substeps"]
+    extra["substep_ms_per_step"] = main_run["substeps"]
     if compare:
         # error of the mixed form against the FP64 form (itself held to the FP64
         # oracle at 1e-10 by the parity tests), after every step from t = 0 to the

@@ -358,6 +358,19 @@ int tumor_kernel_timer(tumor_ctx* ctx, int32_t kernel_class, int32_t enable);
 int tumor_kernel_timer_read(tumor_ctx* ctx, int32_t kernel_class, int64_t* launches, double* ms,
                             double* bytes);
 
+/* Measurement hook: time every step's sub-steps (Sec. 3 splitting) with HIP
+ * events on the context's stream.  enable = 1 resets and starts, 0 stops.
+ * tumor_substep_timer_read: steps timed and ms (host, TUMOR_SUB_COUNT doubles)
+ * summed per sub-step: transport (both halves of the symmetric form, with the
+ * velocity), diffusion (the CN solves), reaction (reaction, oxygen, edema and
+ * the coefficient refresh), elasticity (force, solve and rotation).  The step
+ * also opens a roctx range per sub-step ("tumor transport", ...), which
+ * rocprofv3 --marker-trace records whether or not this timer is on. */
+enum { TUMOR_SUB_TRANSPORT = 0, TUMOR_SUB_DIFFUSION = 1, TUMOR_SUB_REACTION = 2, TUMOR_SUB_ELASTICITY = 3,
+       TUMOR_SUB_COUNT = 4 };
+int tumor_substep_timer(tumor_ctx* ctx, int32_t enable);
+int tumor_substep_timer_read(tumor_ctx* ctx, int64_t* steps, double* ms);
+
 /* Measurement hook: copy `bytes` (a multiple of 16, below 2^42) from src to
  * dst (device pointers, 16-byte aligned, not overlapping) with a streaming
  * kernel of one 16-byte load and store per thread, queued on hip_stream (NULL =

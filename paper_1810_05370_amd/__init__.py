@@ -138,6 +138,8 @@ def load_library(path: Optional[str] = None):
                                                    ctypes.POINTER(ctypes.c_double),
                                                    ctypes.POINTER(ctypes.c_double)]),
         "tumor_stream_copy": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
+        "tumor_substep_timer": (ctypes.c_int, [P, ctypes.c_int32]),
+        "tumor_substep_timer_read": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64), P]),
         "tumor_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
@@ -370,6 +372,19 @@ class Tumor:
         _check(self.lib.tumor_kernel_timer_read(self.ctx, KERNEL_CLASSES[name], ctypes.byref(n),
                                                 ctypes.byref(ms), ctypes.byref(b)))
         return dict(launches=n.value, ms=ms.value, bytes=b.value)
+
+    SUBSTEPS = ("transport", "diffusion", "reaction", "elasticity")
+
+    def substep_timer(self, enable=True):
+        _check(self.lib.tumor_substep_timer(self.ctx, 1 if enable else 0))
+
+    def substep_timer_read(self):
+        """(steps timed, {sub-step: summed ms})."""
+        import numpy as np
+        n = ctypes.c_int64(0)
+        ms = np.zeros(4)
+        _check(self.lib.tumor_substep_timer_read(self.ctx, ctypes.byref(n), ms.ctypes.data_as(ctypes.c_void_p)))
+        return n.value, dict(zip(self.SUBSTEPS, (float(v) for v in ms)))
 
     # -- adjoint ---------------------------------------------------------
     def record(self, nsteps, ckpt_every=1):

@@ -12,7 +12,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtumor.so")
 SOURCES = ["engine.hip", "pointwise.hip", "adjoint.hip", "fft_f64.hip", "fft_f32.hip"]
 
-HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
@@ -39,7 +40,9 @@ def build(verbose: bool = True) -> str:
     with ThreadPoolExecutor(workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    # roctx (sub-step ranges for profilers) from the ROCm install
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           "-L", os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -20,6 +20,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "adjoint.hpp"
 #include "kernels.hpp"
 #include "passes.hpp"
@@ -160,6 +162,12 @@ struct tumor_ctx {
   KTimer* timers[TUMOR_K_COUNT];
   int cur_tag;  // PCG iteration index of the launches being queued (-1 outside loops)
   int static_dev;  // device of an allocation-free context (tumor_init_static), else -1
+  // sub-step timer (tumor_substep_timer): events at the sub-step boundaries of
+  // every step, elapsed times summed per sub-step after the step's final sync
+  bool sub_on;
+  hipEvent_t sub_ev[6];
+  double sub_ms[TUMOR_SUB_COUNT];
+  long long sub_steps;
 };
 
 namespace {
@@ -983,12 +991,23 @@ void transport(Ctx& c, const double* const (&ins)[6], double* const (&outs)[6], 
   });
 }
 
+// Sub-step boundary k (0..5): an event for the sub-step timer and a roctx
+// range (named for the sub-step that starts here) for profilers.
+void substep_mark(Ctx& c, int k) {
+  static const char* const names[6] = {"tumor transport", "tumor diffusion", "tumor reaction",
+                                       "tumor transport (second half)", "tumor elasticity", ""};
+  if (k > 0) roctxRangePop();
+  if (k < 5) roctxRangePushA(names[k]);
+  if (c.sub_on) HIPCHECK(hipEventRecord(c.sub_ev[k], c.st));
+}
+
 void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
   enum { P, I, N, O, L, G, W, F };
   const int n = c.n;
   (void)n;
   // Symmetric form: S1 over dt/2 here and again after the reaction.
   const bool strang = (c.flags & TUMOR_F_STRANG) && (c.flags & TUMOR_F_ADVECTION);
+  substep_mark(c, 0);
   // S1: transport with u_t^n = (u^n - u^{n-1}) / dt
   if (c.flags & TUMOR_F_ADVECTION) {
     const double* const ins[6] = {c.F[P], c.F[I], c.F[N], c.F[G], c.F[W], c.F[F]};
@@ -1006,9 +1025,11 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
       HIPCHECK(hipMemcpyAsync(c.G[k], c.F[k], c.V * sizeof(double), hipMemcpyDeviceToDevice, c.st));
   }
   SolveOut sd[3];
+  substep_mark(c, 1);
   if (c.single) {
     // Single-species model: CN diffusion of c, then its reaction and the refresh.
     sd[0] = cn_solve(c, c.G[P], c.Rdd[0], 0);
+    substep_mark(c, 2);
     const double* in[9] = {c.G[P], c.G[P], c.Rdd[0], c.G[N], c.G[G], c.G[W], c.F[O], c.F[L], c.G[F]};
     double* out[8] = {c.F[P], c.F[I], c.F[N], c.F[G], c.F[W], c.F[O], c.F[L], c.F[F]};
     refresh(c, 1, in, out);
@@ -1018,6 +1039,7 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
   sd[1] = cn_solve(c, c.F[O], c.Rdd[1], 1);
   if (c.flags & TUMOR_F_EDEMA) sd[2] = cn_solve(c, c.F[L], c.Rdd[2], 2);
   else HIPCHECK(hipMemcpyAsync(c.Rdd[2], c.F[L], c.V * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+  substep_mark(c, 2);
   // S3-S5: reaction, oxygen, edema, refresh.
   {
     const double* in[9] = {c.G[P], c.G[I], c.Rdd[0], c.G[N], c.G[G], c.G[W], c.Rdd[1], c.Rdd[2], c.G[F]};
@@ -1025,6 +1047,7 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
     refresh(c, 1, in, out);
   }
   }
+  substep_mark(c, 3);
   if (strang) {
     // second half-step of S1 with the same velocity, from F back into G; the
     // two sets swap roles so the state stays in F; then the refresh (S5)
@@ -1035,6 +1058,7 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
     refresh_state(c);
   }
   // S6-S7: elasticity and rotation.
+  substep_mark(c, 4);
   SolveOut se;
   if (c.flags & TUMOR_F_ELASTICITY) {
     force_rhs(c, c.F[P], c.F[N], c.b64);
@@ -1046,11 +1070,23 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
   } else {
     HIPCHECK(hipMemcpyAsync(c.Up, c.U, 3 * c.S * sizeof(cplx<double>), hipMemcpyDeviceToDevice, c.st));
   }
+  substep_mark(c, 5);
   c.has_forced = false;
   timers_flush(c, 0x7fffffff);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipMemcpyAsync(c.hcs, c.cs, sizeof(tumor::CoefScalars), hipMemcpyDeviceToHost, c.st));
   HIPCHECK(hipStreamSynchronize(c.st));
+  if (c.sub_on) {
+    // boundaries 0..5: transport, diffusion, reaction, second transport half, elasticity
+    static const int slot[5] = {TUMOR_SUB_TRANSPORT, TUMOR_SUB_DIFFUSION, TUMOR_SUB_REACTION, TUMOR_SUB_TRANSPORT,
+                                TUMOR_SUB_ELASTICITY};
+    for (int k = 0; k < 5; ++k) {
+      float ms = 0.f;
+      HIPCHECK(hipEventElapsedTime(&ms, c.sub_ev[k], c.sub_ev[k + 1]));
+      c.sub_ms[slot[k]] += ms;
+    }
+    c.sub_steps++;
+  }
   bool any_bad = se.bad || c.hcs->bad;
   bool any_nc = !se.conv;
   for (int k = 0; k < 3; ++k) {
@@ -2082,6 +2118,28 @@ int tumor_kernel_timer_read(tumor_ctx* ctx, int32_t kernel_class, int64_t* launc
   });
 }
 
+int tumor_substep_timer(tumor_ctx* ctx, int32_t enable) {
+  if (!ctx) return einval("ctx is NULL");
+  return guarded([&]() -> int {
+    Ctx& c = *ctx;
+    if (enable && !c.sub_ev[0]) {
+      for (int k = 0; k < 6; ++k) HIPCHECK(hipEventCreate(&c.sub_ev[k]));
+    }
+    c.sub_on = enable != 0;
+    for (int k = 0; k < TUMOR_SUB_COUNT; ++k) c.sub_ms[k] = 0.0;
+    c.sub_steps = 0;
+    return TUMOR_OK;
+  });
+}
+
+int tumor_substep_timer_read(tumor_ctx* ctx, int64_t* steps, double* ms) {
+  if (!ctx) return einval("ctx is NULL");
+  if (!steps || !ms) return einval("steps/ms is NULL");
+  *steps = ctx->sub_steps;
+  for (int k = 0; k < TUMOR_SUB_COUNT; ++k) ms[k] = ctx->sub_ms[k];
+  return TUMOR_OK;
+}
+
 int tumor_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream) {
   if (!src || !dst) return einval("src/dst is NULL");
   if ((bytes & 15u) != 0) return einval("bytes must be a multiple of 16");
@@ -2141,6 +2199,8 @@ void tumor_destroy(tumor_ctx* ctx) {
     delete ctx->timers[k];
   }
   for (int k = 0; k < TUMOR_K_COUNT; ++k) ctx->timers[k] = nullptr;
+  for (int k = 0; k < 6; ++k)
+    if (ctx->sub_ev[k]) (void)hipEventDestroy(ctx->sub_ev[k]);
   if (ctx->static_dev >= 0) {
     // allocation-free context: its storage is the device's static slot
     std::lock_guard<std::mutex> lock(g_static_mu);

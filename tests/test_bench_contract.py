@@ -147,6 +147,12 @@ class _FakeSim:
     def kernel_timer_read(self, name):
         return dict(launches=1, ms=1.0 if name == "xelast32" else 0.5, bytes=1e9)
 
+    def substep_timer(self, enable=True):
+        pass
+
+    def substep_timer_read(self):
+        return self.steps, dict(transport=1.0, diffusion=1.0, reaction=1.0, elasticity=1.0)
+
     def diagnose(self, thr):
         return dict(max_disp=1.0)
 

@@ -222,3 +222,26 @@ def test_state_snapshot_restores_the_trajectory_bit_for_bit(precision):
     with pytest.raises(tm.TumorError):
         sim.load_state(snap[:-1])
     sim.close()
+
+
+def test_substep_timer_accounts_for_the_step():
+    """The sub-step events cover the step: their sum is the step's event time
+    (within the launch gaps before the first and after the last boundary)."""
+    torch = need_gpu()
+    P = synthetic.params()
+    inp = synthetic.workload_inputs("seeds3_n128", n=64)
+    sim = tm.from_inputs(inp, P, precision="mixed")
+    sim.step(2)
+    sim.substep_timer(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(sim.stream)
+    sim.step(3)
+    ev[1].record(sim.stream)
+    torch.cuda.synchronize()
+    n, sub = sim.substep_timer_read()
+    sim.close()
+    total = ev[0].elapsed_time(ev[1])
+    say(f"sub-steps over {n} steps: {sub}, step events {total:.2f} ms")
+    assert n == 3
+    assert all(v > 0.0 for v in sub.values())
+    assert 0.9 * total <= sum(sub.values()) <= total * 1.001
