@@ -291,12 +291,15 @@ int tumor_adjoint_step(tumor_ctx* ctx, double* adj, double* grad);
  * the library's internal representation, so a restored context steps exactly
  * as the saved one would have (bit for bit).
  *   tumor_state_bytes: size of one snapshot for cfg (host arguments).
- *   tumor_save_state: copy the current state into dst (device, >= bytes).
+ *   tumor_save_state: copy the current state into dst (device, >= bytes,
+ *     8-byte aligned); the snapshot starts with a small header naming n.
  *   tumor_load_state: replace the current state by the snapshot in src
- *     (device) and refresh the coefficients from it.  The snapshot must come
- *     from a context with the same n (and precision).  TUMOR_ESTATE while a
- *     recording (tumor_record) or its reverse sweep is unfinished; a finished
- *     recording is released.  Buffers are caller-owned, unaligned is fine. */
+ *     (device, 8-byte aligned) and refresh the coefficients from it.  A
+ *     snapshot of another grid size (or not a snapshot) gives TUMOR_EINVAL and
+ *     leaves the state unchanged; one of the other precision is accepted (the
+ *     state is FP64 in both).  TUMOR_ESTATE while a recording (tumor_record) or
+ *     its reverse sweep is unfinished; a finished recording is released.
+ *     Buffers are caller-owned. */
 int tumor_state_bytes(const tumor_config* cfg, size_t* bytes);
 int tumor_save_state(tumor_ctx* ctx, void* dst, size_t bytes);
 int tumor_load_state(tumor_ctx* ctx, const void* src, size_t bytes);

@@ -2154,19 +2154,27 @@ int tumor_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream
   });
 }
 
+// A snapshot starts with a 256-byte header (magic, grid size, field count) so
+// that a snapshot of another grid is refused; the state follows.
+constexpr size_t kSnapHeader = 256;
+constexpr long long kSnapMagic = 0x54554d4f52534e31LL;  // "TUMORSN1"
+
 int tumor_state_bytes(const tumor_config* cfg, size_t* bytes) {
   if (!bytes) return einval("bytes is NULL");
   if (check_cfg(cfg) != TUMOR_OK) return einval("invalid tumor_config");
-  *bytes = slot_bytes((long long)cfg->n * cfg->n * cfg->n);
+  *bytes = kSnapHeader + slot_bytes((long long)cfg->n * cfg->n * cfg->n);
   return TUMOR_OK;
 }
 
 int tumor_save_state(tumor_ctx* ctx, void* dst, size_t bytes) {
   if (!ctx) return einval("ctx is NULL");
   if (!dst) return einval("dst is NULL");
-  if (bytes < slot_bytes(ctx->V)) return einval("snapshot buffer smaller than tumor_state_bytes");
+  if (bytes < kSnapHeader + slot_bytes(ctx->V)) return einval("snapshot buffer smaller than tumor_state_bytes");
+  if (reinterpret_cast<uintptr_t>(dst) & 7u) return einval("dst must be 8-byte aligned");
   return guarded([&]() -> int {
-    save_state(*ctx, static_cast<double*>(dst));
+    long long hdr[4] = {kSnapMagic, ctx->n, 14, 0};
+    HIPCHECK(hipMemcpyAsync(dst, hdr, sizeof(hdr), hipMemcpyHostToDevice, ctx->st));
+    save_state(*ctx, reinterpret_cast<double*>(static_cast<char*>(dst) + kSnapHeader));
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(ctx->st));
     return TUMOR_OK;
@@ -2176,14 +2184,20 @@ int tumor_save_state(tumor_ctx* ctx, void* dst, size_t bytes) {
 int tumor_load_state(tumor_ctx* ctx, const void* src, size_t bytes) {
   if (!ctx) return einval("ctx is NULL");
   if (!src) return einval("src is NULL");
-  if (bytes < slot_bytes(ctx->V)) return einval("snapshot buffer smaller than tumor_state_bytes");
+  if (bytes < kSnapHeader + slot_bytes(ctx->V)) return einval("snapshot buffer smaller than tumor_state_bytes");
+  if (reinterpret_cast<uintptr_t>(src) & 7u) return einval("src must be 8-byte aligned");
   if (ctx->rec_active && (ctx->rec_steps < ctx->rec_nsteps || ctx->rev_done < ctx->rec_steps)) {
     g_err = "a recording or its reverse sweep is in progress; loading a state would invalidate its tape";
     return TUMOR_ESTATE;
   }
   return guarded([&]() -> int {
+    long long hdr[4] = {0, 0, 0, 0};
+    HIPCHECK(hipMemcpyAsync(hdr, src, sizeof(hdr), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHECK(hipStreamSynchronize(ctx->st));
+    if (hdr[0] != kSnapMagic || hdr[1] != ctx->n || hdr[2] != 14)
+      throw Fail(TUMOR_EINVAL, "not a state snapshot of a grid of this size");
     ctx->rec_active = 0;
-    load_state(*ctx, static_cast<const double*>(src));
+    load_state(*ctx, reinterpret_cast<const double*>(static_cast<const char*>(src) + kSnapHeader));
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(ctx->st));
     return TUMOR_OK;

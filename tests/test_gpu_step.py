@@ -221,6 +221,17 @@ def test_state_snapshot_restores_the_trajectory_bit_for_bit(precision):
     # a snapshot too small for the state is refused before any device work
     with pytest.raises(tm.TumorError):
         sim.load_state(snap[:-1])
+    # a snapshot of another grid, padded to this grid's size, is refused by its
+    # header and leaves the state as it was
+    other = tm.from_inputs(synthetic.workload_inputs("seeds3_n128", n=16), P, precision=precision)
+    small = other.save_state()
+    other.close()
+    padded = torch.zeros(snap.numel(), dtype=torch.uint8, device="cuda")
+    padded[:small.numel()].copy_(small)
+    with pytest.raises(tm.TumorError) as e:
+        sim.load_state(padded)
+    assert e.value.code == tm.EINVAL
+    assert torch.equal(sim.get("p"), b["p"])
     sim.close()
 
 
