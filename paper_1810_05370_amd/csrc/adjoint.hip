@@ -5,10 +5,11 @@
 //   k_coef_adj  : Lame / screening mixture -> species adjoints, d/d lame_scale
 //   k_s0_adj    : step coefficients K, rho -> w, g, f and d/d(k_w, k_g, k_f, rho)
 //   k_force_adj : pointwise part of the force b = zeta tanh(tau) G tau
-//   k_sl_adj    : semi-Lagrangian transport (interpolation transpose summed
-//                 per brick in LDS, then added to global memory, both in 64-bit
-//                 fixed point so that the sums do not depend on the order of the
-//                 atomics; velocity sensitivity through X and X*)
+//   k_sl_adj    : semi-Lagrangian transport (gathers at X* and X from LDS
+//                 halo tiles; interpolation transpose summed per brick in LDS,
+//                 then added to global memory, both in 64-bit fixed point so
+//                 that the sums do not depend on the order of the atomics;
+//                 velocity sensitivity through X and X*)
 //   k_ic_adj    : projections onto the Gaussian initial-condition basis
 // Parameter sums use deterministic block partials totalled by a one-block kernel.
 #include <algorithm>
@@ -17,6 +18,7 @@
 #include <stdexcept>
 
 #include "adjoint.hpp"
+#include "sl_tile.hpp"
 
 namespace tumor {
 
@@ -238,63 +240,120 @@ __global__ void k_xpay(long long V, const double* x, double coef, const double* 
 }
 
 // ------------------------------------------------------- semi-Lagrangian
-__device__ __forceinline__ void lw4(double t, double (&w)[4], double (&d)[4]) {
+// Cubic Lagrange weights of the nodes j-1 .. j+2 at offset t in [0, 1), and
+// their derivatives in t.
+__device__ __forceinline__ void lw4(double t, double (&w)[4]) {
   w[0] = -t * (t - 1.0) * (t - 2.0) / 6.0;
   w[1] = (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0;
   w[2] = -(t + 1.0) * t * (t - 2.0) / 2.0;
   w[3] = (t + 1.0) * t * (t - 1.0) / 6.0;
+}
+__device__ __forceinline__ void dlw4(double t, double (&d)[4]) {
   d[0] = -(3.0 * t * t - 6.0 * t + 2.0) / 6.0;
   d[1] = (3.0 * t * t - 4.0 * t - 1.0) / 2.0;
   d[2] = -(3.0 * t * t - 2.0 * t - 2.0) / 2.0;
   d[3] = (3.0 * t * t - 1.0) / 6.0;
 }
 
+// Tricubic stencil of a point in grid-index units: base node and weights.
 struct Stencil {
   int ix, iy, iz;
-  double wx[4], wy[4], wz[4], dx[4], dy[4], dz[4];
+  double wx[4], wy[4], wz[4];
   __device__ __forceinline__ void set(double jx, double jy, double jz) {
     const double bx = floor(jx), by = floor(jy), bz = floor(jz);
-    lw4(jx - bx, wx, dx);
-    lw4(jy - by, wy, dy);
-    lw4(jz - bz, wz, dz);
+    lw4(jx - bx, wx);
+    lw4(jy - by, wy);
+    lw4(jz - bz, wz);
     ix = (int)(long long)bx;
     iy = (int)(long long)by;
     iz = (int)(long long)bz;
   }
 };
 
-// Value and gradient (d/dj along x, y, z) of NF interpolants at one stencil.
-template <int NF>
-__device__ __forceinline__ void gather_grad(const Stencil& s, const double* const (&q)[NF], int n,
-                                            double (&val)[NF], double (&gx)[NF], double (&gy)[NF],
-                                            double (&gz)[NF]) {
-  const int m = n - 1;
-#pragma unroll
-  for (int f = 0; f < NF; ++f) val[f] = gx[f] = gy[f] = gz[f] = 0.0;
-  // the 16 (z, y) rows stay rolled: unrolled, they hold far more loads in
-  // flight than the register file has room for
-#pragma unroll 1
-  for (int c = 0; c < 4; ++c) {
-    const long long zo = (long long)((s.iz + c - 1) & m) * n * n;
-#pragma unroll 1
-    for (int b = 0; b < 4; ++b) {
-      const long long yo = zo + (long long)((s.iy + b - 1) & m) * n;
-      const double wzy = s.wz[c] * s.wy[b], dzy = s.dz[c] * s.wy[b], wzdy = s.wz[c] * s.dy[b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const long long idx = yo + ((s.ix + a - 1) & m);
-        const double w = wzy * s.wx[a], wgx = wzy * s.dx[a], wgy = wzdy * s.wx[a], wgz = dzy * s.wx[a];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          const double qv = q[f][idx];
-          val[f] += w * qv;
-          gx[f] += wgx * qv;
-          gy[f] += wgy * qv;
-          gz[f] += wgz * qv;
-        }
-      }
-    }
+// The same with the derivative weights, for value-and-gradient gathers.
+struct StencilD : Stencil {
+  double dx[4], dy[4], dz[4];
+  __device__ __forceinline__ void set(double jx, double jy, double jz) {
+    Stencil::set(jx, jy, jz);
+    dlw4(jx - floor(jx), dx);
+    dlw4(jy - floor(jy), dy);
+    dlw4(jz - floor(jz), dz);
   }
+};
+
+// w[i] for a runtime i in 0..3 by selects, so that rolled loops do not put
+// the weight arrays in scratch memory.
+__device__ __forceinline__ double pick4(const double (&w)[4], int i) {
+  return i == 0 ? w[0] : (i == 1 ? w[1] : (i == 2 ? w[2] : w[3]));
+}
+
+// Visit the 64 nodes of a stencil: fn(idx, w, wgx, wgy, wgz) with the value
+// weight and the three derivative weights (d/dj along x, y, z) of the node.
+// The 16 (z, y) rows stay rolled: unrolled, they hold far more loads in
+// flight than the register file has room for.
+template <typename Fn>
+__device__ __forceinline__ void for_taps(const StencilD& s, int n, Fn fn) {
+  const int m = n - 1;
+#pragma unroll 1
+  for (int r = 0; r < 16; ++r) {
+    const int c = r >> 2, b = r & 3;
+    const long long yo = ((long long)((s.iz + c - 1) & m) * n + ((s.iy + b - 1) & m)) * n;
+    const double wz = pick4(s.wz, c), dz = pick4(s.dz, c), wy = pick4(s.wy, b), dy = pick4(s.dy, b);
+    const double wzy = wz * wy, dzy = dz * wy, wzdy = wz * dy;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      fn(yo + ((s.ix + a - 1) & m), wzy * s.wx[a], wzy * s.dx[a], wzdy * s.wx[a], dzy * s.wx[a]);
+  }
+}
+
+// Value and gradient of the three velocity interpolants at one stencil:
+// val[b] = I[v_b], g[b][a] = d/dj_a I[v_b].
+__device__ __forceinline__ void gather_vel(const StencilD& s, const double* __restrict__ vx,
+                                           const double* __restrict__ vy, const double* __restrict__ vz, int n,
+                                           double (&val)[3], double (&g)[3][3]) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b) val[b] = g[b][0] = g[b][1] = g[b][2] = 0.0;
+  for_taps(s, n, [&](long long idx, double w, double wgx, double wgy, double wgz) {
+    const double q[3] = {vx[idx], vy[idx], vz[idx]};
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      val[b] += w * q[b];
+      g[b][0] += wgx * q[b];
+      g[b][1] += wgy * q[b];
+      g[b][2] += wgz * q[b];
+    }
+  });
+}
+
+// The interpolants that the transpose needs at the departure point X, with
+// the arrival voxel's adjoints lam (constant over the stencil) folded in
+// before the sums: e = I[sum_{k<5} lam_k q_k] and its gradient (e[0], e[1..3]),
+// the gradient of I[lam_5 q_5] (e5), and I[div v] with its gradient (d).
+// Twelve sums instead of the 28 of seven separate values and gradients.
+__device__ __forceinline__ void gather_adj(const StencilD& s, const double* const (&q)[6],
+                                           const double* __restrict__ div, const double (&lam)[6], int n,
+                                           double (&e)[4], double (&e5)[3], double (&d)[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) e[k] = d[k] = 0.0;
+  e5[0] = e5[1] = e5[2] = 0.0;
+  for_taps(s, n, [&](long long idx, double w, double wgx, double wgy, double wgz) {
+    double c = lam[0] * q[0][idx];
+#pragma unroll
+    for (int k = 1; k < 5; ++k) c += lam[k] * q[k][idx];
+    const double c5 = lam[5] * q[5][idx];
+    const double dv = div[idx];
+    e[0] += w * c;
+    e[1] += wgx * c;
+    e[2] += wgy * c;
+    e[3] += wgz * c;
+    e5[0] += wgx * c5;
+    e5[1] += wgy * c5;
+    e5[2] += wgz * c5;
+    d[0] += w * dv;
+    d[1] += wgx * dv;
+    d[2] += wgy * dv;
+    d[3] += wgz * dv;
+  });
 }
 
 // ---- fixed-point accumulation of the transposed interpolation
@@ -314,97 +373,113 @@ __device__ __forceinline__ void fix_add(double* acc, long long q) {
   atomicAdd(reinterpret_cast<unsigned long long*>(acc), static_cast<unsigned long long>(q));
 }
 
-template <int NF>
-__device__ __forceinline__ void scatter(const Stencil& s, double* const (&out)[NF], const double (&val)[NF], int n,
-                                        const double (&scale)[NF]) {
-  const int m = n - 1;
-#pragma unroll 1
-  for (int c = 0; c < 4; ++c) {
-    const long long zo = (long long)((s.iz + c - 1) & m) * n * n;
-#pragma unroll 1
-    for (int b = 0; b < 4; ++b) {
-      const long long yo = zo + (long long)((s.iy + b - 1) & m) * n;
-      const double wzy = s.wz[c] * s.wy[b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const long long idx = yo + ((s.ix + a - 1) & m);
-        const double w = wzy * s.wx[a];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) fix_add(out[f] + idx, to_fix(w * val[f], scale[f]));
-      }
-    }
-  }
-}
-
 // One 16 x 4 x 4 brick of arrival voxels per 256-thread block (n >= 16, so the
 // bricks tile the grid), bricks laid out x fastest, and consecutive block
 // indices spread over the 8 XCDs so that each XCD sweeps a contiguous slab.
 constexpr int kSlAdjBX = 16, kSlAdjBY = 4, kSlAdjBZ = 4;
-// LDS accumulation tile for the transposed interpolation (64-bit fixed point).  A brick's
-// stencils span (16 + 3 + dx) x (4 + 3 + dy) x (4 + 3 + dz) nodes, dx, dy, dz
-// the spread of its departure cells; 2048 covers a spread of 2 cells per axis.
+constexpr int kSlAdjThreads = kSlAdjBX * kSlAdjBY * kSlAdjBZ;
+static_assert(kSlAdjThreads == 256, "the tile helpers assume 256-thread blocks");
+// LDS tile of the box of a brick's stencils, (16 + 3 + dx) x (4 + 3 + dy) x
+// (4 + 3 + dz) nodes for a spread dx, dy, dz of its departure cells; 2048
+// nodes cover a spread of 2 cells per axis.  A gather holds two FP64 values
+// per node, the scatter two 64-bit fixed-point sums (the same 32 KiB).
 constexpr int kSlAdjTile = 2048;
 
-// Transposed interpolation of NF values per voxel of a block: each tap's
-// contribution w * val[f] goes to the node it was read from.  Contributions
-// are first summed in an LDS tile over the bounding box of the block's
-// stencils (LDS atomics), then each tile node is added to global memory with
-// one atomic, one field at a time.  A block whose box exceeds the tile adds
-// every contribution with a global atomic instead.  All sums are 64-bit fixed
-// point (scale[f] per field), so both paths give the same integers.  Called by
-// all threads of the block (block-uniform control flow).
-template <int NF>
-__device__ void scatter_tiled(const Stencil& s, double* const (&out)[NF], const double (&val)[NF], int n,
-                              const double (&scale)[NF], long long* tile, int* box) {
-  __syncthreads();  // every thread is done with box from a previous call
-  if (threadIdx.x == 0) {
-    box[0] = box[1] = box[2] = INT_MAX;
-    box[3] = box[4] = box[5] = INT_MIN;
+// Visit the 64 taps of a stencil in an LDS tile of G-value nodes whose
+// origin is box and extent L: fn(vals, w, wgx, wgy, wgz).
+template <int G, typename Fn>
+__device__ __forceinline__ void tile_taps(const double* tile, const StencilD& s, const int (&box)[3],
+                                          const int (&L)[3], Fn fn) {
+  const int rx = s.ix - 1 - box[0], ry = s.iy - 1 - box[1], rz = s.iz - 1 - box[2];
+#pragma unroll 1
+  for (int r = 0; r < 16; ++r) {
+    const int c = r >> 2, b = r & 3;
+    const int base = ((rz + c) * L[1] + (ry + b)) * L[0] + rx;
+    const double wz = pick4(s.wz, c), dz = pick4(s.dz, c), wy = pick4(s.wy, b), dy = pick4(s.dy, b);
+    const double wzy = wz * wy, dzy = dz * wy, wzdy = wz * dy;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      double q[G];
+      tile_get<G, double>(tile, base + a, q);
+      fn(q, wzy * s.wx[a], wzy * s.dx[a], wzdy * s.wx[a], dzy * s.wx[a]);
+    }
   }
+}
+
+// Stage the box of G fields into the tile (between barriers: the previous
+// readers of the tile are done, and every thread sees the new contents).
+template <int G>
+__device__ __forceinline__ void tile_load(double* tile, const double* const (&src)[G], const int (&box)[3],
+                                          const int (&L)[3], int n) {
+  double sc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) sc[g] = 1.0;
   __syncthreads();
-  atomicMin(&box[0], s.ix);
-  atomicMin(&box[1], s.iy);
-  atomicMin(&box[2], s.iz);
-  atomicMax(&box[3], s.ix);
-  atomicMax(&box[4], s.iy);
-  atomicMax(&box[5], s.iz);
+  tile_stage<double, G>(tile, src, sc, box[0], box[1], box[2], L, n);
   __syncthreads();
-  const int x0 = box[0], y0 = box[1], z0 = box[2];
-  const long long DX = (long long)box[3] - x0 + 4, DY = (long long)box[4] - y0 + 4, DZ = (long long)box[5] - z0 + 4;
-  if (DX * DY * DZ > kSlAdjTile) {
-    scatter<NF>(s, out, val, n, scale);
+}
+
+// Transposed interpolation of nf values per voxel at the stencil s: each
+// tap's contribution w * val[f] goes to the node it was read from.  The
+// values, targets and scales are in LDS (sval[f][thread], sout[f], sscale[f]).
+// With the box in the tile (fits), contributions of two fields at a time
+// are summed in LDS with integer atomics, then each tile node is added to
+// global memory with one atomic per field; otherwise every contribution
+// goes straight to a global atomic.  All sums are 64-bit fixed point, so
+// both paths give the same integers.  Called by all threads of the block
+// (block-uniform control flow).
+__device__ void scatter_block(const Stencil& s, int f0, int nf, double (*sval)[kSlAdjThreads],
+                              double* const* sout, const double* sscale, bool fits, const int (&box)[3],
+                              const int (&L)[3], long long* tile, int n) {
+  const int m = n - 1;
+  if (!fits) {
+    for (int f = f0; f < f0 + nf; ++f) {
+      const double vf = sval[f][threadIdx.x], sc = sscale[f];
+      double* const of = sout[f];
+#pragma unroll 1
+      for (int r = 0; r < 16; ++r) {
+        const int c = r >> 2, b = r & 3;
+        const long long yo = ((long long)((s.iz + c - 1) & m) * n + ((s.iy + b - 1) & m)) * n;
+        const double wzy = pick4(s.wz, c) * pick4(s.wy, b) * vf;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) fix_add(of + yo + ((s.ix + a - 1) & m), to_fix(wzy * s.wx[a], sc));
+      }
+    }
     return;
   }
-  const int m = n - 1;
-  const int dxn = (int)DX, dyn = (int)DY, cnt = (int)(DX * DY * DZ);
-  // tile coordinates of the stencil's first node (x0 - 1, y0 - 1, z0 - 1 is the tile origin)
-  const int bx = s.ix - x0, by = s.iy - y0, bz = s.iz - z0;
-  for (int f = 0; f < NF; ++f) {
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x) tile[k] = 0;
+  const int cnt = L[0] * L[1] * L[2];
+  const int rx = s.ix - 1 - box[0], ry = s.iy - 1 - box[1], rz = s.iz - 1 - box[2];
+  for (int f = f0; f < f0 + nf; f += 2) {
+    const int g2 = (f + 1 < f0 + nf) ? 2 : 1;  // fields in this round (block-uniform)
+    __syncthreads();  // the previous users of the tile are done
+    for (int k = threadIdx.x; k < g2 * cnt; k += kSlAdjThreads) tile[k] = 0;
     __syncthreads();
+    for (int g = 0; g < g2; ++g) {
+      const double vf = sval[f + g][threadIdx.x], sc = sscale[f + g];
+      long long* const tg = tile + g * cnt;
 #pragma unroll 1
-    for (int c = 0; c < 4; ++c) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const double wzy = s.wz[c] * s.wy[b];
-        const int row = ((bz + c) * dyn + (by + b)) * dxn + bx;
+      for (int r = 0; r < 16; ++r) {
+        const int c = r >> 2, b = r & 3;
+        const double wzy = pick4(s.wz, c) * pick4(s.wy, b) * vf;
+        const int row = ((rz + c) * L[1] + (ry + b)) * L[0] + rx;
 #pragma unroll
         for (int a = 0; a < 4; ++a)
-          atomicAdd(reinterpret_cast<unsigned long long*>(&tile[row + a]),
-                    static_cast<unsigned long long>(to_fix(wzy * s.wx[a] * val[f], scale[f])));
+          atomicAdd(reinterpret_cast<unsigned long long*>(&tg[row + a]),
+                    static_cast<unsigned long long>(to_fix(wzy * s.wx[a], sc)));
       }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+    for (int k = threadIdx.x; k < g2 * cnt; k += kSlAdjThreads) {
       const long long t = tile[k];
       if (t != 0) {
-        const int tx = k % dxn, ty = (k / dxn) % dyn, tz = k / (dxn * dyn);
+        const int g = k >= cnt ? 1 : 0;
+        const int e = k - g * cnt;
+        const int tx = e % L[0], ty = (e / L[0]) % L[1], tz = e / (L[0] * L[1]);
         const long long idx =
-            ((long long)((z0 - 1 + tz) & m) * n + ((y0 - 1 + ty) & m)) * n + ((x0 - 1 + tx) & m);
-        fix_add(out[f] + idx, t);
+            ((long long)((box[2] + tz) & m) * n + ((box[1] + ty) & m)) * n + ((box[0] + tx) & m);
+        fix_add(sout[f + g] + idx, t);
       }
     }
-    __syncthreads();
   }
 }
 
@@ -512,12 +587,23 @@ __global__ void __launch_bounds__(256) k_sl_adj_finish(SLAdjArgs a, const GradSc
   }
 }
 
-__global__ void __launch_bounds__(256) k_sl_adj(SLAdjArgs a, const GradScalars* gs) {
-  __shared__ long long tile[kSlAdjTile];
-  __shared__ int box[6];
-  double scale[10];
-  bool finite;
-  sl_adj_scales(gs, a.dt, a.s, scale, finite);
+// Transpose of the semi-Lagrangian step (Sec. 3) for one arrival voxel per
+// thread.  With X* = x - s v, v* = I[v](X*), X = x - s/2 (v + v*) and the
+// Heun factor cfac = 1 - dt/2 (div(X) + div(x)) + dt^2/2 div(X) div(x), the
+// forward step is q+_k(x) = cfac I[q_k](X) for k < 5 and q+_5 = I[q_5](X).
+// The gathers at X* and X read LDS halo tiles of the brick's stencil box (or
+// global memory when the box exceeds the tile); the transposed
+// interpolations accumulate in the same tiles.  Interpolation weights are
+// recomputed from the departure points where they are needed, rather than
+// held across the gathers and scatters, so that the kernel stays within the
+// register file.
+__global__ void __launch_bounds__(kSlAdjThreads) k_sl_adj(SLAdjArgs a, const GradScalars* gs) {
+  __shared__ __align__(16) long long tile[2 * kSlAdjTile];
+  __shared__ double sval[10][kSlAdjThreads];
+  __shared__ double* sout[10];
+  __shared__ double sscale[10];
+  __shared__ int red[24];
+  double* const dtile = reinterpret_cast<double*>(tile);
   const int n = a.n_grid;
   const int nbx = n / kSlAdjBX, nby = n / kSlAdjBY;
   const int nb = (int)gridDim.x;
@@ -528,63 +614,148 @@ __global__ void __launch_bounds__(256) k_sl_adj(SLAdjArgs a, const GradScalars* 
   const long long v = ((long long)jz * n + jy) * n + jx;
   const double s = a.s, dt = a.dt;
   const double vx = a.vx[v], vy = a.vy[v], vz = a.vz[v], d0 = a.div[v];
-  // X* and v(X*)
-  Stencil st_s;
-  st_s.set(jx - s * vx, jy - s * vy, jz - s * vz);
-  const double* const vel[3] = {a.vx, a.vy, a.vz};
-  double vs[3], vsx[3], vsy[3], vsz[3];
-  gather_grad<3>(st_s, vel, n, vs, vsx, vsy, vsz);
-  // X and the fields there
-  Stencil st;
-  st.set(jx - 0.5 * s * (vx + vs[0]), jy - 0.5 * s * (vy + vs[1]), jz - 0.5 * s * (vz + vs[2]));
-  const double* const fl[7] = {a.q[0], a.q[1], a.q[2], a.q[3], a.q[4], a.q[5], a.div};
-  double q[7], qx[7], qy[7], qz[7];
-  gather_grad<7>(st, fl, n, q, qx, qy, qz);
-  const double dX = q[6];
+  // X*, computed once: the scatter's stencil must have the gather's floors
+  const double XS[3] = {jx - s * vx, jy - s * vy, jz - s * vz};
+  int box1[3], L1[3], box2[3], L2[3];
+  bool fits1, fits2;
+  // v* = I[v](X*) and its gradient gv[b][c] = d/dj_c I[v_b](X*)
+  double vs[3], gv[3][3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) vs[b] = gv[b][0] = gv[b][1] = gv[b][2] = 0.0;
+  {
+    StencilD st;
+    st.set(XS[0], XS[1], XS[2]);
+    int lo[3] = {st.ix, st.iy, st.iz}, hi[3] = {st.ix, st.iy, st.iz};
+    block_box(lo, hi, red);
+    fits1 = box_fits(lo, hi, n, kSlAdjTile, box1, L1);
+    if (fits1) {
+      const double* const s01[2] = {a.vx, a.vy};
+      tile_load<2>(dtile, s01, box1, L1, n);
+      tile_taps<2>(dtile, st, box1, L1, [&](const double (&q)[2], double w, double wgx, double wgy, double wgz) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          vs[b] += w * q[b];
+          gv[b][0] += wgx * q[b];
+          gv[b][1] += wgy * q[b];
+          gv[b][2] += wgz * q[b];
+        }
+      });
+      const double* const s2[1] = {a.vz};
+      tile_load<1>(dtile, s2, box1, L1, n);
+      tile_taps<1>(dtile, st, box1, L1, [&](const double (&q)[1], double w, double wgx, double wgy, double wgz) {
+        vs[2] += w * q[0];
+        gv[2][0] += wgx * q[0];
+        gv[2][1] += wgy * q[0];
+        gv[2][2] += wgz * q[0];
+      });
+    } else {
+      gather_vel(st, a.vx, a.vy, a.vz, n, vs, gv);
+    }
+  }
+  const double X[3] = {jx - 0.5 * s * (vx + vs[0]), jy - 0.5 * s * (vy + vs[1]), jz - 0.5 * s * (vz + vs[2])};
+  double lam[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) lam[k] = a.lam[k][v];
+  // at X: e = I[sum_{k<5} lam_k q_k] with its gradient, grad I[lam_5 q_5], I[div v] with its gradient
+  double e[4], e5[3], dq[4];
+  {
+    StencilD st;
+    st.set(X[0], X[1], X[2]);
+    int lo[3] = {st.ix, st.iy, st.iz}, hi[3] = {st.ix, st.iy, st.iz};
+    block_box(lo, hi, red);
+    fits2 = box_fits(lo, hi, n, kSlAdjTile, box2, L2);
+    if (fits2) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) e[k] = dq[k] = 0.0;
+      e5[0] = e5[1] = e5[2] = 0.0;
+      auto acc_e = [&](double c, double w, double wgx, double wgy, double wgz) {
+        e[0] += w * c;
+        e[1] += wgx * c;
+        e[2] += wgy * c;
+        e[3] += wgz * c;
+      };
+      const double* const p01[2] = {a.q[0], a.q[1]};
+      tile_load<2>(dtile, p01, box2, L2, n);
+      tile_taps<2>(dtile, st, box2, L2, [&](const double (&q)[2], double w, double wgx, double wgy, double wgz) {
+        acc_e(lam[0] * q[0] + lam[1] * q[1], w, wgx, wgy, wgz);
+      });
+      const double* const p23[2] = {a.q[2], a.q[3]};
+      tile_load<2>(dtile, p23, box2, L2, n);
+      tile_taps<2>(dtile, st, box2, L2, [&](const double (&q)[2], double w, double wgx, double wgy, double wgz) {
+        acc_e(lam[2] * q[0] + lam[3] * q[1], w, wgx, wgy, wgz);
+      });
+      const double* const p45[2] = {a.q[4], a.q[5]};
+      tile_load<2>(dtile, p45, box2, L2, n);
+      tile_taps<2>(dtile, st, box2, L2, [&](const double (&q)[2], double w, double wgx, double wgy, double wgz) {
+        acc_e(lam[4] * q[0], w, wgx, wgy, wgz);
+        const double c5 = lam[5] * q[1];
+        e5[0] += wgx * c5;
+        e5[1] += wgy * c5;
+        e5[2] += wgz * c5;
+      });
+      const double* const pd[1] = {a.div};
+      tile_load<1>(dtile, pd, box2, L2, n);
+      tile_taps<1>(dtile, st, box2, L2, [&](const double (&q)[1], double w, double wgx, double wgy, double wgz) {
+        dq[0] += w * q[0];
+        dq[1] += wgx * q[0];
+        dq[2] += wgy * q[0];
+        dq[3] += wgz * q[0];
+      });
+    } else {
+      gather_adj(st, a.q, a.div, lam, n, e, e5, dq);
+    }
+  }
+  const double dX = dq[0];
   const double cfac = 1.0 - 0.5 * dt * (dX + d0) + 0.5 * dt * dt * dX * d0;
-  double bar[7];
-  double cbar = 0.0;
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const double lam = a.lam[k][v];
-    cbar += lam * q[k];
-    bar[k] = lam * cfac;
-  }
-  bar[5] = a.lam[5][v];
-  bar[6] = cbar * (-0.5 * dt + 0.5 * dt * dt * d0);
+  const double cbar = e[0];  // sum_{k<5} lam_k I[q_k](X)
+  const double bar6 = cbar * (-0.5 * dt + 0.5 * dt * dt * d0);
   const double ddirect = cbar * (-0.5 * dt + 0.5 * dt * dt * dX);
-  double Jb[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    Jb[0] += bar[k] * qx[k];
-    Jb[1] += bar[k] * qy[k];
-    Jb[2] += bar[k] * qz[k];
-  }
-  double* const outs[7] = {a.out[0], a.out[1], a.out[2], a.out[3], a.out[4], a.out[5], a.divb};
-  const double sc7[7] = {scale[0], scale[1], scale[2], scale[3], scale[4], scale[5], scale[6]};
-  scatter_tiled<7>(st, outs, bar, n, sc7, tile, box);
-  fix_add(a.divb + v, to_fix(ddirect, scale[6]));
-  // X = x - s/2 (v + v*), v* = I[v](X*), X* = x - s v
+  // adjoint of X: sum_k bar_k grad I[q_k](X), bar_6 belonging to div v
   double vsb[3], vown[3];
 #pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    vsb[b] = -0.5 * s * Jb[b];
-    vown[b] = -0.5 * s * Jb[b];
+  for (int c = 0; c < 3; ++c) vsb[c] = -0.5 * s * (cfac * e[1 + c] + e5[c] + bar6 * dq[1 + c]);
+  // X* moves with v (directly) and through v*
+#pragma unroll
+  for (int c = 0; c < 3; ++c) vown[c] = vsb[c] - s * (vsb[0] * gv[0][c] + vsb[1] * gv[1][c] + vsb[2] * gv[2][c]);
+  // values, targets and fixed-point scales of the ten scattered fields
+#pragma unroll
+  for (int k = 0; k < 5; ++k) sval[k][threadIdx.x] = lam[k] * cfac;
+  sval[5][threadIdx.x] = lam[5];
+  sval[6][threadIdx.x] = bar6;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) sval[7 + c][threadIdx.x] = vsb[c];
+  if (threadIdx.x == 0) {
+    double scale[10];
+    bool finite;
+    sl_adj_scales(gs, dt, s, scale, finite);
+    double* const t[10] = {a.out[0], a.out[1], a.out[2], a.out[3], a.out[4], a.out[5], a.divb,
+                           a.vb[0], a.vb[1], a.vb[2]};
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+      sout[k] = t[k];
+      sscale[k] = scale[k];
+    }
   }
-  double Jsb[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    Jsb[0] += vsb[b] * vsx[b];
-    Jsb[1] += vsb[b] * vsy[b];
-    Jsb[2] += vsb[b] * vsz[b];
+  __syncthreads();
+  {
+    double xx = X[0], xy = X[1], xz = X[2];
+    asm volatile("" : "+v"(xx), "+v"(xy), "+v"(xz));
+    Stencil st;
+    st.set(xx, xy, xz);
+    scatter_block(st, 0, 7, sval, sout, sscale, fits2, box2, L2, tile, n);
+  }
+  fix_add(a.divb + v, to_fix(ddirect, sscale[6]));
+  {
+    // X* again, opaque to the compiler, which would otherwise keep the
+    // weights of the first gather alive across the second
+    double xs = XS[0], ys = XS[1], zs = XS[2];
+    asm volatile("" : "+v"(xs), "+v"(ys), "+v"(zs));
+    Stencil st;
+    st.set(xs, ys, zs);
+    scatter_block(st, 7, 3, sval, sout, sscale, fits1, box1, L1, tile, n);
   }
 #pragma unroll
-  for (int b = 0; b < 3; ++b) vown[b] += -s * Jsb[b];
-  double* const vb[3] = {a.vb[0], a.vb[1], a.vb[2]};
-  const double sc3[3] = {scale[7], scale[8], scale[9]};
-  scatter_tiled<3>(st_s, vb, vsb, n, sc3, tile, box);
-#pragma unroll
-  for (int b = 0; b < 3; ++b) fix_add(a.vb[b] + v, to_fix(vown[b], scale[7 + b]));
+  for (int c = 0; c < 3; ++c) fix_add(a.vb[c] + v, to_fix(vown[c], sscale[7 + c]));
 }
 
 // ------------------------------------------------------ initial condition

@@ -116,10 +116,10 @@ def _brick_boxes(X, n, bx=16, by=4, bz=4):
 def test_adjoint_with_a_large_shear_velocity():
     """A divergence-free shear displacement history of up to 2.5 cells per step
     (v_y varies with x and z, v_z with x and y): in most bricks of arrival
-    voxels the stencils spread over more nodes than the transposed
-    interpolation's LDS tile (2048) holds, and the scatter takes the
-    direct-atomic path; in the others, the tile path.  Both must match the
-    oracle."""
+    voxels the stencils spread over more nodes than the adjoint transport's
+    LDS tile (2048) holds, and the gathers read global memory and the scatter
+    takes the direct-atomic path; in the others, the tile paths.  Both must
+    match the oracle."""
     from oracle import transport
     from oracle.spectral import Grid
     steps = 2
