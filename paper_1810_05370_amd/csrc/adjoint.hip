@@ -223,11 +223,6 @@ __global__ void k_force_adj(long long V, double zeta, const double* p, const dou
   W[v] = -zeta * t * y[v];
 }
 
-__global__ void k_acc_prod(long long V, double coef, const double* x, const double* y, double* out) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < V) out[v] += coef * x[v] * y[v];
-}
-
 __global__ void k_axpy(long long V, double coef, const double* x, double* out) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < V) out[v] += coef * x[v];
@@ -811,9 +806,6 @@ void launch_s0_adj(const S0AdjArgs& a, hipStream_t st) {
 void launch_force_adj(long long V, double zeta, const double* p, const double* n, const double* gtau,
                       const double* y, double* taub, double* W, hipStream_t st) {
   hipLaunchKernelGGL(k_force_adj, dim3(pw_blocks(V)), dim3(256), 0, st, V, zeta, p, n, gtau, y, taub, W);
-}
-void launch_acc_prod(long long V, double coef, const double* x, const double* y, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_acc_prod, dim3(pw_blocks(V)), dim3(256), 0, st, V, coef, x, y, out);
 }
 void launch_axpy(long long V, double coef, const double* x, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_axpy, dim3(pw_blocks(V)), dim3(256), 0, st, V, coef, x, out);

@@ -68,7 +68,6 @@ void launch_coef_adj(const CoefAdjArgs& a, hipStream_t st);
 void launch_s0_adj(const S0AdjArgs& a, hipStream_t st);
 void launch_force_adj(long long V, double zeta, const double* p, const double* n, const double* gtau,
                       const double* y, double* taub, double* W, hipStream_t st);
-void launch_acc_prod(long long V, double coef, const double* x, const double* y, double* out, hipStream_t st);
 void launch_axpy(long long V, double coef, const double* x, double* out, hipStream_t st);
 void launch_xpay(long long V, const double* x, double coef, const double* y, double* out, hipStream_t st);
 // Transposed transport: bounds pass, scatter into 64-bit fixed-point

@@ -349,6 +349,53 @@ constexpr ColTerm T1(int s, double c = 1.0) { return ColTerm{s, SYM_ONE, c}; }
 constexpr ColTerm TW(int s, double c = 1.0) { return ColTerm{s, SYM_IW, c}; }
 constexpr ColTerm TR(int s, double c = 1.0) { return ColTerm{s, SYM_RAW, c}; }
 
+// One factor of a physical-space product: C2R of a sum of terms.
+struct Fac {
+  int n = 0;
+  ColTerm t[tumor::kMaxTerms];
+};
+Fac fac(std::initializer_list<ColTerm> terms) {
+  Fac f;
+  for (const ColTerm& x : terms) {
+    if (f.n == tumor::kMaxTerms) throw std::logic_error("fac: too many terms");
+    f.t[f.n++] = x;
+  }
+  return f;
+}
+
+// Builder of a physical-product x pass (XDotArgs).
+struct DotProg {
+  tumor::XDotArgs a;
+  DotProg() { std::memset(&a, 0, sizeof(a)); }
+  DotProg& in(int k, const void* ptr) {
+    a.in[k] = ptr;
+    return *this;
+  }
+  // a new output: dst = (accumulate: dst +=) the products added after it
+  DotProg& out(double* dst, bool accumulate = false) {
+    if (a.nout == tumor::kMaxDotOut) throw std::logic_error("DotProg: too many outputs");
+    const int o = a.nout++;
+    a.out[o] = dst;
+    a.accumulate[o] = accumulate ? 1 : 0;
+    return *this;
+  }
+  // coef * C2R(fa) * C2R(fb) into the last output (fb empty: coef * C2R(fa))
+  DotProg& prod(double coef, const Fac& fa, const Fac& fb = Fac()) {
+    const int o = a.nout - 1;
+    if (o < 0 || a.nprod[o] == tumor::kMaxDotProd) throw std::logic_error("DotProg: too many products");
+    const int d = a.nprod[o]++;
+    a.coef[o][d] = coef;
+    put(a.fa[o][d], fa);
+    put(a.fb[o][d], fb);
+    return *this;
+  }
+  static void put(tumor::XFactor& f, const Fac& src) {
+    f.nterm = src.n;
+    for (int q = 0; q < src.n; ++q)
+      f.term[q] = tumor::DotTerm{(short)src.t[q].src, (short)src.t[q].sym, (float)src.t[q].coef};
+  }
+};
+
 // Krylov work fused into an operator apply (see ZPUpdateArgs / ColProg.dsv).
 struct Fuse {
   bool pupdate;  // first pass: x += alpha p, p = M^-1 r + beta p (in place) before transforming p
@@ -1230,19 +1277,6 @@ void load_state(Ctx& c, const double* slot) {
   refresh_state(c);
 }
 
-// out = G_a in1 + G_b in2 (physical, FP64), derivatives along a, b (0, 1, 2 = x, y, z).
-void inv3_sum(Ctx& c, const cplx<double>* in1, int a, const cplx<double>* in2, int b, double* out) {
-  PrecBufs<double>& P = c.p64;
-  colp<double>(c, 2, true, Prog().in(0, in1).in(1, in2).out(P.A[0], {a == 2 ? TW(0) : T1(0)}).out(
-                                P.A[1], {b == 2 ? TW(1) : T1(1)}));
-  colp<double>(c, 1, true,
-               Prog().in(0, P.A[0]).in(1, P.A[1]).out(P.B[0], {a == 1 ? TW(0) : T1(0)}).out(
-                   P.B[1], {b == 1 ? TW(1) : T1(1)}));
-  Prog x;
-  x.in(0, P.B[0]).in(1, P.B[1]).out(out, {a == 0 ? TW(0) : T1(0), b == 0 ? TW(1) : T1(1)});
-  tumor::launch_xinv<double>(c.n, to_x(x.p, 1.0 / (double)c.V), P.tw, c.st);
-}
-
 void zero(Ctx& c, double* p, long long count) {
   HIPCHECK(hipMemsetAsync(p, 0, count * sizeof(double), c.st));
 }
@@ -1283,12 +1317,113 @@ void cn_adjoint(Ctx& c, const double* cbar_plus, double* out, const double* cm, 
   PrecBufs<double>& P = c.p64;
   diff_apply<double>(c, c.Un, P.q, 1.0, h, nullptr);
   inv3<double>(c, P.q, out, 1.0 / (double)c.V);
-  fwd3<double>(c, cm, cp, P.r);  // spectrum of c- + c+
-  for (int a = 0; a < 3; ++a) {
-    inv3<double>(c, c.Un, c.T[0], 1.0 / (double)c.V, a);
-    inv3<double>(c, P.r, c.T[1], 1.0 / (double)c.V, a);
-    tumor::launch_acc_prod(c.V, -h, c.T[0], c.T[1], c.KB, c.st);
+  fwd3<double>(c, cm, cp, P.r);  // spectrum of s = c- + c+
+  // z and y inverse passes of y and s, then the three products on the x pass
+  colp<double>(c, 2, true,
+               Prog().in(0, c.Un).in(1, P.r).out(P.A[0], {T1(0)}).out(P.A[1], {TW(0)}).out(P.A[2], {T1(1)}).out(
+                   P.A[3], {TW(1)}));
+  colp<double>(c, 1, true,
+               Prog()
+                   .in(0, P.A[0]).in(1, P.A[1]).in(2, P.A[2]).in(3, P.A[3])
+                   .out(P.B[0], {T1(0)}).out(P.B[1], {TW(0)}).out(P.B[2], {T1(1)})
+                   .out(P.B[3], {T1(2)}).out(P.B[4], {TW(2)}).out(P.B[5], {T1(3)}));
+  const double iV = 1.0 / (double)c.V, cf = -h * iV * iV;
+  DotProg d;
+  for (int k = 0; k < 6; ++k) d.in(k, P.B[k]);
+  d.out(c.KB, true)
+      .prod(cf, fac({TW(0)}), fac({TW(3)}))
+      .prod(cf, fac({T1(1)}), fac({T1(4)}))
+      .prod(cf, fac({T1(2)}), fac({T1(5)}));
+  tumor::launch_xdot<double>(c.n, d.a, P.tw, c.st);
+}
+
+// Coefficient sensitivities of the elasticity adjoint (Eqs. e:hook,
+// e:variable_elasticity, e:screening) from y (spectral, in Un) and u (in U):
+//   EB = -sum_a y_a u_a,  LB = -div y div u,  MB = -1/2 sum_ab S^y_ab S^u_ab,
+// S_ab = G_b v_a + G_a v_b, and the physical y_a in Y[a].  The z and y inverse
+// passes of each field leave eight partial transforms (v_x, v_y, v_z, dy v_x,
+// dy v_y, dz v_x, dz v_z, dz v_y + dy v_z); one x pass forms every product.
+void elast_sens(Ctx& c) {
+  PrecBufs<double>& P = c.p64;
+  const long long S = c.S;
+  cplx<double>* const part[2][8] = {{P.B[0], P.B[1], P.B[2], P.B[3], P.B[4], P.B[5], P.B[6], P.B[7]},
+                                     {P.r, P.r + S, P.r + 2 * S, P.p, P.p + S, P.p + 2 * S, P.q, P.q + S}};
+  for (int f = 0; f < 2; ++f) {
+    const cplx<double>* v = f == 0 ? c.Un : c.U;
+    colp<double>(c, 2, true,
+                 Prog()
+                     .in(0, v).in(1, v + S).in(2, v + 2 * S)
+                     .out(P.A[0], {T1(0)}).out(P.A[1], {T1(1)}).out(P.A[2], {T1(2)})
+                     .out(P.A[3], {TW(0)}).out(P.A[4], {TW(2)}).out(P.A[5], {TW(1)}));
+    cplx<double>* const* o = part[f];
+    colp<double>(c, 1, true,
+                 Prog()
+                     .in(0, P.A[0]).in(1, P.A[1]).in(2, P.A[2]).in(3, P.A[3]).in(4, P.A[4]).in(5, P.A[5])
+                     .out(o[0], {T1(0)}).out(o[1], {T1(1)}).out(o[2], {T1(2)})
+                     .out(o[3], {TW(0)}).out(o[4], {TW(1)})
+                     .out(o[5], {T1(3)}).out(o[6], {T1(4)}).out(o[7], {T1(5), TW(2)}));
   }
+  DotProg d;
+  for (int k = 0; k < 8; ++k) d.in(k, part[0][k]).in(8 + k, part[1][k]);
+  // factors of the field whose partial transforms start at input b
+  auto sxx = [](int b) { return fac({TW(b, 2.0)}); };
+  auto syy = [](int b) { return fac({T1(b + 4, 2.0)}); };
+  auto szz = [](int b) { return fac({T1(b + 6, 2.0)}); };
+  auto sxy = [](int b) { return fac({T1(b + 3), TW(b + 1)}); };
+  auto sxz = [](int b) { return fac({T1(b + 5), TW(b + 2)}); };
+  auto syz = [](int b) { return fac({T1(b + 7)}); };
+  auto dv = [](int b) { return fac({TW(b), T1(b + 4), T1(b + 6)}); };
+  auto val = [](int b, int a) { return fac({T1(b + a)}); };
+  const double iV = 1.0 / (double)c.V, iV2 = iV * iV;
+  d.out(c.MB)
+      .prod(-0.5 * iV2, sxx(0), sxx(8))
+      .prod(-0.5 * iV2, syy(0), syy(8))
+      .prod(-0.5 * iV2, szz(0), szz(8))
+      .prod(-iV2, sxy(0), sxy(8))
+      .prod(-iV2, sxz(0), sxz(8))
+      .prod(-iV2, syz(0), syz(8));
+  d.out(c.LB).prod(-iV2, dv(0), dv(8));
+  d.out(c.EB).prod(-iV2, val(0, 0), val(8, 0)).prod(-iV2, val(0, 1), val(8, 1)).prod(-iV2, val(0, 2), val(8, 2));
+  for (int a = 0; a < 3; ++a) d.out(c.Y[a]).prod(iV, val(0, a));
+  tumor::launch_xdot<double>(c.n, d.a, P.tw, c.st);
+}
+
+// Adjoint of the force b = zeta tanh(tau) G tau, tau = p' + n' (Eq. e:force),
+// with b_bar = -y: TB = sum_a [-zeta sech^2(tau) G_a tau y_a] - div W,
+// W_a = -zeta tanh(tau) y_a.  G tau comes from one inverse transform with three
+// outputs; div W from one forward transform that sums the three derivatives
+// and one inverse transform.
+void force_adj(Ctx& c) {
+  PrecBufs<double>& P = c.p64;
+  const long long V = c.V;
+  const double iV = 1.0 / (double)V;
+  enum { kP = 0, kN = 2 };  // p and n in F
+  fwd3<double>(c, c.F[kP], c.F[kN], P.r);  // spectrum of tau
+  colp<double>(c, 2, true, Prog().in(0, P.r).out(P.A[0], {T1(0)}).out(P.A[1], {TW(0)}));
+  colp<double>(c, 1, true, Prog().in(0, P.A[0]).in(1, P.A[1]).out(P.B[0], {T1(0)}).out(P.B[1], {TW(0)}).out(
+                               P.B[2], {T1(1)}));
+  Prog gx;
+  gx.in(0, P.B[0]).in(1, P.B[1]).in(2, P.B[2]).out(c.T[0], {TW(0)}).out(c.T[1], {T1(1)}).out(c.T[2], {T1(2)});
+  tumor::launch_xinv<double>(c.n, to_x(gx.p, iV), P.tw, c.st);
+  zero(c, c.TB, V);
+  // pointwise part; W_a replaces G_a tau in T[a]
+  for (int a = 0; a < 3; ++a)
+    tumor::launch_force_adj(V, c.prm.zeta, c.F[kP], c.F[kN], c.T[a], c.Y[a], c.TB, c.T[a], c.st);
+  Prog fx;
+  fx.in(0, c.T[0]).in(1, c.T[1]).in(2, c.T[2]).out(P.A[0], {T1(0)}).out(P.A[1], {T1(1)}).out(P.A[2], {T1(2)});
+  tumor::launch_xfwd<double>(c.n, to_x(fx.p, 1.0), P.tw, c.st, true);
+  // spectra of W_x and of dy W_y + dz W_z (the x derivative of W_x waits for the inverse x pass)
+  colp<double>(c, 1, false,
+               Prog().in(0, P.A[0]).in(1, P.A[1]).in(2, P.A[2]).out(P.B[0], {T1(0)}).out(P.B[1], {TW(1)}).out(
+                   P.B[2], {T1(2)}));
+  colp<double>(c, 2, false, Prog().in(0, P.B[0]).in(1, P.B[1]).in(2, P.B[2]).out(P.A[0], {T1(0)}).out(
+                                P.A[1], {T1(1), TW(2)}));
+  colp<double>(c, 2, true, Prog().in(0, P.A[0]).in(1, P.A[1]).out(P.B[0], {T1(0)}).out(P.B[1], {T1(1)}));
+  colp<double>(c, 1, true, Prog().in(0, P.B[0]).in(1, P.B[1]).out(P.A[0], {T1(0)}).out(P.A[1], {T1(1)}));
+  Prog dx;
+  dx.in(0, P.A[0]).in(1, P.A[1]).out(c.T[3], {TW(0), T1(1)});
+  tumor::launch_xinv<double>(c.n, to_x(dx.p, iV), P.tw, c.st);
+  tumor::launch_axpy(V, -1.0, c.T[3], c.TB, c.st);
 }
 
 // Reverse one recorded step.  On entry the forward step from X^m has just been
@@ -1308,38 +1443,8 @@ void adjoint_core(Ctx& c, const double* x0, double* adj, int m, double* grad) {
   // ---- S6 elasticity and force, S5 mixture
   if (c.flags & TUMOR_F_ELASTICITY) {
     adjoint_solve(c, 3, Lm[8], 7);  // y (spectral) in Un
-    zero(c, c.EB, V);
-    zero(c, c.MB, V);
-    zero(c, c.T[2], V);
-    zero(c, c.T[3], V);
-    for (int a = 0; a < 3; ++a) {
-      inv3<double>(c, c.Un + a * c.S, c.Y[a], iV);
-      inv3<double>(c, c.U + a * c.S, c.T[0], iV);
-      tumor::launch_acc_prod(V, -1.0, c.Y[a], c.T[0], c.EB, c.st);
-    }
-    for (int a = 0; a < 3; ++a) {
-      for (int b = a; b < 3; ++b) {
-        inv3_sum(c, c.Un + a * c.S, b, c.Un + b * c.S, a, c.T[0]);
-        inv3_sum(c, c.U + a * c.S, b, c.U + b * c.S, a, c.T[1]);
-        tumor::launch_acc_prod(V, a == b ? -0.5 : -1.0, c.T[0], c.T[1], c.MB, c.st);
-        if (a == b) {
-          tumor::launch_axpy(V, 0.5, c.T[0], c.T[2], c.st);
-          tumor::launch_axpy(V, 0.5, c.T[1], c.T[3], c.st);
-        }
-      }
-    }
-    zero(c, c.LB, V);
-    tumor::launch_acc_prod(V, -1.0, c.T[2], c.T[3], c.LB, c.st);
-    // force: tau = p' + n', b_bar = -y
-    zero(c, c.TB, V);
-    fwd3<double>(c, c.F[P], c.F[N], PB.r);
-    for (int a = 0; a < 3; ++a) {
-      inv3<double>(c, PB.r, c.T[0], iV, a);
-      tumor::launch_force_adj(V, c.prm.zeta, c.F[P], c.F[N], c.T[0], c.Y[a], c.TB, c.T[1], c.st);
-      fwd3<double>(c, c.T[1], nullptr, PB.p);
-      inv3<double>(c, PB.p, c.T[0], iV, a);
-      tumor::launch_axpy(V, -1.0, c.T[0], c.TB, c.st);
-    }
+    elast_sens(c);
+    force_adj(c);
     tumor::launch_axpy(V, 1.0, c.TB, Lm[P], c.st);
     tumor::launch_axpy(V, 1.0, c.TB, Lm[N], c.st);
     tumor::CoefAdjArgs ca;

@@ -112,6 +112,36 @@ struct XForceArgs {
   double zeta;
 };
 
+// Products in physical space on the x pass (the coefficient sensitivities of
+// the adjoint).  A factor is C2R( sum of up to kMaxTerms terms coef * s(kx) *
+// in[src] ) of packed rows after the y and z inverse passes; each output is
+//   out[o] (=, or += with accumulate) sum_d coef[o][d] * A_od * B_od,
+// with B_od = 1 when its factor has no terms.  Outputs are physical FP64.
+constexpr int kMaxDotIn = 16;
+constexpr int kMaxDotOut = 6;
+constexpr int kMaxDotProd = 6;
+// compact term (kernel arguments are limited to 4 KiB)
+struct DotTerm {
+  short src;
+  short sym;    // ColSym
+  float coef;   // small exact multipliers (1, 2)
+};
+struct XFactor {
+  int nterm;
+  DotTerm term[kMaxTerms];
+};
+struct XDotArgs {
+  const void* in[kMaxDotIn];
+  double* out[kMaxDotOut];
+  int nout;
+  int accumulate[kMaxDotOut];
+  int nprod[kMaxDotOut];
+  XFactor fa[kMaxDotOut][kMaxDotProd];
+  XFactor fb[kMaxDotOut][kMaxDotProd];
+  double coef[kMaxDotOut][kMaxDotProd];
+};
+static_assert(sizeof(XDotArgs) <= 3072, "kernel arguments are limited to 4 KiB");
+
 struct PassGeom {
   int n;
 };
@@ -132,5 +162,7 @@ template <typename R>
 void launch_xdiff(int n, const XDiffArgs& a, const void* tw, hipStream_t st);
 template <typename R>
 void launch_xforce(int n, const XForceArgs& a, const void* tw, hipStream_t st);
+template <typename R>
+void launch_xdot(int n, const XDotArgs& a, const void* tw, hipStream_t st);
 
 }  // namespace tumor

@@ -309,8 +309,8 @@ __device__ __forceinline__ void row_r2c(cplx<R> (&v)[8], const LdsRowView<R>& ld
 
 // Packed C2R: gathers sum_t coef * s_t(kx) * in_t at k and L-k, pre-processes,
 // inverse transforms; on return v[j] = N * (x[2p], x[2p+1]).
-template <typename R, int N, bool HALF = false>
-__device__ __forceinline__ void row_c2r_terms(cplx<R> (&v)[8], int nt, const ColTerm* terms,
+template <typename R, int N, bool HALF = false, typename Term>
+__device__ __forceinline__ void row_c2r_terms(cplx<R> (&v)[8], int nt, const Term* terms,
                                               const void* const* in, long long rowoff,
                                               const LdsRowView<R>& lds, int t,
                                               const cplx<R>* __restrict__ tw, int off = 0) {
@@ -321,7 +321,7 @@ __device__ __forceinline__ void row_c2r_terms(cplx<R> (&v)[8], int nt, const Col
     const int kp = (L - k) & (L - 1);
     cplx<R> A = czero<R>(), B = czero<R>();
     for (int q = 0; q < nt; ++q) {
-      const ColTerm tm = terms[q];
+      const Term tm = terms[q];
       const cplx<R>* __restrict__ src = static_cast<const cplx<R>*>(in[tm.src]) + rowoff;
       const R cf = R(tm.coef);
       cplx<R> a = src[off + k], b = src[off + kp];
@@ -645,6 +645,50 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xforce(XForceArgs a, con
   }
 }
 
+// Sums of products of inverse-transformed rows (XDotArgs), one output at a
+// time: each product's two factors are transformed in turn and multiplied
+// into a running sum, so two rows and the sum are live.
+template <typename R, int N>
+__global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdot(XDotArgs a, const cplx<R>* __restrict__ twg) {
+  TUMOR_ROW_SETUP(N)
+  // block-uniform bases and a 32-bit lane offset, as in k_xelast
+  const long long bs = (long long)blockIdx.x * RC::RW * L;
+  const int ro = rl * L;
+  for (int o = 0; o < a.nout; ++o) {
+    cplx<R> sum[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sum[j] = czero<R>();
+    for (int d = 0; d < a.nprod[o]; ++d) {
+      cplx<R> fa[8];
+      row_c2r_terms<R, N>(fa, a.fa[o][d].nterm, a.fa[o][d].term, a.in, bs, lds, t, tw, ro);
+      const R cf = R(a.coef[o][d]);
+      if (a.fb[o][d].nterm > 0) {
+        cplx<R> fb[8];
+        row_c2r_terms<R, N>(fb, a.fb[o][d].nterm, a.fb[o][d].term, a.in, bs, lds, t, tw, ro);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          sum[j].x += cf * fa[j].x * fb[j].x;
+          sum[j].y += cf * fa[j].y * fb[j].y;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          sum[j].x += cf * fa[j].x;
+          sum[j].y += cf * fa[j].y;
+        }
+      }
+    }
+    // physical rows hold N reals, read and written as L pairs
+    cplx<R>* __restrict__ dst = reinterpret_cast<cplx<R>*>(a.out[o]) + bs;
+    if (a.accumulate[o]) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sum[j] = cadd(sum[j], dst[ro + t + TP * j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dst[ro + t + TP * j] = sum[j];
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 #define TUMOR_DISPATCH_N(n, ...)                                                     \
   switch (n) {                                                                       \
@@ -734,6 +778,16 @@ void launch_xdiff(int n, const XDiffArgs& a, const void* tw, hipStream_t st) {
   TUMOR_DISPATCH_N(n, {
     dim3 grid((NN * NN) / RowCfg<NN>::RW);
     hipLaunchKernelGGL((k_xdiff<R, NN>), grid, dim3(RowCfg<NN>::THREADS), 0, st, a, twp);
+  });
+}
+
+template <typename R>
+void launch_xdot(int n, const XDotArgs& a, const void* tw, hipStream_t st) {
+  static_assert(sizeof(R) == sizeof(double), "the products are formed in FP64 (physical FP64 outputs)");
+  const cplx<R>* twp = static_cast<const cplx<R>*>(tw);
+  TUMOR_DISPATCH_N(n, {
+    dim3 grid((NN * NN) / RowCfg<NN>::RW);
+    hipLaunchKernelGGL((k_xdot<R, NN>), grid, dim3(RowCfg<NN>::THREADS), 0, st, a, twp);
   });
 }
 
