@@ -109,6 +109,7 @@ struct KTimer {
   double bytes;
   hipEvent_t ev[2 * kMaxPend];
   double pend_bytes[kMaxPend];
+  double pend_sys[kMaxPend];  // batched launches: bytes per system still iterating
   int pend_tag[kMaxPend];
 };
 
@@ -146,12 +147,13 @@ struct tumor_ctx {
   cplx<double>* b64;
   PrecBufs<double> p64;
   PrecBufs<float> p32;
-  tumor::SolveScalars* sv64;
+  tumor::SolveScalars* sv64;  // kMaxSys entries (one per system of a batched solve)
   tumor::SolveScalars* sv32;
+  int* bflag;                 // per-system skip flags of the batched FP64 applies
   tumor::CoefScalars* cs;
   double* partials;
   // host side
-  tumor::SolveScalars* hsv;
+  tumor::SolveScalars* hsv;  // kMaxSys entries
   tumor::CoefScalars* hcs;
   int pred[8];
   int pred_in[8][3];  // mixed precision: inner iterations of outer pass 0, 1, >= 2
@@ -161,6 +163,12 @@ struct tumor_ctx {
   tumor::ReactConsts rc;
   KTimer* timers[TUMOR_K_COUNT];
   int cur_tag;  // PCG iteration index of the launches being queued (-1 outside loops)
+  // batched solve in progress (timer accounting): a launch's bytes are split
+  // over bsys_total systems, of which bsys_active are computed outside the
+  // iterations; within them, a system counts while tag < batch_it[system]
+  int bsys_total, bsys_active;
+  int batch_ns;
+  int batch_it[tumor::kMaxSys];
   int static_dev;  // device of an allocation-free context (tumor_init_static), else -1
   // sub-step timer (tumor_substep_timer): events at the sub-step boundaries of
   // every step, elapsed times summed per sub-step after the step's final sync
@@ -179,11 +187,20 @@ void timer_flush(Ctx& c, int cls, int valid_tag) {
   if (!t || t->pending == 0) return;
   HIPCHECK(hipEventSynchronize(t->ev[2 * t->pending - 1]));
   for (int k = 0; k < t->pending; ++k) {
-    if (t->pend_tag[k] >= valid_tag) continue;  // launch skipped on the device (solve already done)
+    double bytes = t->pend_bytes[k];
+    if (t->pend_sys[k] > 0.0) {
+      // a batched launch within the iterations: the systems still iterating did work
+      int nact = 0;
+      for (int q = 0; q < c.batch_ns; ++q) nact += t->pend_tag[k] < c.batch_it[q] ? 1 : 0;
+      if (nact == 0) continue;
+      bytes += t->pend_sys[k] * nact;
+    } else if (t->pend_tag[k] >= valid_tag) {
+      continue;  // launch skipped on the device (solve already done)
+    }
     float ms = 0.f;
     HIPCHECK(hipEventElapsedTime(&ms, t->ev[2 * k], t->ev[2 * k + 1]));
     t->ms += ms;
-    t->bytes += t->pend_bytes[k];
+    t->bytes += bytes;
     t->launches += 1;
   }
   t->pending = 0;
@@ -193,9 +210,11 @@ void timers_flush(Ctx& c, int valid_tag) {
   for (int k = 0; k < TUMOR_K_COUNT; ++k) timer_flush(c, k, valid_tag);
 }
 
-// Launch f(), bracketed by events if the class is being timed.
+// Launch f(), bracketed by events if the class is being timed.  `fixed`
+// bytes, plus `per_sys` bytes for each system of a batched solve that the
+// launch computes.
 template <typename F>
-void timed(Ctx& c, int cls, double bytes, F&& f) {
+void timed_b(Ctx& c, int cls, double fixed, double per_sys, F&& f) {
   KTimer* t = c.timers[cls];
   if (!t || !t->on) {
     f();
@@ -205,9 +224,24 @@ void timed(Ctx& c, int cls, double bytes, F&& f) {
   HIPCHECK(hipEventRecord(t->ev[2 * t->pending], c.st));
   f();
   HIPCHECK(hipEventRecord(t->ev[2 * t->pending + 1], c.st));
-  t->pend_bytes[t->pending] = bytes;
+  if (c.cur_tag < 0) {
+    // outside the iterations the host knows which systems are computed
+    t->pend_bytes[t->pending] = fixed + per_sys * c.bsys_active;
+    t->pend_sys[t->pending] = 0.0;
+  } else {
+    t->pend_bytes[t->pending] = fixed;
+    t->pend_sys[t->pending] = per_sys;
+  }
   t->pend_tag[t->pending] = c.cur_tag < 0 ? -1 : c.cur_tag;
   t->pending++;
+}
+
+// Launch f() timed with `bytes`; within a batched apply (bsys_total > 0) the
+// bytes are those of all its systems, split evenly.
+template <typename F>
+void timed(Ctx& c, int cls, double bytes, F&& f) {
+  if (c.bsys_total > 0) timed_b(c, cls, 0.0, bytes / c.bsys_total, f);
+  else timed_b(c, cls, bytes, 0.0, f);
 }
 
 template <typename R>
@@ -280,10 +314,11 @@ void layout(Ctx& c, Carver& cv) {
     for (int k = 0; k < 3; ++k) c.VB[k] = cv.take<double>(V);
     c.gs = cv.take<tumor::GradScalars>(1);
   }
-  c.sv64 = cv.take<tumor::SolveScalars>(1);
-  c.sv32 = cv.take<tumor::SolveScalars>(1);
+  c.sv64 = cv.take<tumor::SolveScalars>(tumor::kMaxSys);
+  c.sv32 = cv.take<tumor::SolveScalars>(tumor::kMaxSys);
+  c.bflag = cv.take<int>(4);
   c.cs = cv.take<tumor::CoefScalars>(1);
-  c.partials = cv.take<double>((size_t)tumor::kRedBlocksMax * tumor::kPartialsPerBlock);
+  c.partials = cv.take<double>((size_t)tumor::kPartialsCount);
 }
 
 size_t workspace_size(const tumor_config& cfg) {
@@ -316,9 +351,10 @@ struct Prog {
     p.in[k] = ptr;
     return *this;
   }
-  Prog& out(void* dst, std::initializer_list<ColTerm> terms) {
+  Prog& out(void* dst, std::initializer_list<ColTerm> terms, const int* oskip = nullptr) {
     const int o = p.nout++;
     p.out[o] = dst;
+    p.oskip[o] = oskip;
     int q = 0;
     for (const ColTerm& t : terms) p.term[o][q++] = t;
     p.nterm[o] = q;
@@ -493,6 +529,7 @@ void diff_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, double raw, double dcoe
           Prog().in(0, P.A[0]).in(1, P.A[1]).out(P.B[0], {T1(0)}).out(P.B[1], {TW(0)}).out(P.B[2], {T1(1)}).skip(
               skip));
   tumor::XDiffArgs xa;
+  std::memset(&xa, 0, sizeof(xa));
   xa.in[0] = P.B[0];
   xa.in[1] = P.B[1];
   xa.in[2] = P.B[2];
@@ -500,7 +537,8 @@ void diff_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, double raw, double dcoe
   xa.out[1] = P.A[1];
   xa.out[2] = P.A[2];
   xa.K = P.K;
-  xa.skip = skip;
+  xa.skip[0] = skip;
+  xa.ns = 1;
   timed(c, kcls<R>(TUMOR_K_XDIFF64, TUMOR_K_XDIFF32), 7.0 * c.V * sizeof(R),
         [&] { tumor::launch_xdiff<R>(c.n, xa, P.tw, c.st); });
   colp<R>(c, 1, false,
@@ -860,6 +898,378 @@ SolveOut cn_solve(Ctx& c, const double* src, double* dst, int which) {
   return so;
 }
 
+// ------------------------------------------------ batched CN solves (i, o, l)
+// The Crank-Nicolson systems of the species share the operator (1 - dt/2 D_K)
+// and its preconditioner, so they are solved as one Krylov iteration over ns
+// blocks with per-system scalars and stopping rules (BatchArgs): each FFT
+// pass handles every system still iterating (K is read once), and one scalar
+// read-back serves all of them.  Each system's arithmetic, sums included, is
+// that of its own solve.
+
+template <typename R>
+tumor::BatchArgs bargs(Ctx& c, int ns, int active, cplx<R>* x, tumor::SolveScalars* sv, double h) {
+  PrecBufs<R>& P = pb<R>(c);
+  tumor::BatchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = x;
+  a.r = P.r;
+  a.p = P.p;
+  a.q = P.q;
+  a.cs = c.cs;
+  a.sv = sv;
+  a.partials = c.partials;
+  a.n = c.n;
+  a.ns = ns;
+  a.active = active;
+  a.pc.h = h;
+  a.pc.kind = tumor::PREC_DIFF;
+  for (int k = 0; k < tumor::kMaxSys; ++k) a.scale32[k] = 1.0;
+  return a;
+}
+
+// Krylov work fused into a batched apply (see ZPUpdateArgs.nsys, ColProg.dot_nsys).
+struct BFuse {
+  bool pupdate;
+  const void* r;
+  void* x;
+  tumor::SolveScalars* sv;  // ns entries
+  tumor::PrecConsts pc;
+};
+
+// Keeps the timers' batched-apply accounting set for a scope.
+struct BatchScope {
+  Ctx& c;
+  BatchScope(Ctx& cc, int total, int active) : c(cc) {
+    c.bsys_total = total;
+    c.bsys_active = active;
+  }
+  ~BatchScope() {
+    c.bsys_total = 0;
+    c.bsys_active = 0;
+  }
+};
+
+// out_k = raw * in_k + dcoef * D in_k (spectral) for the ns systems whose
+// skip flag is clear; D c = div(K grad c).  Pass buffers: the z inverse into
+// 0 .. 2ns-1, the y inverse into 6 .. 6+3ns-1, the x pass in place, the y
+// forward into 0 .. 2ns-1.
+template <typename R>
+void diff_apply_b(Ctx& c, int ns, const cplx<R>* in, cplx<R>* out, double raw, double dcoef,
+                  const int* const* skip, const BFuse* fz = nullptr) {
+  PrecBufs<R>& P = pb<R>(c);
+  cplx<R>* buf[16];
+  for (int k = 0; k < 8; ++k) {
+    buf[k] = P.A[k];
+    buf[8 + k] = P.B[k];
+  }
+  const long long S = c.S;
+  if (fz && fz->pupdate) {
+    tumor::ZPUpdateArgs za;
+    std::memset(&za, 0, sizeof(za));
+    za.r = fz->r;
+    za.p = const_cast<cplx<R>*>(in);
+    za.x = fz->x;
+    for (int k = 0; k < 2 * ns; ++k) za.out[k] = buf[k];
+    za.sv = fz->sv;
+    za.cs = c.cs;
+    za.pc = fz->pc;
+    za.nsys = ns;
+    timed(c, kcls<R>(TUMOR_K_ZINVP64_1, TUMOR_K_ZINVP32_1), 7.0 * ns * double(c.V) * sizeof(R),
+          [&] { tumor::launch_zinv_pupdate<R>(c.n, 1, za, P.tw, c.st); });
+  } else {
+    Prog z;
+    for (int k = 0; k < ns; ++k) z.in(k, in + k * S).out(buf[2 * k], {T1(k)}, skip[k]).out(buf[2 * k + 1], {TW(k)}, skip[k]);
+    colp<R>(c, 2, true, z);
+  }
+  Prog y;
+  for (int k = 0; k < ns; ++k)
+    y.in(2 * k, buf[2 * k])
+        .in(2 * k + 1, buf[2 * k + 1])
+        .out(buf[6 + 3 * k], {T1(2 * k)}, skip[k])
+        .out(buf[7 + 3 * k], {TW(2 * k)}, skip[k])
+        .out(buf[8 + 3 * k], {T1(2 * k + 1)}, skip[k]);
+  colp<R>(c, 1, true, y);
+  tumor::XDiffArgs xa;
+  std::memset(&xa, 0, sizeof(xa));
+  for (int e = 0; e < 3 * ns; ++e) xa.in[e] = xa.out[e] = buf[6 + e];
+  for (int k = 0; k < ns; ++k) xa.skip[k] = skip[k];
+  xa.K = P.K;
+  xa.ns = ns;
+  // K once, then three rows in and three out per system
+  timed_b(c, kcls<R>(TUMOR_K_XDIFF64, TUMOR_K_XDIFF32), double(c.V) * sizeof(R), 6.0 * double(c.V) * sizeof(R),
+          [&] { tumor::launch_xdiff<R>(c.n, xa, P.tw, c.st); });
+  Prog yf;
+  for (int k = 0; k < ns; ++k)
+    yf.in(3 * k, buf[6 + 3 * k])
+        .in(3 * k + 1, buf[7 + 3 * k])
+        .in(3 * k + 2, buf[8 + 3 * k])
+        .out(buf[2 * k], {T1(3 * k), TW(3 * k + 1)}, skip[k])
+        .out(buf[2 * k + 1], {T1(3 * k + 2)}, skip[k]);
+  colp<R>(c, 1, false, yf);
+  Prog zf;
+  for (int k = 0; k < ns; ++k) {
+    zf.in(3 * k, buf[2 * k]).in(3 * k + 1, buf[2 * k + 1]).in(3 * k + 2, in + k * S);
+    // the untransformed term last: the inner-product pass takes p from it
+    if (raw != 0.0)
+      zf.out(out + k * S, {T1(3 * k, dcoef), TW(3 * k + 1, dcoef), TR(3 * k + 2, raw)}, skip[k]);
+    else
+      zf.out(out + k * S, {T1(3 * k, dcoef), TW(3 * k + 1, dcoef)}, skip[k]);
+  }
+  if (fz) {
+    for (int k = 0; k < ns; ++k) zf.p.dotp[k] = in + k * S;
+    zf.p.dsv = fz->sv;
+    zf.p.dpart = c.partials;
+    zf.p.dot_nsys = ns;
+  }
+  colp<R>(c, 2, false, zf);
+}
+
+// Batched PCG iterations after the residuals and norms are in place, for
+// the systems in `active`; per system thr2, limit, fixed and pred.  Chunked
+// between read-backs like pcg_iterate, on the slowest system's prediction.
+template <typename R>
+void pcg_iterate_b(Ctx& c, tumor::BatchArgs a, const double* thr2, const int* limit, const bool* fixed,
+                   const int* pred, int zero_x, const double* rr0, int* its, bool* conv, bool* bad) {
+  const int ns = a.ns;
+  int lim_max = 0, chunk = 1;
+  bool any_fixed = false;
+  for (int k = 0; k < ns; ++k) {
+    a.thr2[k] = thr2[k];
+    a.limit[k] = limit[k];
+    a.fixed[k] = fixed[k] ? 1 : 0;
+    its[k] = 0;
+    conv[k] = true;
+    bad[k] = false;
+    if (!(a.active & (1 << k))) continue;
+    lim_max = std::max(lim_max, limit[k]);
+    any_fixed = any_fixed || fixed[k];
+    chunk = std::max(chunk, std::min(limit[k], pred[k] + 1));
+  }
+  if (any_fixed) chunk = std::min(lim_max, 64);
+  const int kc = kcls<R>(TUMOR_K_KRYLOV64, TUMOR_K_KRYLOV32);
+  const double vb = double(c.V) * sizeof(R);  // one system's Krylov vector
+  const int nact = __builtin_popcount((unsigned)a.active);
+  timed(c, kc, (zero_x ? 3.0 : 2.0) * vb * nact, [&] { tumor::launch_bpcg_start<R>(a, zero_x, c.st); });
+  const int* skip[tumor::kMaxSys] = {};
+  for (int k = 0; k < ns; ++k) skip[k] = &a.sv[k].done;
+  {
+  BatchScope scope(c, ns, nact);
+  c.batch_ns = ns;
+  int launched = 0;
+  for (;;) {
+    for (int i = 0; i < chunk && launched < lim_max; ++i, ++launched) {
+      c.cur_tag = launched;
+      BFuse fz{launched > 0, a.r, a.x, a.sv, a.pc};
+      diff_apply_b<R>(c, ns, static_cast<const cplx<R>*>(a.p), static_cast<cplx<R>*>(a.q), 1.0, -a.pc.h, skip,
+                      &fz);
+      timed_b(c, kc, 0.0, 3.0 * vb, [&] { tumor::launch_bpcg_update<R>(a, c.st); });
+    }
+    c.cur_tag = -1;
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(c.hsv, a.sv, ns * sizeof(tumor::SolveScalars), hipMemcpyDeviceToHost, c.st));
+    HIPCHECK(hipStreamSynchronize(c.st));
+    bool all_done = true;
+    int left = 0;
+    for (int k = 0; k < ns; ++k) {
+      c.batch_it[k] = (a.active & (1 << k)) ? c.hsv[k].it : 0;
+      if (!(a.active & (1 << k)) || c.hsv[k].done) continue;
+      all_done = false;
+      // the remaining iterations the residual reduction of this system predicts
+      int more = 4;
+      const double rr = c.hsv[k].rr;
+      const int it = c.hsv[k].it;
+      if (fixed[k]) {
+        more = limit[k] - it;
+      } else if (rr0[k] > 0.0 && it > 0 && rr > thr2[k] && rr < rr0[k] && std::isfinite(rr)) {
+        const double per_it = std::log(rr / rr0[k]) / it;
+        const double rest = std::log(thr2[k] / rr) / per_it;
+        if (std::isfinite(rest)) more = std::max(1, std::min(32, (int)std::ceil(rest) + 1));
+      }
+      left = std::max(left, std::min(more, limit[k] - it));
+    }
+    timers_flush(c, 0x7fffffff);
+    if (all_done || launched >= lim_max) break;
+    chunk = std::max(1, std::min(left, any_fixed ? 64 : 32));
+  }
+  c.batch_ns = 0;
+  }
+  timed(c, kc, 3.0 * vb * nact, [&] { tumor::launch_bpcg_xfinal<R>(a, c.st); });
+  for (int k = 0; k < ns; ++k) {
+    if (!(a.active & (1 << k))) continue;
+    its[k] = c.hsv[k].it;
+    conv[k] = c.hsv[k].conv != 0;
+    bad[k] = c.hsv[k].bad != 0;
+  }
+}
+
+// Crank-Nicolson diffusion of ns physical fields src[k] into dst[k] (may
+// alias), which[k] = solve slot (iteration predictions, forced counts).
+void cn_solve_b(Ctx& c, int ns, const double* const* src, double* const* dst, const int* which, SolveOut* so) {
+  const double h = 0.5 * c.cfg.dt;
+  const long long S = c.S;
+  const int all = (1 << ns) - 1;
+  cplx<double>* x = c.Un;  // ns blocks; free between elasticity solves
+  for (int k = 0; k < ns; ++k) {
+    so[k] = SolveOut();
+    fwd3<double>(c, src[k], nullptr, x + k * S);
+  }
+  PrecBufs<double>& P = c.p64;
+  tumor::BatchArgs a = bargs<double>(c, ns, all, x, c.sv64, h);
+  a.b = c.b64;
+  const int* flag[tumor::kMaxSys] = {};
+  for (int k = 0; k < ns; ++k) flag[k] = c.bflag + k;
+  auto apply64 = [&](int mask, const cplx<double>* in, cplx<double>* out, double raw, double dcoef) {
+    BatchScope scope(c, ns, __builtin_popcount((unsigned)mask));
+    tumor::launch_set_flags(c.bflag, ns, mask, c.st);
+    diff_apply_b<double>(c, ns, in, out, raw, dcoef, flag);
+  };
+  // D x0 for every system, then b = x0 + h D x0 and r = b - (x0 - h D x0)
+  apply64(all, x, P.q, 0.0, 1.0);
+  timed(c, TUMOR_K_KRYLOV64, 4.0 * ns * c.V * 8.0, [&] { tumor::launch_bcn_residual<double>(a, x, P.q, c.st); });
+  HIPCHECK(hipMemcpyAsync(c.hsv, c.sv64, ns * sizeof(tumor::SolveScalars), hipMemcpyDeviceToHost, c.st));
+  HIPCHECK(hipStreamSynchronize(c.st));
+  double bb[tumor::kMaxSys], rr[tumor::kMaxSys], thr2[tumor::kMaxSys];
+  int forced[tumor::kMaxSys];
+  int active = 0;
+  for (int k = 0; k < ns; ++k) {
+    bb[k] = c.hsv[k].bb;
+    rr[k] = c.hsv[k].rr;
+    thr2[k] = c.cfg.rtol_diff * c.cfg.rtol_diff * bb[k];
+    forced[k] = (c.has_forced && which[k] >= 0 && which[k] < 4) ? c.forced[which[k]] : -1;
+    if (c.hsv[k].bad) {
+      so[k].bad = true;
+      so[k].conv = false;
+    } else if (bb[k] == 0.0) {
+      HIPCHECK(hipMemsetAsync(x + k * S, 0, S * sizeof(cplx<double>), c.st));
+    } else if (forced[k] < 0 && rr[k] <= thr2[k]) {
+      so[k].relres = std::sqrt(rr[k] / bb[k]);
+    } else {
+      active |= 1 << k;
+    }
+  }
+  if (!c.mixed) {
+    int limit[tumor::kMaxSys], pred[tumor::kMaxSys], its[tumor::kMaxSys];
+    bool fixed[tumor::kMaxSys], conv[tumor::kMaxSys], bad[tumor::kMaxSys];
+    for (int k = 0; k < ns; ++k) {
+      fixed[k] = forced[k] >= 0;
+      limit[k] = fixed[k] ? forced[k] : c.cfg.max_it;
+      pred[k] = c.pred[which[k]];
+      if ((active & (1 << k)) && limit[k] <= 0) {
+        // no iterations (a forced count of zero)
+        active &= ~(1 << k);
+        so[k].relres = std::sqrt(rr[k] / bb[k]);
+        c.pred[which[k]] = 1;
+      }
+    }
+    if (active) {
+      tumor::BatchArgs ai = a;
+      ai.active = active;
+      pcg_iterate_b<double>(c, ai, thr2, limit, fixed, pred, 0, rr, its, conv, bad);
+      for (int k = 0; k < ns; ++k) {
+        if (!(active & (1 << k))) continue;
+        so[k].it = its[k];
+        so[k].conv = conv[k];
+        so[k].bad = bad[k];
+        so[k].relres = std::sqrt(c.hsv[k].rr / bb[k]);
+        c.pred[which[k]] = std::max(1, its[k]);
+      }
+    }
+  } else {
+    // x64 += PCG32(b - A64 x64) per system until its FP64 residual meets rtol
+    PrecBufs<float>& Q = c.p32;
+    tumor::BatchArgs a32 = bargs<float>(c, ns, 0, Q.x, c.sv32, h);
+    const long long cnt = 2LL * S;  // reals per system
+    const int max_outer = 30;
+    int total[tumor::kMaxSys] = {0, 0, 0};
+    while (active) {
+      double sc[tumor::kMaxSys] = {1.0, 1.0, 1.0}, thr_in[tumor::kMaxSys], rr_in[tumor::kMaxSys];
+      int limit[tumor::kMaxSys], pred[tumor::kMaxSys], its[tumor::kMaxSys];
+      bool fixed[tumor::kMaxSys] = {false, false, false}, conv[tumor::kMaxSys], bad[tumor::kMaxSys];
+      tumor::BatchArgs cv = a;  // r32 = float(scale * r64), r64 unchanged
+      cv.b = a.r;
+      cv.ax = nullptr;
+      cv.active = active;
+      for (int k = 0; k < ns; ++k) {
+        limit[k] = c.cfg.max_it;
+        thr_in[k] = 0.0;
+        rr_in[k] = 0.0;
+        pred[k] = 1;
+        if (!(active & (1 << k))) continue;
+        const double rms = std::sqrt(rr[k] / double(cnt));
+        sc[k] = (rms > 0.0 && std::isfinite(rms)) ? std::ldexp(1.0, -std::ilogb(rms)) : 1.0;
+        const double need = c.cfg.rtol_diff * std::sqrt(bb[k] / rr[k]);
+        const double in_rtol = std::max(1e-4, 0.3 * need);
+        thr_in[k] = in_rtol * in_rtol * rr[k] * sc[k] * sc[k];
+        rr_in[k] = rr[k] * sc[k] * sc[k];
+        pred[k] = c.pred_in[which[k]][std::min(so[k].outer, 2)];
+        cv.scale32[k] = sc[k];
+      }
+      timed(c, TUMOR_K_KRYLOV64, __builtin_popcount((unsigned)active) * c.V * (16.0 + 4.0),
+            [&] { tumor::launch_bresidual<double>(cv, Q.r, c.st); });
+      tumor::BatchArgs ai = a32;
+      ai.active = active;
+      pcg_iterate_b<float>(c, ai, thr_in, limit, fixed, pred, 1, rr_in, its, conv, bad);
+      double inv_sc[tumor::kMaxSys] = {1.0, 1.0, 1.0};
+      int stop = 0;
+      for (int k = 0; k < ns; ++k) {
+        if (!(active & (1 << k))) continue;
+        if (conv[k]) c.pred_in[which[k]][std::min(so[k].outer, 2)] = std::max(1, its[k]);
+        total[k] += its[k];
+        so[k].outer++;
+        inv_sc[k] = 1.0 / sc[k];
+        if (bad[k]) {
+          so[k].bad = true;
+          so[k].conv = false;
+          stop |= 1 << k;
+        } else if (!conv[k] && its[k] >= c.cfg.max_it) {
+          stop |= 1 << k;  // the correction is still added; the FP64 residual decides conv
+        }
+      }
+      // every system that ran without a breakdown adds its correction
+      int add = 0;
+      for (int k = 0; k < ns; ++k)
+        if ((active & (1 << k)) && !so[k].bad) add |= 1 << k;
+      tumor::launch_badd32to64(x, Q.x, inv_sc, ns, add, cnt, c.st);
+      // r64 = b - A64 x64 for the systems that added a correction
+      if (add) {
+        apply64(add, x, P.q, 1.0, -h);
+        tumor::BatchArgs ar = a;
+        ar.b = c.b64;
+        ar.ax = P.q;
+        ar.active = add;
+        timed(c, TUMOR_K_KRYLOV64, 3.0 * __builtin_popcount((unsigned)add) * c.V * 8.0,
+              [&] { tumor::launch_bresidual<double>(ar, nullptr, c.st); });
+        HIPCHECK(hipMemcpyAsync(c.hsv, c.sv64, ns * sizeof(tumor::SolveScalars), hipMemcpyDeviceToHost, c.st));
+        HIPCHECK(hipStreamSynchronize(c.st));
+      }
+      int next = 0;
+      for (int k = 0; k < ns; ++k) {
+        if (!(active & (1 << k))) continue;
+        if (so[k].bad) continue;
+        rr[k] = c.hsv[k].rr;
+        if (c.hsv[k].bad) {
+          so[k].bad = true;
+          so[k].conv = false;
+          continue;
+        }
+        if (rr[k] <= thr2[k]) continue;                // converged
+        if (stop & (1 << k)) continue;                 // inner limit reached without convergence
+        if (so[k].outer >= max_outer) continue;
+        next |= 1 << k;
+      }
+      active = next;
+    }
+    for (int k = 0; k < ns; ++k) {
+      if (so[k].outer == 0) continue;
+      so[k].it = total[k];
+      so[k].relres = std::sqrt(rr[k] / bb[k]);
+      so[k].conv = !so[k].bad && rr[k] <= thr2[k];
+      c.pred[which[k]] = std::max(1, total[k] / std::max(1, so[k].outer));
+    }
+  }
+  for (int k = 0; k < ns; ++k) inv3<double>(c, x + k * S, dst[k], 1.0 / (double)c.V);
+}
+
 // Elasticity solve (eta - L) u = rhs, rhs spectral in b64, warm start from U.
 SolveOut elast_solve(Ctx& c, cplx<double>* x, int which) {
   HIPCHECK(hipMemcpyAsync(x, c.U, 3 * c.S * sizeof(cplx<double>), hipMemcpyDeviceToDevice, c.st));
@@ -1081,11 +1491,15 @@ void do_step(Ctx& c, tumor_step_stats* stats, int& status) {
     double* out[8] = {c.F[P], c.F[I], c.F[N], c.F[G], c.F[W], c.F[O], c.F[L], c.F[F]};
     refresh(c, 1, in, out);
   } else {
-  // S2: Crank-Nicolson diffusion of i, o (and l).
-  sd[0] = cn_solve(c, c.G[I], c.Rdd[0], 0);
-  sd[1] = cn_solve(c, c.F[O], c.Rdd[1], 1);
-  if (c.flags & TUMOR_F_EDEMA) sd[2] = cn_solve(c, c.F[L], c.Rdd[2], 2);
-  else HIPCHECK(hipMemcpyAsync(c.Rdd[2], c.F[L], c.V * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+  // S2: Crank-Nicolson diffusion of i, o (and l), one batched solve.
+  {
+    const double* src[3] = {c.G[I], c.F[O], c.F[L]};
+    double* dst[3] = {c.Rdd[0], c.Rdd[1], c.Rdd[2]};
+    const int which[3] = {0, 1, 2};
+    cn_solve_b(c, (c.flags & TUMOR_F_EDEMA) ? 3 : 2, src, dst, which, sd);
+  }
+  if (!(c.flags & TUMOR_F_EDEMA))
+    HIPCHECK(hipMemcpyAsync(c.Rdd[2], c.F[L], c.V * sizeof(double), hipMemcpyDeviceToDevice, c.st));
   substep_mark(c, 2);
   // S3-S5: reaction, oxygen, edema, refresh.
   {
@@ -1685,8 +2099,8 @@ int init_context(Ctx* c, const tumor_config* cfg, const tumor_params* prm, void*
     c->cur_tag = -1;
     set_consts(*c);
     twiddles(*c);
-    HIPCHECK(hipMemsetAsync(c->sv64, 0, sizeof(tumor::SolveScalars), c->st));
-    HIPCHECK(hipMemsetAsync(c->sv32, 0, sizeof(tumor::SolveScalars), c->st));
+    HIPCHECK(hipMemsetAsync(c->sv64, 0, tumor::kMaxSys * sizeof(tumor::SolveScalars), c->st));
+    HIPCHECK(hipMemsetAsync(c->sv32, 0, tumor::kMaxSys * sizeof(tumor::SolveScalars), c->st));
     HIPCHECK(hipMemsetAsync(c->cs, 0, sizeof(tumor::CoefScalars), c->st));
     enum { P, I, N, O, L, G, W, F };
     const size_t fb = V * sizeof(double);
@@ -1728,7 +2142,7 @@ struct StaticSlot {
   void* ws;      // device address of `scratch` on this device (null until looked up)
   bool in_use;   // a live context holds the array
   tumor_ctx ctx;
-  tumor::SolveScalars hsv;
+  tumor::SolveScalars hsv[tumor::kMaxSys];
   tumor::CoefScalars hcs;
   double ic[5 * kStaticMaxIC + 1];
 };
@@ -1763,7 +2177,7 @@ int tumor_init(tumor_ctx** out, const tumor_config* cfg, const tumor_params* prm
   c->ic_host = new (std::nothrow) double[5 * (size_t)n_ic + 1];
   void* h1 = nullptr;
   void* h2 = nullptr;
-  if (c->ic_host && hipHostMalloc(&h1, sizeof(tumor::SolveScalars), hipHostMallocDefault) == hipSuccess &&
+  if (c->ic_host && hipHostMalloc(&h1, tumor::kMaxSys * sizeof(tumor::SolveScalars), hipHostMallocDefault) == hipSuccess &&
       hipHostMalloc(&h2, sizeof(tumor::CoefScalars), hipHostMallocDefault) == hipSuccess) {
     c->hsv = static_cast<tumor::SolveScalars*>(h1);
     c->hcs = static_cast<tumor::CoefScalars*>(h2);
@@ -1822,7 +2236,7 @@ int tumor_init_static(tumor_ctx** out, const tumor_config* cfg, const tumor_para
   tumor_ctx* c = &s.ctx;
   std::memset(c, 0, sizeof(*c));
   c->static_dev = dev;
-  c->hsv = &s.hsv;
+  c->hsv = s.hsv;
   c->hcs = &s.hcs;
   c->ic_host = s.ic;
   rc = init_context(c, cfg, prm, s.ws, wm, gm, csf, n_ic, ic_centers, ic_sigmas, ic_weights, hip_stream);

@@ -11,6 +11,14 @@ namespace tumor {
 constexpr int kRedThreads = 256;
 constexpr int kRedBlocksMax = 1024;
 constexpr int kPartialsPerBlock = 16;
+// The partials buffer: kRedBlocksMax blocks of kPartialsPerBlock for the
+// reductions, or up to kPartialsCount / kDotStride blocks of an FFT pass with
+// one inner-product partial per batched system.
+constexpr int kDotStride = 4;
+constexpr int kPartialsCount = 65536;
+static_assert(kPartialsCount >= kRedBlocksMax * kPartialsPerBlock, "partials buffer");
+// Independent systems of a batched solve (the CN solves of i, o and l).
+constexpr int kMaxSys = 3;
 
 // Device scalars of one PCG solve.  Written by a one-block totalling kernel
 // (k_fin_*) from the reduction kernels' per-block partials, read by the
@@ -149,7 +157,43 @@ void launch_pcg_xfinal(const KrylovArgs& a, hipStream_t st);
 // out = M^-1 in (one application of the preconditioner)
 template <typename R>
 void launch_precond(const KrylovArgs& a, const void* in, void* out, hipStream_t st);
-// x64 += x32 over ncomp blocks
+// ---- ns independent systems sharing one operator (the CN solves of i, o, l).
+// Vectors hold ns blocks of S complex values; system k has its own scalars
+// sv[k] and stopping rule (thr2, limit, fixed).  Only systems whose bit is set
+// in `active` are read or written; the finishing kernels mark the others done.
+// Each system's arithmetic (and the order of its sums) is that of the
+// one-system kernels above.
+struct BatchArgs {
+  void *x, *r, *p, *q, *b;
+  const void* ax;  // nullable (residual: r = b - ax)
+  const CoefScalars* cs;
+  SolveScalars* sv;  // ns entries
+  double* partials;
+  int n, ns, active;
+  PrecConsts pc;  // PREC_DIFF
+  double thr2[kMaxSys];
+  int limit[kMaxSys];
+  int fixed[kMaxSys];
+  double scale32[kMaxSys];  // launch_bresidual: r32 = float(scale32 * r)
+};
+template <typename R>
+void launch_bresidual(const BatchArgs& a, void* r32, hipStream_t st);
+template <typename R>
+void launch_bcn_residual(const BatchArgs& a, const void* c, const void* dc, hipStream_t st);
+template <typename R>
+void launch_bpcg_start(const BatchArgs& a, int zero_x, hipStream_t st);
+template <typename R>
+void launch_bpcg_update(const BatchArgs& a, hipStream_t st);
+template <typename R>
+void launch_bpcg_xfinal(const BatchArgs& a, hipStream_t st);
+// alpha_k = rho_k / <p, q>_k for the systems not done (partials at stride kDotStride)
+void launch_bfin_alpha(SolveScalars* sv, int ns, const double* part, int nb, hipStream_t st);
+// flags[k] = 0 for the systems in mask, 1 for the others (k < ns)
+void launch_set_flags(int* flags, int ns, int mask, hipStream_t st);
+// x64[k] += s[k] * double(x32[k]) for the systems in mask (blocks of count values)
+void launch_badd32to64(void* x64, const void* x32, const double (&s)[kMaxSys], int ns, int mask, long long count,
+                       hipStream_t st);
+
 // Mass-effect diagnostics of a displacement (Sec. 3, e:hook, e:princ_stress,
 // e:jacobian; Sec. 4 grid search).  f[3a + b'] are physical fields: f[0..2]
 // = u_a, then F_ab = G_b u_a stored at f[3 + 3b + a] (derivative b of u_a).

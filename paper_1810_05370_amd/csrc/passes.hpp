@@ -25,7 +25,7 @@
 
 namespace tumor {
 
-constexpr int kMaxCol = 8;
+constexpr int kMaxCol = 9;
 constexpr int kMaxTerms = 3;
 
 enum ColSym : int { SYM_ONE = 0, SYM_IW = 1, SYM_RAW = 2 };
@@ -46,18 +46,26 @@ struct ColProg {
   int nterm[kMaxCol];
   ColTerm term[kMaxCol][kMaxTerms];
   const int* skip;  // if non-null and *skip != 0 the launch does nothing
+  // per output: if non-null and *oskip[o] != 0, output o is not computed
+  // (a converged system of a batched solve)
+  const int* oskip[kMaxCol];
   // Optional fused Krylov inner product of a forward z pass: with dsv set,
   // each block stores its partial of sum_o <dotp[o], out[o]> (Parseval-
   // weighted) in dpart[block], and the launcher queues the one-block kernel
-  // that publishes alpha = rho / total to dsv.
+  // that publishes alpha = rho / total to dsv.  With dot_nsys > 0, output o
+  // belongs to system o of a batched solve: its partial goes to
+  // dpart[block * kDotStride + o] and alpha to dsv[o].
   const void* dotp[kMaxCol];
   SolveScalars* dsv;
   double* dpart;
+  int dot_nsys;
 };
 
 // First (inverse z) pass of a Krylov operator apply with the direction update
 // fused in: p = M^-1 r + beta p (in place), then out[2a] = IFFT_z(p_a) and
 // out[2a+1] = IFFT_z(i w_z p_a) for the NC components.
+// With nsys > 0 the vectors hold nsys independent one-component systems
+// (scalars sv[0 .. nsys)); a system whose solve is done is left untouched.
 struct ZPUpdateArgs {
   const void* r;
   void* p;
@@ -66,6 +74,7 @@ struct ZPUpdateArgs {
   SolveScalars* sv;
   const CoefScalars* cs;
   PrecConsts pc;
+  int nsys;
 };
 
 // Rows of the x pass: generic programs.
@@ -95,13 +104,16 @@ struct XElastArgs {
   const int* skip;
 };
 
-// Diffusion x pass.  Inputs: C, dy c, dz c (packed rows); coefficient K.
-// Outputs: i w_x F(K dx c), F(K dy c), F(K dz c).
+// Diffusion x pass for ns fields (systems) sharing K.  Inputs per field s:
+// C, dy c, dz c (packed rows) at in[3s .. 3s+2]; coefficient K.  Outputs:
+// i w_x F(K dx c), F(K dy c), F(K dz c) at out[3s .. 3s+2] (each may be its
+// own input).  Field s is skipped if skip[s] is non-null and *skip[s] != 0.
 struct XDiffArgs {
-  const void* in[3];
-  void* out[3];
+  const void* in[9];
+  void* out[9];
   const void* K;
-  const int* skip;
+  const int* skip[3];
+  int ns;
 };
 
 // Force x pass.  Inputs: T, dy t, dz t (packed rows of tau = p + n).

@@ -66,16 +66,17 @@ __device__ __forceinline__ double wave_sum_f(double v) {
   return v;
 }
 
-__device__ void store_dot_partial(double v, double* part) {
+__device__ void store_dot_partial(double v, double* part, int stride = 1, int slot = 0) {
   __shared__ double sh[16];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   v = wave_sum_f(v);
+  __syncthreads();  // a previous call's total has read sh
   if (lane == 0) sh[wv] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += sh[w];
-    part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+    part[(long long)(blockIdx.y * gridDim.x + blockIdx.x) * stride + slot] = s;
   }
 }
 
@@ -105,11 +106,22 @@ __global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(
 #pragma unroll
     for (int j = 0; j < 8; ++j) dst[j] = sp[base + (long long)(t + TP * j) * astride];
   };
+  // outputs to compute (block-uniform): all but those of converged systems
+  unsigned am = 0;
+  for (int o = 0; o < prog.nout; ++o)
+    if (!(prog.oskip[o] && *prog.oskip[o])) am |= 1u << o;
+  if (am == 0) return;
+  // the active output after o, or -1
+  auto next_out = [&](int o) -> int {
+    const unsigned rest = am & ~((2u << o) - 1u);
+    return rest ? __builtin_ctz(rest) : -1;
+  };
   cplx<R> nxt[8];
   cplx<R> pdot[8];
   (void)pdot;
-  load_col(nxt, prog.term[0][0].src);
-  for (int o = 0; o < prog.nout; ++o) {
+  load_col(nxt, prog.term[__builtin_ctz(am)][0].src);
+  for (int o = __builtin_ctz(am); o >= 0; o = next_out(o)) {
+    const int on = next_out(o);
     cplx<R> acc[8];
     const int nt = prog.nterm[o];
     if constexpr (INV) {
@@ -138,8 +150,8 @@ __global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(
       }
       // nxt still holds the raw column of term 0: an output that starts from
       // the same source (and does not overwrite it) reuses it
-      if (o + 1 < prog.nout) {
-        const int ns = prog.term[o + 1][0].src;
+      if (on >= 0) {
+        const int ns = prog.term[on][0].src;
         if (ns != prog.term[o][0].src || prog.out[o] == prog.in[ns]) load_col(nxt, ns);
       }
       fft_block<R, N, true, 1>(acc, lds, t, tw);
@@ -158,7 +170,7 @@ __global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(
 #pragma unroll
         for (int j = 0; j < 8; ++j) tmp[j] = nxt[j];
         if (q + 1 < nt) load_col(nxt, prog.term[o][q + 1].src);
-        else if (o + 1 < prog.nout) load_col(nxt, prog.term[o + 1][0].src);
+        else if (on >= 0) load_col(nxt, prog.term[on][0].src);
         if (tm.sym != SYM_RAW) fft_block<R, N, false, 1>(tmp, lds, t, tw);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -173,7 +185,7 @@ __global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(
           const R cf = R(last.coef);
 #pragma unroll
           for (int j = 0; j < 8; ++j) pdot[j] = nxt[j];
-          if (o + 1 < prog.nout) load_col(nxt, prog.term[o + 1][0].src);
+          if (on >= 0) load_col(nxt, prog.term[on][0].src);
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
             acc[j].x += cf * pdot[j].x;
@@ -194,15 +206,23 @@ __global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(
     if constexpr (DOT) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) dotacc += (double)pdot[j].x * (double)acc[j].x + (double)pdot[j].y * (double)acc[j].y;
+      if (prog.dot_nsys) {
+        // output o is system o's direction: its own partial
+        const int kxp = blockIdx.x * TC + col;
+        store_dot_partial(dotacc * ((kxp == 0) ? 1.0 : 2.0), prog.dpart, kDotStride, o);
+        dotacc = 0.0;
+      }
     }
   }
   if constexpr (DOT) {
-    static_assert((N / 2 / TC) * N <= kRedBlocksMax * kPartialsPerBlock,
-                  "one inner-product partial per block must fit the partials buffer");
-    // Parseval weight: the packed kx = 0 column counts once, the others twice
-    const int kxp = blockIdx.x * TC + col;
-    dotacc *= (kxp == 0) ? 1.0 : 2.0;
-    store_dot_partial(dotacc, prog.dpart);
+    static_assert((N / 2 / TC) * N * kDotStride <= kPartialsCount,
+                  "the inner-product partials of every block must fit the partials buffer");
+    if (!prog.dot_nsys) {
+      // Parseval weight: the packed kx = 0 column counts once, the others twice
+      const int kxp = blockIdx.x * TC + col;
+      dotacc *= (kxp == 0) ? 1.0 : 2.0;
+      store_dot_partial(dotacc, prog.dpart);
+    }
   }
 }
 
@@ -262,6 +282,67 @@ __global__ void __launch_bounds__((ColCfg<N, R, 256>::THREADS))
       for (int j = 0; j < 8; ++j) acc[j] = d ? ciw(pn[c][j], R(wavenum<N>(t + TP * j))) : pn[c][j];
       fft_block<R, N, true, 1>(acc, lds, t, tw);
       cplx<R>* __restrict__ dst = static_cast<cplx<R>*>(a.out[2 * c + d]);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dst[base + (long long)(t + TP * j) * astride] = acc[j];
+    }
+  }
+}
+
+// The same first pass for a.nsys independent one-component systems (a
+// batched solve): system s reads its scalars from a.sv[s] and is skipped once
+// its solve is done.
+template <typename R, int N>
+__global__ void __launch_bounds__((ColCfg<N, R, 256>::THREADS))
+    k_zinv_pupdate_b(ZPUpdateArgs a, const cplx<R>* __restrict__ twg) {
+  using Cfg = ColCfg<N, R, 256>;
+  constexpr int TP = Cfg::TP, TC = Cfg::TC;
+  constexpr long long C = N / 2;
+  constexpr long long S = (long long)N * N * C;
+  constexpr long long astride = (long long)N * C;
+  __shared__ cplx<R> sbuf[Cfg::LDS];
+  __shared__ cplx<R> stw[N];
+  stage_twiddles<R, N>(stw, twg);
+  const cplx<R>* tw = stw;
+  const int tid = threadIdx.x;
+  const int col = tid % TC;
+  const int t = tid / TC;
+  const int kx = blockIdx.x * TC + col;
+  const int ky = wavenum<N>(blockIdx.y);
+  const long long base = (long long)blockIdx.y * C + kx;
+  const LdsView<R> lds{sbuf + col, TC, 1};
+  const cplx<R>* __restrict__ r = static_cast<const cplx<R>*>(a.r);
+  cplx<R>* __restrict__ p = static_cast<cplx<R>*>(a.p);
+  cplx<R>* __restrict__ x = static_cast<cplx<R>*>(a.x);
+  for (int sy = 0; sy < a.nsys; ++sy) {
+    const SolveScalars* sv = a.sv + sy;
+    if (sv->done) continue;  // block-uniform
+    const R beta = R(sv->beta);
+    const R alpha = R(sv->alpha);
+    const long long so = sy * S;
+    cplx<R> pn[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int n = t + TP * j;
+      const long long idx = so + base + (long long)n * astride;
+      cplx<R> rv[1] = {r[idx]}, zv[1];
+      apply_prec<R, 1>(rv, zv, kx, ky, wavenum<N>(n), a.cs, a.pc);
+      const cplx<R> pv = p[idx];
+      if (x) {
+        cplx<R> xv = x[idx];
+        xv.x += alpha * pv.x;
+        xv.y += alpha * pv.y;
+        x[idx] = xv;
+      }
+      pn[j] = {zv[0].x + beta * pv.x, zv[0].y + beta * pv.y};
+      p[idx] = pn[j];
+    }
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      cplx<R> acc[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = d ? ciw(pn[j], R(wavenum<N>(t + TP * j))) : pn[j];
+      fft_block<R, N, true, 1>(acc, lds, t, tw);
+      cplx<R>* __restrict__ dst = static_cast<cplx<R>*>(a.out[2 * sy + d]);
 #pragma unroll
       for (int j = 0; j < 8; ++j) dst[base + (long long)(t + TP * j) * astride] = acc[j];
     }
@@ -587,15 +668,17 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
 
 template <typename R, int N>
 __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdiff(XDiffArgs a, const cplx<R>* __restrict__ twg) {
-  if (a.skip && *a.skip) return;
+  unsigned act = 0;  // fields to compute (block-uniform)
+  for (int f = 0; f < a.ns; ++f)
+    if (!(a.skip[f] && *a.skip[f])) act |= 1u << f;
+  if (act == 0) return;
   TUMOR_ROW_SETUP(N)
   const R invV = R(1.0) / (R(N) * R(N) * R(N));
   // block-uniform bases and a 32-bit lane offset, as in k_xelast
   const long long bs = (long long)blockIdx.x * RC::RW * L;
   const int ro = rl * L;
   const cplx<R>* K = static_cast<const cplx<R>*>(a.K) + bs;
-  const cplx<R>* C = static_cast<const cplx<R>*>(a.in[0]) + bs;
-  // K / N^3 for this row, loaded once for the three directions
+  // K / N^3 for this row, loaded once for the fields and directions
   cplx<R> kr[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -603,10 +686,13 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdiff(XDiffArgs a, const
     kr[j] = {k.x * invV, k.y * invV};
   }
 #pragma unroll 1
-  for (int d = 0; d < 3; ++d) {
+  for (int e = 0; e < 3 * a.ns; ++e) {
+    const int f = e / 3, d = e - 3 * f;
+    if (!(act & (1u << f))) continue;
+    // each output row is written after its own input row has been read (the
+    // FFT's barriers separate them), so an output may be its input
     cplx<R> g[8];
-    if (d == 0) row_c2r<R, N>(g, C, true, nullptr, lds, t, tw, ro);
-    else row_c2r<R, N>(g, static_cast<const cplx<R>*>(a.in[d]) + bs, false, nullptr, lds, t, tw, ro);
+    row_c2r<R, N>(g, static_cast<const cplx<R>*>(a.in[e]) + bs, d == 0, nullptr, lds, t, tw, ro);
 #pragma unroll
     for (int j = 0; j < 8; ++j) g[j] = {kr[j].x * g[j].x, kr[j].y * g[j].y};
     row_r2c<R, N>(g, lds, t, tw);
@@ -614,7 +700,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdiff(XDiffArgs a, const
 #pragma unroll
       for (int j = 0; j < 8; ++j) g[j] = iwx<R, N>(g[j], t + TP * j);
     }
-    store_row<R, N>(static_cast<cplx<R>*>(a.out[d]) + bs, g, t, ro);
+    store_row<R, N>(static_cast<cplx<R>*>(a.out[e]) + bs, g, t, ro);
   }
 }
 
@@ -714,7 +800,8 @@ void launch_col_pass_seg(int axis, bool inverse, const ColProg& prog, const cplx
   else if (prog.dsv) {
     hipLaunchKernelGGL((k_col_pass<R, NN, false, true, SEG>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride,
                        astride, twp);
-    launch_fin_alpha(prog.dsv, prog.dpart, (int)(grid.x * grid.y), 1, st);
+    if (prog.dot_nsys) launch_bfin_alpha(prog.dsv, prog.dot_nsys, prog.dpart, (int)(grid.x * grid.y), st);
+    else launch_fin_alpha(prog.dsv, prog.dpart, (int)(grid.x * grid.y), 1, st);
   } else
     hipLaunchKernelGGL((k_col_pass<R, NN, false, false, SEG>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride,
                        astride, twp);
@@ -735,7 +822,9 @@ void launch_zinv_pupdate(int n, int ncomp, const ZPUpdateArgs& a, const void* tw
   TUMOR_DISPATCH_N(n, {
     using Cfg = ColCfg<NN, R, 256>;
     dim3 grid((NN / 2) / Cfg::TC, NN);
-    if (ncomp == 1)
+    if (a.nsys > 0)
+      hipLaunchKernelGGL((k_zinv_pupdate_b<R, NN>), grid, dim3(Cfg::THREADS), 0, st, a, twp);
+    else if (ncomp == 1)
       hipLaunchKernelGGL((k_zinv_pupdate<R, NN, 1>), grid, dim3(Cfg::THREADS), 0, st, a, twp);
     else
       hipLaunchKernelGGL((k_zinv_pupdate<R, NN, 3>), grid, dim3(Cfg::THREADS), 0, st, a, twp);

@@ -1035,13 +1035,317 @@ void launch_precond(const KrylovArgs& a, const void* in, void* out, hipStream_t 
                                                  static_cast<cplx<R>*>(out)));
 }
 
+// ---------------------------------------------- batched independent systems
+// ns one-component systems (PREC_DIFF) sharing an operator: system k's
+// partials sit at slots k (and kMaxSys + k) of a block, its scalars in sv[k].
+// The per-system sums run over the same elements in the same order as the
+// one-system kernels, so each system's scalars equal its own solve's.
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_bresidual(BatchArgs a, SpecIdx ix, cplx<float>* r32) {
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  const cplx<R>* b = static_cast<const cplx<R>*>(a.b);
+  const cplx<R>* ax = static_cast<const cplx<R>*>(a.ax);
+  cplx<R>* r = static_cast<cplx<R>*>(a.r);
+  double acc[2 * kMaxSys] = {};
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int kx = (int)(e & ix.hmask);
+#pragma unroll
+    for (int c = 0; c < kMaxSys; ++c) {
+      if (c >= a.ns || !(a.active & (1 << c))) continue;
+      const long long k = e + c * S;
+      const cplx<R> bv = b[k];
+      const cplx<R> rv = ax ? csub(bv, ax[k]) : bv;
+      r[k] = rv;
+      if (r32) r32[k] = {float(a.scale32[c] * rv.x), float(a.scale32[c] * rv.y)};
+      acc[c] += wdot(bv, bv, kx);
+      acc[kMaxSys + c] += wdot(rv, rv, kx);
+    }
+  }
+  block_store_partials<2 * kMaxSys>(acc, a.partials);
+}
+
+// Crank-Nicolson start per system: x0 = c, b = c + h Dc, r = b - (c - h Dc).
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_bcn_residual(BatchArgs a, SpecIdx ix, const cplx<R>* c,
+                                                               const cplx<R>* dc) {
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  cplx<R>* b = static_cast<cplx<R>*>(a.b);
+  cplx<R>* r = static_cast<cplx<R>*>(a.r);
+  const R h = R(a.pc.h);
+  double acc[2 * kMaxSys] = {};
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
+       e += (long long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    ix.decode(e, kx, ky, kz);
+#pragma unroll
+    for (int s = 0; s < kMaxSys; ++s) {
+      if (s >= a.ns || !(a.active & (1 << s))) continue;
+      const long long k = e + s * S;
+      const cplx<R> cv = c[k], dv = dc[k];
+      const cplx<R> bv = {cv.x + h * dv.x, cv.y + h * dv.y};
+      const cplx<R> av = {cv.x - h * dv.x, cv.y - h * dv.y};
+      const cplx<R> rv = csub(bv, av);
+      b[k] = bv;
+      r[k] = rv;
+      acc[s] += wdot(bv, bv, kx);
+      acc[kMaxSys + s] += wdot(rv, rv, kx);
+    }
+  }
+  block_store_partials<2 * kMaxSys>(acc, a.partials);
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_bfin_resid(SolveScalars* sv, int ns, int active, const double* part,
+                                                             int nb) {
+  double tot[2 * kMaxSys];
+  total_partials<2 * kMaxSys>(tot, part, nb, kPartialsPerBlock);
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < ns; ++s) {
+      if (!(active & (1 << s))) continue;
+      sv[s].bb = tot[s];
+      sv[s].rr = tot[kMaxSys + s];
+      sv[s].it = 0;
+      sv[s].done = 0;
+      sv[s].conv = 0;
+      sv[s].bad = (isfinite(tot[s]) && isfinite(tot[kMaxSys + s])) ? 0 : 1;
+    }
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_bpcg_start(BatchArgs a, SpecIdx ix, int zero_x) {
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  const cplx<R>* r = static_cast<const cplx<R>*>(a.r);
+  cplx<R>* p = static_cast<cplx<R>*>(a.p);
+  cplx<R>* x = static_cast<cplx<R>*>(a.x);
+  double acc[kMaxSys] = {};
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
+       e += (long long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    ix.decode(e, kx, ky, kz);
+#pragma unroll
+    for (int s = 0; s < kMaxSys; ++s) {
+      if (s >= a.ns || !(a.active & (1 << s))) continue;
+      cplx<R> rv[1] = {r[e + s * S]}, zv[1];
+      apply_prec<R, 1>(rv, zv, kx, ky, kz, a.cs, a.pc);
+      p[e + s * S] = zv[0];
+      if (zero_x) x[e + s * S] = czero<R>();
+      acc[s] += wdot(rv[0], zv[0], kx);
+    }
+  }
+  block_store_partials<kMaxSys>(acc, a.partials);
+}
+
+// rho_k = <r, M^-1 r>_k; systems outside `active` are marked done with no iterations.
+__global__ void __launch_bounds__(kRedThreads) k_bfin_start(SolveScalars* sv, int ns, int active, const double* part,
+                                                             int nb) {
+  double tot[kMaxSys];
+  total_partials<kMaxSys>(tot, part, nb, kPartialsPerBlock);
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < ns; ++s) {
+      sv[s].it = 0;
+      sv[s].conv = 0;
+      if (!(active & (1 << s))) {
+        sv[s].done = 1;
+        sv[s].bad = 0;
+        continue;
+      }
+      sv[s].rho = tot[s];
+      const bool ok = isfinite(tot[s]) && tot[s] > 0.0;
+      sv[s].bad = ok ? 0 : 1;
+      sv[s].done = ok ? 0 : 1;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_bfin_alpha(SolveScalars* sv, int ns, const double* part, int nb) {
+  for (int s = 0; s < ns; ++s) {
+    if (sv[s].done) continue;  // uniform
+    double tot[1];
+    total_partials<1>(tot, part + s, nb, kDotStride);
+    if (threadIdx.x == 0) {
+      sv[s].pq = tot[0];
+      if (!(isfinite(tot[0]) && tot[0] > 0.0)) {
+        sv[s].bad = 1;
+        sv[s].done = 1;
+        sv[s].alpha = 0.0;  // nothing left for the deferred x update to add
+      } else {
+        sv[s].alpha = sv[s].rho / tot[0];
+      }
+    }
+    __syncthreads();  // every thread has read sv[s].done before thread 0 may change it
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_bpcg_update(BatchArgs a, SpecIdx ix) {
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  cplx<R>* r = static_cast<cplx<R>*>(a.r);
+  const cplx<R>* q = static_cast<const cplx<R>*>(a.q);
+  bool run[kMaxSys];
+  R alpha[kMaxSys];
+  bool any = false;
+#pragma unroll
+  for (int s = 0; s < kMaxSys; ++s) {
+    run[s] = s < a.ns && !a.sv[s].done;
+    alpha[s] = run[s] ? R(a.sv[s].alpha) : R(0);
+    any = any || run[s];
+  }
+  if (!any) return;
+  double acc[2 * kMaxSys] = {};
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < S;
+       e += (long long)gridDim.x * blockDim.x) {
+    int kx, ky, kz;
+    ix.decode(e, kx, ky, kz);
+#pragma unroll
+    for (int s = 0; s < kMaxSys; ++s) {
+      if (!run[s]) continue;
+      const long long k = e + s * S;
+      const cplx<R> qv = q[k];
+      cplx<R> rr = r[k];
+      rr.x -= alpha[s] * qv.x;
+      rr.y -= alpha[s] * qv.y;
+      r[k] = rr;
+      cplx<R> rv[1] = {rr}, zv[1];
+      apply_prec<R, 1>(rv, zv, kx, ky, kz, a.cs, a.pc);
+      acc[s] += wdot(rv[0], rv[0], kx);
+      acc[kMaxSys + s] += wdot(rv[0], zv[0], kx);
+    }
+  }
+  block_store_partials<2 * kMaxSys>(acc, a.partials);
+}
+
+// Per system not done: iteration count, ||r||^2, convergence, beta and rho.
+__global__ void __launch_bounds__(kRedThreads) k_bfin_update(BatchArgs a, int nb) {
+  bool any = false;
+  for (int s = 0; s < a.ns; ++s) any = any || !a.sv[s].done;
+  if (!any) return;
+  double tot[2 * kMaxSys];
+  total_partials<2 * kMaxSys>(tot, a.partials, nb, kPartialsPerBlock);
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < a.ns; ++s) {
+      SolveScalars* sv = a.sv + s;
+      if (sv->done) continue;
+      const double rr = tot[s], rz = tot[kMaxSys + s];
+      sv->it += 1;
+      sv->rr = rr;
+      if (!(isfinite(rr) && isfinite(rz))) {
+        sv->bad = 1;
+        sv->done = 1;
+      } else if (!a.fixed[s] && rr <= a.thr2[s]) {
+        sv->conv = 1;
+        sv->done = 1;
+      } else if (sv->it >= a.limit[s]) {
+        sv->conv = a.fixed[s] ? 1 : 0;
+        sv->done = 1;
+      } else {
+        sv->beta = rz / sv->rho;
+        sv->rho = rz;
+      }
+    }
+  }
+}
+
+// x_k += alpha_k p_k for the last iteration each system ran (none: no-op).
+template <typename R>
+__global__ void __launch_bounds__(256) k_bpcg_xfinal(BatchArgs a) {
+  const long long S = (long long)a.n * a.n * (a.n / 2);
+  cplx<R>* x = static_cast<cplx<R>*>(a.x);
+  const cplx<R>* p = static_cast<const cplx<R>*>(a.p);
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S) return;
+  for (int s = 0; s < a.ns; ++s) {
+    if (!(a.active & (1 << s)) || a.sv[s].it == 0) continue;
+    const R alpha = R(a.sv[s].alpha);
+    const cplx<R> pv = p[e + s * S];
+    cplx<R> xv = x[e + s * S];
+    xv.x += alpha * pv.x;
+    xv.y += alpha * pv.y;
+    x[e + s * S] = xv;
+  }
+}
+
+__global__ void k_set_flags(int* flags, int ns, int mask) {
+  if ((int)threadIdx.x < ns) flags[threadIdx.x] = ((mask >> threadIdx.x) & 1) ? 0 : 1;
+}
+
+struct BScale {
+  double s[kMaxSys];
+};
+__global__ void k_badd32to64(double* x, const float* y, BScale sc, int ns, int mask, long long count) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  for (int s = 0; s < ns; ++s)
+    if (mask & (1 << s)) x[s * count + k] += sc.s[s] * (double)y[s * count + k];
+}
+
+template <typename R>
+void launch_bresidual(const BatchArgs& a, void* r32, hipStream_t st) {
+  const SpecIdx ix = make_idx(a.n);
+  const int nb = red_blocks(spec_count(a.n));
+  hipLaunchKernelGGL((k_bresidual<R>), dim3(nb), dim3(kRedThreads), 0, st, a, ix, static_cast<cplx<float>*>(r32));
+  hipLaunchKernelGGL(k_bfin_resid, dim3(1), dim3(kRedThreads), 0, st, a.sv, a.ns, a.active, a.partials, nb);
+}
+
+template <typename R>
+void launch_bcn_residual(const BatchArgs& a, const void* c, const void* dc, hipStream_t st) {
+  const SpecIdx ix = make_idx(a.n);
+  const int nb = red_blocks(spec_count(a.n));
+  hipLaunchKernelGGL((k_bcn_residual<R>), dim3(nb), dim3(kRedThreads), 0, st, a, ix, static_cast<const cplx<R>*>(c),
+                     static_cast<const cplx<R>*>(dc));
+  hipLaunchKernelGGL(k_bfin_resid, dim3(1), dim3(kRedThreads), 0, st, a.sv, a.ns, a.active, a.partials, nb);
+}
+
+template <typename R>
+void launch_bpcg_start(const BatchArgs& a, int zero_x, hipStream_t st) {
+  const SpecIdx ix = make_idx(a.n);
+  const int nb = red_blocks(spec_count(a.n));
+  hipLaunchKernelGGL((k_bpcg_start<R>), dim3(nb), dim3(kRedThreads), 0, st, a, ix, zero_x);
+  hipLaunchKernelGGL(k_bfin_start, dim3(1), dim3(kRedThreads), 0, st, a.sv, a.ns, a.active, a.partials, nb);
+}
+
+void launch_bfin_alpha(SolveScalars* sv, int ns, const double* part, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_bfin_alpha, dim3(1), dim3(kRedThreads), 0, st, sv, ns, part, nb);
+}
+
+template <typename R>
+void launch_bpcg_update(const BatchArgs& a, hipStream_t st) {
+  const SpecIdx ix = make_idx(a.n);
+  const int nb = red_blocks(spec_count(a.n));
+  hipLaunchKernelGGL((k_bpcg_update<R>), dim3(nb), dim3(kRedThreads), 0, st, a, ix);
+  hipLaunchKernelGGL(k_bfin_update, dim3(1), dim3(kRedThreads), 0, st, a, nb);
+}
+
+template <typename R>
+void launch_bpcg_xfinal(const BatchArgs& a, hipStream_t st) {
+  const long long S = spec_count(a.n);
+  hipLaunchKernelGGL((k_bpcg_xfinal<R>), dim3((unsigned)((S + 255) / 256)), dim3(256), 0, st, a);
+}
+
+void launch_set_flags(int* flags, int ns, int mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, st, flags, ns, mask);
+}
+
+void launch_badd32to64(void* x64, const void* x32, const double (&s)[kMaxSys], int ns, int mask, long long count,
+                       hipStream_t st) {
+  BScale sc;
+  for (int k = 0; k < kMaxSys; ++k) sc.s[k] = s[k];
+  hipLaunchKernelGGL(k_badd32to64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                     static_cast<double*>(x64), static_cast<const float*>(x32), sc, ns, mask, count);
+}
+
 #define TUMOR_INST_KRYLOV(R)                                                               \
   template void launch_residual<R>(const KrylovArgs&, void*, hipStream_t);                 \
   template void launch_cn_residual<R>(const KrylovArgs&, const void*, const void*, hipStream_t); \
   template void launch_pcg_start<R>(const KrylovArgs&, int, hipStream_t);                  \
   template void launch_pcg_update<R>(const KrylovArgs&, hipStream_t);                      \
   template void launch_pcg_xfinal<R>(const KrylovArgs&, hipStream_t);                      \
-  template void launch_precond<R>(const KrylovArgs&, const void*, void*, hipStream_t);
+  template void launch_precond<R>(const KrylovArgs&, const void*, void*, hipStream_t);     \
+  template void launch_bresidual<R>(const BatchArgs&, void*, hipStream_t);                 \
+  template void launch_bcn_residual<R>(const BatchArgs&, const void*, const void*, hipStream_t); \
+  template void launch_bpcg_start<R>(const BatchArgs&, int, hipStream_t);                  \
+  template void launch_bpcg_update<R>(const BatchArgs&, hipStream_t);                      \
+  template void launch_bpcg_xfinal<R>(const BatchArgs&, hipStream_t);
 TUMOR_INST_KRYLOV(double)
 TUMOR_INST_KRYLOV(float)
 
