@@ -29,12 +29,12 @@ METRIC = "split time steps/s at 256³ (fwd, fwd+adjoint), mixed vs FP64 on one G
 HBM_PEAK_GBS = 8000.0
 CLASSES = ("colinv64", "colfwd64", "colinv32", "colfwd32", "colinv32z", "colfwd32z", "xelast64", "xelast32",
            "xdiff64", "xdiff32", "xother", "sl", "react", "krylov64", "krylov32", "zinvp64", "zinvp32",
-           "zinvp64c1", "zinvp32c1", "coldot64", "coldot32")
+           "zinvp64c1", "zinvp32c1", "zinvpb64", "zinvpb32", "coldot64", "coldot32")
 # classes that time exactly one kernel symbol, so that the roofline's kernel can
 # be matched to a rocprofv3 summary line (xother, sl and krylov group several)
 SINGLE_KERNEL = ("colinv64", "colfwd64", "colinv32", "colfwd32", "colinv32z", "colfwd32z", "coldot64",
                  "coldot32", "xelast64", "xelast32", "xdiff64", "xdiff32", "zinvp64", "zinvp32", "zinvp64c1",
-                 "zinvp32c1", "react")
+                 "zinvp32c1", "zinvpb64", "zinvpb32", "react")
 
 # Stable windows of the 256^3 forward workloads: (steps from t = 0 before the
 # window, longest run from the window's start).  The coupled transport /

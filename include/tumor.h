@@ -354,7 +354,9 @@ enum {
                                             (elasticity, 3 components)                 */
   TUMOR_K_COLDOT64, TUMOR_K_COLDOT32,    /* last pass with the fused inner product      */
   TUMOR_K_COLINV32Z, TUMOR_K_COLFWD32Z,  /* FP32 z passes (COLINV32/COLFWD32: y passes)  */
-  TUMOR_K_ZINVP64_1, TUMOR_K_ZINVP32_1,  /* fused first pass of the CN solves (1 comp.)  */
+  TUMOR_K_ZINVP64_1, TUMOR_K_ZINVP32_1,  /* fused first pass of a one-field CN solve      */
+  TUMOR_K_ZINVPB64, TUMOR_K_ZINVPB32,    /* fused first pass of the batched CN solve of
+                                            i, o and l                                 */
   TUMOR_K_COUNT
 };
 int tumor_kernel_timer(tumor_ctx* ctx, int32_t kernel_class, int32_t enable);

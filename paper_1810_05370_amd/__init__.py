@@ -41,7 +41,7 @@ VECTOR_OPS = ("elasticity", "elast_precond", "force")
 KERNEL_CLASSES = {"colinv64": 0, "colfwd64": 1, "colinv32": 2, "colfwd32": 3, "xelast64": 4, "xelast32": 5,
                   "xdiff64": 6, "xdiff32": 7, "xother": 8, "sl": 9, "react": 10, "krylov64": 11, "krylov32": 12,
                   "zinvp64": 13, "zinvp32": 14, "coldot64": 15, "coldot32": 16, "colinv32z": 17,
-                  "colfwd32z": 18, "zinvp64c1": 19, "zinvp32c1": 20}
+                  "colfwd32z": 18, "zinvp64c1": 19, "zinvp32c1": 20, "zinvpb64": 21, "zinvpb32": 22}
 # rocprofv3 kernel names of each class (for cross-checking event timings against traces)
 KERNEL_NAMES = {"colinv64": "k_col_pass<double, {n}, true, false, 256>",
                 "colfwd64": "k_col_pass<double, {n}, false, false, 256>",
@@ -53,6 +53,7 @@ KERNEL_NAMES = {"colinv64": "k_col_pass<double, {n}, true, false, 256>",
                 "coldot32": "k_col_pass<float, {n}, false, true, 256>",
                 "zinvp64": "k_zinv_pupdate<double, {n}, 3>", "zinvp32": "k_zinv_pupdate<float, {n}, 3>",
                 "zinvp64c1": "k_zinv_pupdate<double, {n}, 1>", "zinvp32c1": "k_zinv_pupdate<float, {n}, 1>",
+                "zinvpb64": "k_zinv_pupdate_b<double, {n}>", "zinvpb32": "k_zinv_pupdate_b<float, {n}>",
                 "xelast64": "k_xelast<double, {n}>", "xelast32": "k_xelast<float, {n}>",
                 "xdiff64": "k_xdiff<double, {n}>", "xdiff32": "k_xdiff<float, {n}>", "sl": "k_sl",
                 "react": "k_react"}

@@ -974,7 +974,7 @@ void diff_apply_b(Ctx& c, int ns, const cplx<R>* in, cplx<R>* out, double raw, d
     za.cs = c.cs;
     za.pc = fz->pc;
     za.nsys = ns;
-    timed(c, kcls<R>(TUMOR_K_ZINVP64_1, TUMOR_K_ZINVP32_1), 7.0 * ns * double(c.V) * sizeof(R),
+    timed(c, kcls<R>(TUMOR_K_ZINVPB64, TUMOR_K_ZINVPB32), 7.0 * ns * double(c.V) * sizeof(R),
           [&] { tumor::launch_zinv_pupdate<R>(c.n, 1, za, P.tw, c.st); });
   } else {
     Prog z;
