@@ -1104,14 +1104,18 @@ void pcg_iterate_b(Ctx& c, tumor::BatchArgs a, const double* thr2, const int* li
 
 // Crank-Nicolson diffusion of ns physical fields src[k] into dst[k] (may
 // alias), which[k] = solve slot (iteration predictions, forced counts).
-void cn_solve_b(Ctx& c, int ns, const double* const* src, double* const* dst, const int* which, SolveOut* so) {
+// With rhs set (the adjoint's solves) src[k] are instead right-hand sides:
+// (1 - dt/2 D) y_k = src[k] from y_k = 0, and the solutions stay spectral in
+// the blocks of Un (dst unused).
+void cn_solve_b(Ctx& c, int ns, const double* const* src, double* const* dst, const int* which, SolveOut* so,
+                bool rhs = false) {
   const double h = 0.5 * c.cfg.dt;
   const long long S = c.S;
   const int all = (1 << ns) - 1;
   cplx<double>* x = c.Un;  // ns blocks; free between elasticity solves
   for (int k = 0; k < ns; ++k) {
     so[k] = SolveOut();
-    fwd3<double>(c, src[k], nullptr, x + k * S);
+    fwd3<double>(c, src[k], nullptr, rhs ? c.b64 + k * S : x + k * S);
   }
   PrecBufs<double>& P = c.p64;
   tumor::BatchArgs a = bargs<double>(c, ns, all, x, c.sv64, h);
@@ -1123,9 +1127,15 @@ void cn_solve_b(Ctx& c, int ns, const double* const* src, double* const* dst, co
     tumor::launch_set_flags(c.bflag, ns, mask, c.st);
     diff_apply_b<double>(c, ns, in, out, raw, dcoef, flag);
   };
-  // D x0 for every system, then b = x0 + h D x0 and r = b - (x0 - h D x0)
-  apply64(all, x, P.q, 0.0, 1.0);
-  timed(c, TUMOR_K_KRYLOV64, 4.0 * ns * c.V * 8.0, [&] { tumor::launch_bcn_residual<double>(a, x, P.q, c.st); });
+  if (rhs) {
+    // x0 = 0: r = b
+    HIPCHECK(hipMemsetAsync(x, 0, ns * S * sizeof(cplx<double>), c.st));
+    timed(c, TUMOR_K_KRYLOV64, 2.0 * ns * c.V * 8.0, [&] { tumor::launch_bresidual<double>(a, nullptr, c.st); });
+  } else {
+    // D x0 for every system, then b = x0 + h D x0 and r = b - (x0 - h D x0)
+    apply64(all, x, P.q, 0.0, 1.0);
+    timed(c, TUMOR_K_KRYLOV64, 4.0 * ns * c.V * 8.0, [&] { tumor::launch_bcn_residual<double>(a, x, P.q, c.st); });
+  }
   HIPCHECK(hipMemcpyAsync(c.hsv, c.sv64, ns * sizeof(tumor::SolveScalars), hipMemcpyDeviceToHost, c.st));
   HIPCHECK(hipStreamSynchronize(c.st));
   double bb[tumor::kMaxSys], rr[tumor::kMaxSys], thr2[tumor::kMaxSys];
@@ -1267,7 +1277,8 @@ void cn_solve_b(Ctx& c, int ns, const double* const* src, double* const* dst, co
       c.pred[which[k]] = std::max(1, total[k] / std::max(1, so[k].outer));
     }
   }
-  for (int k = 0; k < ns; ++k) inv3<double>(c, x + k * S, dst[k], 1.0 / (double)c.V);
+  if (!rhs)
+    for (int k = 0; k < ns; ++k) inv3<double>(c, x + k * S, dst[k], 1.0 / (double)c.V);
 }
 
 // Elasticity solve (eta - L) u = rhs, rhs spectral in b64, warm start from U.
@@ -1724,17 +1735,17 @@ SolveOut adjoint_solve(Ctx& c, int ncomp, const double* rhs, int which) {
   return solve_system(c, 3, tumor::PREC_ELAST, 0.0, x, c.b64, c.cfg.rtol_elast, which, A64, A32, r0);
 }
 
-// CN adjoint: y = A^-1 cbar_plus; out = (1 + dt/2 D) y; KB += -dt/2 sum_a G_a y G_a (c- + c+).
-void cn_adjoint(Ctx& c, const double* cbar_plus, double* out, const double* cm, const double* cp, int which) {
-  adjoint_solve(c, 1, cbar_plus, which);
+// CN adjoint of one field, given y = A^-1 cbar_plus (spectral): out = (1 + dt/2 D) y;
+// KB += -dt/2 sum_a G_a y G_a (c- + c+).
+void cn_adjoint_post(Ctx& c, const cplx<double>* y, double* out, const double* cm, const double* cp) {
   const double h = 0.5 * c.cfg.dt;
   PrecBufs<double>& P = c.p64;
-  diff_apply<double>(c, c.Un, P.q, 1.0, h, nullptr);
+  diff_apply<double>(c, y, P.q, 1.0, h, nullptr);
   inv3<double>(c, P.q, out, 1.0 / (double)c.V);
   fwd3<double>(c, cm, cp, P.r);  // spectrum of s = c- + c+
   // z and y inverse passes of y and s, then the three products on the x pass
   colp<double>(c, 2, true,
-               Prog().in(0, c.Un).in(1, P.r).out(P.A[0], {T1(0)}).out(P.A[1], {TW(0)}).out(P.A[2], {T1(1)}).out(
+               Prog().in(0, y).in(1, P.r).out(P.A[0], {T1(0)}).out(P.A[1], {TW(0)}).out(P.A[2], {T1(1)}).out(
                    P.A[3], {TW(1)}));
   colp<double>(c, 1, true,
                Prog()
@@ -1916,10 +1927,19 @@ void adjoint_core(Ctx& c, const double* x0, double* adj, int m, double* grad) {
     double* out[8] = {nullptr};
     refresh(c, 0, in, out);
   }
-  cn_adjoint(c, c.IDD, Lm[I], c.G[I], c.Rdd[0], 4);
+  {
+    // the three (two without edema) adjoint CN solves as one batched solve
+    const int ns = (c.flags & TUMOR_F_EDEMA) ? 3 : 2;
+    const double* rhs[3] = {c.IDD, Lm[O], Lm[L]};
+    const int which[3] = {4, 5, 6};
+    SolveOut so[3];
+    cn_solve_b(c, ns, rhs, nullptr, which, so, true);
+    double* const out[3] = {Lm[I], Lm[O], Lm[L]};
+    const double* const cm[3] = {c.G[I], F0[O], F0[L]};
+    const double* const cp[3] = {c.Rdd[0], c.Rdd[1], c.Rdd[2]};
+    for (int k = 0; k < ns; ++k) cn_adjoint_post(c, c.Un + k * c.S, out[k], cm[k], cp[k]);
+  }
   tumor::launch_axpy(V, -1.0, c.DDB, Lm[I], c.st);
-  cn_adjoint(c, Lm[O], Lm[O], F0[O], c.Rdd[1], 5);
-  if (c.flags & TUMOR_F_EDEMA) cn_adjoint(c, Lm[L], Lm[L], F0[L], c.Rdd[2], 6);
   // ---- S1 transport
   if (c.flags & TUMOR_F_ADVECTION) {
     for (int k = 0; k < 6; ++k) zero(c, c.SLO[k], V);

@@ -289,11 +289,14 @@ __global__ void __launch_bounds__((ColCfg<N, R, 256>::THREADS))
 }
 
 // The same first pass for a.nsys independent one-component systems (a
-// batched solve): system s reads its scalars from a.sv[s] and is skipped once
-// its solve is done.
+// batched solve): blockIdx.z is the system, whose scalars are a.sv[z]; the
+// blocks of a system whose solve is done exit at once.
 template <typename R, int N>
 __global__ void __launch_bounds__((ColCfg<N, R, 256>::THREADS))
     k_zinv_pupdate_b(ZPUpdateArgs a, const cplx<R>* __restrict__ twg) {
+  const int sy = blockIdx.z;
+  const SolveScalars* sv = a.sv + sy;
+  if (sv->done) return;
   using Cfg = ColCfg<N, R, 256>;
   constexpr int TP = Cfg::TP, TC = Cfg::TC;
   constexpr long long C = N / 2;
@@ -310,42 +313,37 @@ __global__ void __launch_bounds__((ColCfg<N, R, 256>::THREADS))
   const int ky = wavenum<N>(blockIdx.y);
   const long long base = (long long)blockIdx.y * C + kx;
   const LdsView<R> lds{sbuf + col, TC, 1};
+  const R beta = R(sv->beta);
+  const R alpha = R(sv->alpha);
   const cplx<R>* __restrict__ r = static_cast<const cplx<R>*>(a.r);
   cplx<R>* __restrict__ p = static_cast<cplx<R>*>(a.p);
   cplx<R>* __restrict__ x = static_cast<cplx<R>*>(a.x);
-  for (int sy = 0; sy < a.nsys; ++sy) {
-    const SolveScalars* sv = a.sv + sy;
-    if (sv->done) continue;  // block-uniform
-    const R beta = R(sv->beta);
-    const R alpha = R(sv->alpha);
-    const long long so = sy * S;
-    cplx<R> pn[8];
+  cplx<R> pn[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int n = t + TP * j;
-      const long long idx = so + base + (long long)n * astride;
-      cplx<R> rv[1] = {r[idx]}, zv[1];
-      apply_prec<R, 1>(rv, zv, kx, ky, wavenum<N>(n), a.cs, a.pc);
-      const cplx<R> pv = p[idx];
-      if (x) {
-        cplx<R> xv = x[idx];
-        xv.x += alpha * pv.x;
-        xv.y += alpha * pv.y;
-        x[idx] = xv;
-      }
-      pn[j] = {zv[0].x + beta * pv.x, zv[0].y + beta * pv.y};
-      p[idx] = pn[j];
+  for (int j = 0; j < 8; ++j) {
+    const int n = t + TP * j;
+    const long long idx = sy * S + base + (long long)n * astride;
+    cplx<R> rv[1] = {r[idx]}, zv[1];
+    apply_prec<R, 1>(rv, zv, kx, ky, wavenum<N>(n), a.cs, a.pc);
+    const cplx<R> pv = p[idx];
+    if (x) {
+      cplx<R> xv = x[idx];
+      xv.x += alpha * pv.x;
+      xv.y += alpha * pv.y;
+      x[idx] = xv;
     }
+    pn[j] = {zv[0].x + beta * pv.x, zv[0].y + beta * pv.y};
+    p[idx] = pn[j];
+  }
 #pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      cplx<R> acc[8];
+  for (int d = 0; d < 2; ++d) {
+    cplx<R> acc[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc[j] = d ? ciw(pn[j], R(wavenum<N>(t + TP * j))) : pn[j];
-      fft_block<R, N, true, 1>(acc, lds, t, tw);
-      cplx<R>* __restrict__ dst = static_cast<cplx<R>*>(a.out[2 * sy + d]);
+    for (int j = 0; j < 8; ++j) acc[j] = d ? ciw(pn[j], R(wavenum<N>(t + TP * j))) : pn[j];
+    fft_block<R, N, true, 1>(acc, lds, t, tw);
+    cplx<R>* __restrict__ dst = static_cast<cplx<R>*>(a.out[2 * sy + d]);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) dst[base + (long long)(t + TP * j) * astride] = acc[j];
-    }
+    for (int j = 0; j < 8; ++j) dst[base + (long long)(t + TP * j) * astride] = acc[j];
   }
 }
 
@@ -823,7 +821,7 @@ void launch_zinv_pupdate(int n, int ncomp, const ZPUpdateArgs& a, const void* tw
     using Cfg = ColCfg<NN, R, 256>;
     dim3 grid((NN / 2) / Cfg::TC, NN);
     if (a.nsys > 0)
-      hipLaunchKernelGGL((k_zinv_pupdate_b<R, NN>), grid, dim3(Cfg::THREADS), 0, st, a, twp);
+      hipLaunchKernelGGL((k_zinv_pupdate_b<R, NN>), dim3(grid.x, grid.y, a.nsys), dim3(Cfg::THREADS), 0, st, a, twp);
     else if (ncomp == 1)
       hipLaunchKernelGGL((k_zinv_pupdate<R, NN, 1>), grid, dim3(Cfg::THREADS), 0, st, a, twp);
     else
