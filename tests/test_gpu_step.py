@@ -256,3 +256,31 @@ def test_substep_timer_accounts_for_the_step():
     assert n == 3
     assert all(v > 0.0 for v in sub.values())
     assert 0.9 * total <= sum(sub.values()) <= total * 1.001
+
+
+def test_batched_cn_kernel_timers_count_the_systems_still_iterating():
+    """The batched CN solve's passes carry i, o and l while each iterates.  The
+    kernel timers count, per launch, the bytes of the systems it computed: for
+    the fused first pass 7 array passes per system, for the x pass K once plus
+    6 per system.  So the mean bytes per launch lie between one and three
+    systems' worth, and below three since o converges first."""
+    need_gpu()
+    P = synthetic.params()
+    n = 64
+    inp = synthetic.workload_inputs("seeds3_n128", n=n)
+    sim = tm.from_inputs(inp, P, precision="mixed")
+    sim.step(3)   # i and l nonzero: all three systems iterate
+    for c in ("zinvpb32", "xdiff32"):
+        sim.kernel_timer(c, True)
+    stats = sim.step(2)
+    reads = {c: sim.kernel_timer_read(c) for c in ("zinvpb32", "xdiff32")}
+    sim.close()
+    V, fb = n ** 3, 4
+    say(f"batched timers: {reads}, diffusion iterations {stats['it_diff']}")
+    its = stats["it_diff"]
+    assert min(its) < max(its)
+    for c, (fixed, per) in {"zinvpb32": (0, 7), "xdiff32": (1, 6)}.items():
+        r = reads[c]
+        assert r["launches"] > 0
+        b = r["bytes"] / r["launches"]
+        assert (fixed + per) * V * fb <= b < (fixed + 3 * per) * V * fb, (c, b)
