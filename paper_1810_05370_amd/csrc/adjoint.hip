@@ -324,7 +324,7 @@ __device__ __forceinline__ void gather_vel(const StencilD& s, const double* __re
 // the arrival voxel's adjoints lam (constant over the stencil) folded in
 // before the sums: e = I[sum_{k<5} lam_k q_k] and its gradient (e[0], e[1..3]),
 // the gradient of I[lam_5 q_5] (e5), and I[div v] with its gradient (d).
-// Twelve sums instead of the 28 of seven separate values and gradients.
+// Eleven sums instead of the 28 of seven separate values and gradients.
 __device__ __forceinline__ void gather_adj(const StencilD& s, const double* const (&q)[6],
                                            const double* __restrict__ div, const double (&lam)[6], int n,
                                            double (&e)[4], double (&e5)[3], double (&d)[4]) {
