@@ -152,6 +152,7 @@ struct tumor_ctx {
   int* bflag;                 // per-system skip flags of the batched FP64 applies
   tumor::CoefScalars* cs;
   double* partials;
+  double* dpart;  // inner-product partials of the last pass of a Krylov apply (read by the update)
   // host side
   tumor::SolveScalars* hsv;  // kMaxSys entries
   tumor::CoefScalars* hcs;
@@ -319,6 +320,7 @@ void layout(Ctx& c, Carver& cv) {
   c.bflag = cv.take<int>(4);
   c.cs = cv.take<tumor::CoefScalars>(1);
   c.partials = cv.take<double>((size_t)tumor::kPartialsCount);
+  c.dpart = cv.take<double>((size_t)tumor::kPartialsCount);
 }
 
 size_t workspace_size(const tumor_config& cfg) {
@@ -551,7 +553,7 @@ void diff_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, double raw, double dcoe
   if (fz) {
     z.p.dotp[0] = in;
     z.p.dsv = fz->sv;
-    z.p.dpart = c.partials;
+    z.p.dpart = c.dpart;
   }
   colp<R>(c, 2, false, z);
 }
@@ -622,7 +624,7 @@ void elast_apply(Ctx& c, const cplx<R>* in, cplx<R>* out, const int* skip, const
   if (fz) {
     for (int k = 0; k < 3; ++k) zf.p.dotp[k] = in + k * S;
     zf.p.dsv = fz->sv;
-    zf.p.dpart = c.partials;
+    zf.p.dpart = c.dpart;
   }
   colp<R>(c, 2, false, zf);
 }
@@ -736,6 +738,9 @@ int pcg_iterate(Ctx& c, tumor::KrylovArgs a, Apply apply, double thr2, int limit
   a.thr2 = thr2;
   a.limit = limit;
   a.fixed = fixed ? 1 : 0;
+  a.dpart = c.dpart;
+  a.dnb = tumor::col_pass_blocks<R>(c.n, 2);
+  a.dstride = 1;
   const int kc = kcls<R>(TUMOR_K_KRYLOV64, TUMOR_K_KRYLOV32);
   const double vb = double(a.ncomp) * double(c.V) * sizeof(R);  // one Krylov vector
   timed(c, kc, (zero_x ? 3.0 : 2.0) * vb, [&] { tumor::launch_pcg_start<R>(a, zero_x, c.st); });
@@ -1018,7 +1023,7 @@ void diff_apply_b(Ctx& c, int ns, const cplx<R>* in, cplx<R>* out, double raw, d
   if (fz) {
     for (int k = 0; k < ns; ++k) zf.p.dotp[k] = in + k * S;
     zf.p.dsv = fz->sv;
-    zf.p.dpart = c.partials;
+    zf.p.dpart = c.dpart;
     zf.p.dot_nsys = ns;
   }
   colp<R>(c, 2, false, zf);
@@ -1046,6 +1051,8 @@ void pcg_iterate_b(Ctx& c, tumor::BatchArgs a, const double* thr2, const int* li
     chunk = std::max(chunk, std::min(limit[k], pred[k] + 1));
   }
   if (any_fixed) chunk = std::min(lim_max, 64);
+  a.dpart = c.dpart;
+  a.dnb = tumor::col_pass_blocks<R>(c.n, 2);
   const int kc = kcls<R>(TUMOR_K_KRYLOV64, TUMOR_K_KRYLOV32);
   const double vb = double(c.V) * sizeof(R);  // one system's Krylov vector
   const int nact = __builtin_popcount((unsigned)a.active);

@@ -9,4 +9,5 @@ template void launch_xfwd<float>(int, const XProg&, const void*, hipStream_t, bo
 template void launch_xelast<float>(int, const XElastArgs&, const void*, hipStream_t);
 template void launch_xdiff<float>(int, const XDiffArgs&, const void*, hipStream_t);
 template void launch_xforce<float>(int, const XForceArgs&, const void*, hipStream_t);
+template int col_pass_blocks<float>(int, int);
 }  // namespace tumor

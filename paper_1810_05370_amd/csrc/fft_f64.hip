@@ -9,5 +9,6 @@ template void launch_xfwd<double>(int, const XProg&, const void*, hipStream_t, b
 template void launch_xelast<double>(int, const XElastArgs&, const void*, hipStream_t);
 template void launch_xdiff<double>(int, const XDiffArgs&, const void*, hipStream_t);
 template void launch_xforce<double>(int, const XForceArgs&, const void*, hipStream_t);
+template int col_pass_blocks<double>(int, int);
 template void launch_xdot<double>(int, const XDotArgs&, const void*, hipStream_t);
 }  // namespace tumor

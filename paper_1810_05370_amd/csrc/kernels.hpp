@@ -135,6 +135,11 @@ struct KrylovArgs {
   int limit;     // iteration limit (max_it or a forced count)
   int fixed;     // 1: ignore convergence, stop at `limit`
   double scale32;  // launch_residual: r32 = float(scale32 * r), a power of two
+  // launch_pcg_update: the inner-product pass's block partials of <p, q>
+  // (dnb blocks, dstride apart); every block of the update totals them
+  // itself (same order as a one-block kernel) to get alpha = rho / <p, q>
+  const double* dpart;
+  int dnb, dstride;
 };
 
 // r = b - ax (ax nullable: r = b); bb, rr -> sv.  Optionally r32 = float(r).
@@ -146,7 +151,8 @@ void launch_cn_residual(const KrylovArgs& a, const void* c, const void* dc, hipS
 // p = M^-1 r; rho = <r, M^-1 r>; it = 0; done = 0.  zero_x: x = 0 as well.
 template <typename R>
 void launch_pcg_start(const KrylovArgs& a, int zero_x, hipStream_t st);
-// r -= alpha q, convergence test, beta.  x += alpha p is deferred: the fused
+// alpha = rho / <p, q> (from the partials at a.dpart), r -= alpha q,
+// convergence test, beta.  x += alpha p is deferred: the fused
 // p-update pass of the next iteration applies it before replacing p
 // (ZPUpdateArgs.x), and launch_pcg_xfinal after the last iteration.
 template <typename R>
@@ -175,6 +181,9 @@ struct BatchArgs {
   int limit[kMaxSys];
   int fixed[kMaxSys];
   double scale32[kMaxSys];  // launch_bresidual: r32 = float(scale32 * r)
+  // launch_bpcg_update: system k's <p, q> partials at dpart[block * kDotStride + k], dnb blocks
+  const double* dpart;
+  int dnb;
 };
 template <typename R>
 void launch_bresidual(const BatchArgs& a, void* r32, hipStream_t st);
@@ -186,8 +195,6 @@ template <typename R>
 void launch_bpcg_update(const BatchArgs& a, hipStream_t st);
 template <typename R>
 void launch_bpcg_xfinal(const BatchArgs& a, hipStream_t st);
-// alpha_k = rho_k / <p, q>_k for the systems not done (partials at stride kDotStride)
-void launch_bfin_alpha(SolveScalars* sv, int ns, const double* part, int nb, hipStream_t st);
 // flags[k] = 0 for the systems in mask, 1 for the others (k < ns)
 void launch_set_flags(int* flags, int ns, int mask, hipStream_t st);
 // x64[k] += s[k] * double(x32[k]) for the systems in mask (blocks of count values)
@@ -212,8 +219,6 @@ struct DiagArgs {
 // sqrt(h^3 sum (J-1)^2), d_max (voxels; 0 without seeds or displacement)
 void launch_diag(const DiagArgs& a, double* results, hipStream_t st);
 
-// alpha = rho / sum of nb partials of <p, q> (stride apart); nothing once done.
-void launch_fin_alpha(SolveScalars* sv, const double* part, int nb, int stride, hipStream_t st);
 
 // x64 += s * double(x32)
 void launch_add32to64(void* x64, const void* x32, double s, long long count, hipStream_t st);

@@ -51,10 +51,9 @@ struct ColProg {
   const int* oskip[kMaxCol];
   // Optional fused Krylov inner product of a forward z pass: with dsv set,
   // each block stores its partial of sum_o <dotp[o], out[o]> (Parseval-
-  // weighted) in dpart[block], and the launcher queues the one-block kernel
-  // that publishes alpha = rho / total to dsv.  With dot_nsys > 0, output o
-  // belongs to system o of a batched solve: its partial goes to
-  // dpart[block * kDotStride + o] and alpha to dsv[o].
+  // weighted) in dpart[block]; the PCG update that follows totals them
+  // (col_pass_blocks blocks).  With dot_nsys > 0, output o belongs to system
+  // o of a batched solve: its partial goes to dpart[block * kDotStride + o].
   const void* dotp[kMaxCol];
   SolveScalars* dsv;
   double* dpart;
@@ -176,5 +175,8 @@ template <typename R>
 void launch_xforce(int n, const XForceArgs& a, const void* tw, hipStream_t st);
 template <typename R>
 void launch_xdot(int n, const XDotArgs& a, const void* tw, hipStream_t st);
+// blocks of a column pass along `axis` (the count of its inner-product partials)
+template <typename R>
+int col_pass_blocks(int n, int axis);
 
 }  // namespace tumor

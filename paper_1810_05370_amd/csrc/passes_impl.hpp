@@ -795,12 +795,10 @@ void launch_col_pass_seg(int axis, bool inverse, const ColProg& prog, const cplx
   if (inverse)
     hipLaunchKernelGGL((k_col_pass<R, NN, true, false, SEG>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride,
                        astride, twp);
-  else if (prog.dsv) {
+  else if (prog.dsv)
     hipLaunchKernelGGL((k_col_pass<R, NN, false, true, SEG>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride,
                        astride, twp);
-    if (prog.dot_nsys) launch_bfin_alpha(prog.dsv, prog.dot_nsys, prog.dpart, (int)(grid.x * grid.y), st);
-    else launch_fin_alpha(prog.dsv, prog.dpart, (int)(grid.x * grid.y), 1, st);
-  } else
+  else
     hipLaunchKernelGGL((k_col_pass<R, NN, false, false, SEG>), grid, dim3(Cfg::THREADS), 0, st, prog, fstride,
                        astride, twp);
 }
@@ -812,6 +810,16 @@ void launch_col_pass(int n, int axis, bool inverse, const ColProg& prog, const v
     if (col_seg<R>(axis) == 256) launch_col_pass_seg<R, NN, 256>(axis, inverse, prog, twp, st);
     else launch_col_pass_seg<R, NN, 128>(axis, inverse, prog, twp, st);
   });
+}
+
+template <typename R>
+int col_pass_blocks(int n, int axis) {
+  int nb = 0;
+  TUMOR_DISPATCH_N(n, {
+    if (col_seg<R>(axis) == 256) nb = (int)((NN / 2) / ColCfg<NN, R, 256>::TC) * NN;
+    else nb = (int)((NN / 2) / ColCfg<NN, R, 128>::TC) * NN;
+  });
+  return nb;
 }
 
 template <typename R>

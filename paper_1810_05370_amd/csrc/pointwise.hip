@@ -861,29 +861,33 @@ __global__ void __launch_bounds__(kRedThreads) k_pcg_start(KrylovArgs a, SpecIdx
   block_store_partials<1>(acc, a.partials);
 }
 
-// alpha = rho / <p, q> from the partials of <p, q> (nb blocks, given stride).
-__global__ void __launch_bounds__(kRedThreads) k_fin_alpha(SolveScalars* sv, const double* part, int nb,
-                                                            int stride) {
-  if (sv->done) return;
+// alpha = rho / <p, q>: every block totals the inner-product pass's partials
+// itself, in the order of a one-block totalling kernel, so all blocks agree;
+// block 0 publishes it (or the breakdown) for the deferred x update.
+__device__ __forceinline__ bool pcg_alpha(SolveScalars* sv, const double* part, int nb, int stride, double& alpha) {
+  __syncthreads();  // a previous total in this block has been read (shared buffer)
   double tot[1];
   total_partials<1>(tot, part, nb, stride);
-  if (threadIdx.x == 0) {
+  const bool ok = isfinite(tot[0]) && tot[0] > 0.0;
+  alpha = ok ? sv->rho / tot[0] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     sv->pq = tot[0];
-    if (!(isfinite(tot[0]) && tot[0] > 0.0)) {
+    sv->alpha = alpha;  // 0 on breakdown: nothing left for the deferred x update to add
+    if (!ok) {
       sv->bad = 1;
       sv->done = 1;
-      sv->alpha = 0.0;  // nothing left for the deferred x update to add
-    } else {
-      sv->alpha = sv->rho / tot[0];
     }
   }
+  return ok;
 }
 
 template <typename R, int NC>
 __global__ void __launch_bounds__(kRedThreads) k_pcg_update(KrylovArgs a, SpecIdx ix) {
   if (a.sv->done) return;
+  double al;
+  if (!pcg_alpha(a.sv, a.dpart, a.dnb, a.dstride, al)) return;
   const long long S = (long long)a.n * a.n * (a.n / 2);
-  const R alpha = R(a.sv->alpha);
+  const R alpha = R(al);
   cplx<R>* r = static_cast<cplx<R>*>(a.r);
   const cplx<R>* q = static_cast<const cplx<R>*>(a.q);
   double acc[2] = {0.0, 0.0};
@@ -1007,9 +1011,6 @@ void launch_pcg_start(const KrylovArgs& a, int zero_x, hipStream_t st) {
   hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kRedThreads), 0, st, a.sv, a.partials, nb);
 }
 
-void launch_fin_alpha(SolveScalars* sv, const double* part, int nb, int stride, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kRedThreads), 0, st, sv, part, nb, stride);
-}
 
 template <typename R>
 void launch_pcg_update(const KrylovArgs& a, hipStream_t st) {
@@ -1158,25 +1159,6 @@ __global__ void __launch_bounds__(kRedThreads) k_bfin_start(SolveScalars* sv, in
   }
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_bfin_alpha(SolveScalars* sv, int ns, const double* part, int nb) {
-  for (int s = 0; s < ns; ++s) {
-    if (sv[s].done) continue;  // uniform
-    double tot[1];
-    total_partials<1>(tot, part + s, nb, kDotStride);
-    if (threadIdx.x == 0) {
-      sv[s].pq = tot[0];
-      if (!(isfinite(tot[0]) && tot[0] > 0.0)) {
-        sv[s].bad = 1;
-        sv[s].done = 1;
-        sv[s].alpha = 0.0;  // nothing left for the deferred x update to add
-      } else {
-        sv[s].alpha = sv[s].rho / tot[0];
-      }
-    }
-    __syncthreads();  // every thread has read sv[s].done before thread 0 may change it
-  }
-}
-
 template <typename R>
 __global__ void __launch_bounds__(kRedThreads) k_bpcg_update(BatchArgs a, SpecIdx ix) {
   const long long S = (long long)a.n * a.n * (a.n / 2);
@@ -1187,8 +1169,10 @@ __global__ void __launch_bounds__(kRedThreads) k_bpcg_update(BatchArgs a, SpecId
   bool any = false;
 #pragma unroll
   for (int s = 0; s < kMaxSys; ++s) {
-    run[s] = s < a.ns && !a.sv[s].done;
-    alpha[s] = run[s] ? R(a.sv[s].alpha) : R(0);
+    run[s] = s < a.ns && !a.sv[s].done;  // block-uniform
+    double al = 0.0;
+    if (run[s]) run[s] = pcg_alpha(a.sv + s, a.dpart + s, a.dnb, kDotStride, al);
+    alpha[s] = R(al);
     any = any || run[s];
   }
   if (!any) return;
@@ -1304,9 +1288,6 @@ void launch_bpcg_start(const BatchArgs& a, int zero_x, hipStream_t st) {
   hipLaunchKernelGGL(k_bfin_start, dim3(1), dim3(kRedThreads), 0, st, a.sv, a.ns, a.active, a.partials, nb);
 }
 
-void launch_bfin_alpha(SolveScalars* sv, int ns, const double* part, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_bfin_alpha, dim3(1), dim3(kRedThreads), 0, st, sv, ns, part, nb);
-}
 
 template <typename R>
 void launch_bpcg_update(const BatchArgs& a, hipStream_t st) {
