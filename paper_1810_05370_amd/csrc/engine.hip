@@ -2718,7 +2718,9 @@ int tumor_save_state(tumor_ctx* ctx, void* dst, size_t bytes) {
   if (bytes < kSnapHeader + slot_bytes(ctx->V)) return einval("snapshot buffer smaller than tumor_state_bytes");
   if (reinterpret_cast<uintptr_t>(dst) & 7u) return einval("dst must be 8-byte aligned");
   return guarded([&]() -> int {
-    long long hdr[4] = {kSnapMagic, ctx->n, 14, 0};
+    // the whole header is written (zeros after the four fields), so equal
+    // states give byte-identical snapshots
+    long long hdr[kSnapHeader / sizeof(long long)] = {kSnapMagic, ctx->n, 14, 0};
     HIPCHECK(hipMemcpyAsync(dst, hdr, sizeof(hdr), hipMemcpyHostToDevice, ctx->st));
     save_state(*ctx, reinterpret_cast<double*>(static_cast<char*>(dst) + kSnapHeader));
     HIPCHECK(hipGetLastError());

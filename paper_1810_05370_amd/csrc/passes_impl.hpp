@@ -59,14 +59,15 @@ __device__ __forceinline__ int xwave(int k) {  // x wave number of packed index 
 }
 
 // Block sum of v stored as this block's partial of an inner product (plain
-// store; launch_fin_alpha, queued right after the pass, totals the partials).
+// store in slot blk, by default the workgroup's linear index; the PCG update
+// that follows the pass totals the partials).
 __device__ __forceinline__ double wave_sum_f(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-__device__ void store_dot_partial(double v, double* part, int stride = 1, int slot = 0) {
+__device__ void store_dot_partial(double v, double* part, int stride = 1, int slot = 0, long long blk = -1) {
   __shared__ double sh[16];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   v = wave_sum_f(v);
@@ -76,7 +77,8 @@ __device__ void store_dot_partial(double v, double* part, int stride = 1, int sl
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += sh[w];
-    part[(long long)(blockIdx.y * gridDim.x + blockIdx.x) * stride + slot] = s;
+    if (blk < 0) blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    part[blk * stride + slot] = s;
   }
 }
 
@@ -96,7 +98,18 @@ __global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(
   const int tid = threadIdx.x;
   const int col = tid % TC;
   const int t = tid / TC;
-  const long long base = (long long)blockIdx.y * fstride + (long long)blockIdx.x * TC + col;
+  // XCD-aware tile order of y passes.  Workgroups go round-robin to the 8
+  // XCDs; the tiles are permuted so that each XCD takes whole z planes (all
+  // column tiles of a plane, one after another), and its L2 and address
+  // translation see an eighth of the pages.  (z passes read every plane in
+  // each tile, where the order makes no difference.)
+  const int gx = gridDim.x;
+  const bool ypass = astride < fstride && (gridDim.y & 7u) == 0;
+  const int lin = blockIdx.y * gx + blockIdx.x;
+  const int bx = ypass ? (lin >> 3) % gx : (int)blockIdx.x;
+  const int by = ypass ? ((lin >> 3) / gx) * 8 + (lin & 7) : (int)blockIdx.y;
+  const long long blk = (long long)by * gx + bx;  // the tile's inner-product slot
+  const long long base = (long long)by * fstride + (long long)bx * TC + col;
   const LdsView<R> lds{sbuf + col, TC, 1};
   double dotacc = 0.0;
   // Software pipelining: the input column of the next FFT job is loaded into
@@ -208,8 +221,8 @@ __global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(
       for (int j = 0; j < 8; ++j) dotacc += (double)pdot[j].x * (double)acc[j].x + (double)pdot[j].y * (double)acc[j].y;
       if (prog.dot_nsys) {
         // output o is system o's direction: its own partial
-        const int kxp = blockIdx.x * TC + col;
-        store_dot_partial(dotacc * ((kxp == 0) ? 1.0 : 2.0), prog.dpart, kDotStride, o);
+        const int kxp = bx * TC + col;
+        store_dot_partial(dotacc * ((kxp == 0) ? 1.0 : 2.0), prog.dpart, kDotStride, o, blk);
         dotacc = 0.0;
       }
     }
@@ -219,9 +232,9 @@ __global__ void __launch_bounds__((ColCfg<N, R, SEG>::THREADS), ((DOT && sizeof(
                   "the inner-product partials of every block must fit the partials buffer");
     if (!prog.dot_nsys) {
       // Parseval weight: the packed kx = 0 column counts once, the others twice
-      const int kxp = blockIdx.x * TC + col;
+      const int kxp = bx * TC + col;
       dotacc *= (kxp == 0) ? 1.0 : 2.0;
-      store_dot_partial(dotacc, prog.dpart);
+      store_dot_partial(dotacc, prog.dpart, 1, 0, blk);
     }
   }
 }
@@ -487,12 +500,18 @@ __device__ __forceinline__ cplx<R> iwx(cplx<R> a, int k) {
   const cplx<R>* tw = stw;                                           \
   const int t = threadIdx.x % TP;                                    \
   const int rl = threadIdx.x / TP;                                   \
-  const long long row = (long long)blockIdx.x * RC::RW + rl;         \
+  const long long row = row_tile() * RC::RW + rl;         \
   const LdsRowView<R> lds{sbuf + rl * LPR};                         \
   const long long soff = row * L;                                    \
   const long long poff = row * N;                                    \
   (void)soff;                                                        \
   (void)poff;
+
+// Row tiles are taken in reverse order: the y pass before an x pass writes
+// the z planes in increasing order, so the rows it wrote last, still in the
+// last-level cache, are read first; and the y pass after it reads first the
+// rows written last.
+__device__ __forceinline__ long long row_tile() { return (long long)gridDim.x - 1 - blockIdx.x; }
 
 // ------------------------------------------------------------- x kernels
 template <typename R, int N>
@@ -501,7 +520,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xinv(XProg prog, const c
   TUMOR_ROW_SETUP(N)
   const R scale = R(prog.scale);
   // block-uniform bases and a 32-bit lane offset, as in k_xelast
-  const long long bs = (long long)blockIdx.x * RC::RW * L;
+  const long long bs = row_tile() * RC::RW * L;
   const int ro = rl * L;
   for (int o = 0; o < prog.nout; ++o) {
     cplx<R> v[8];
@@ -560,7 +579,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS, (sizeof(R) == 4 ? 3 : 2))
   // Rows are addressed as a block-uniform base plus a 32-bit lane offset ro
   // (the physical coefficient rows hold N reals = L complex pairs), which
   // keeps 64-bit per-lane addresses out of the registers.
-  const long long bs = (long long)blockIdx.x * RC::RW * L;
+  const long long bs = row_tile() * RC::RW * L;
   const int ro = rl * L;
   const cplx<R>* in[8];
 #pragma unroll
@@ -673,7 +692,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdiff(XDiffArgs a, const
   TUMOR_ROW_SETUP(N)
   const R invV = R(1.0) / (R(N) * R(N) * R(N));
   // block-uniform bases and a 32-bit lane offset, as in k_xelast
-  const long long bs = (long long)blockIdx.x * RC::RW * L;
+  const long long bs = row_tile() * RC::RW * L;
   const int ro = rl * L;
   const cplx<R>* K = static_cast<const cplx<R>*>(a.K) + bs;
   // K / N^3 for this row, loaded once for the fields and directions
@@ -736,7 +755,7 @@ template <typename R, int N>
 __global__ void __launch_bounds__(RowCfg<N>::THREADS) k_xdot(XDotArgs a, const cplx<R>* __restrict__ twg) {
   TUMOR_ROW_SETUP(N)
   // block-uniform bases and a 32-bit lane offset, as in k_xelast
-  const long long bs = (long long)blockIdx.x * RC::RW * L;
+  const long long bs = row_tile() * RC::RW * L;
   const int ro = rl * L;
   for (int o = 0; o < a.nout; ++o) {
     cplx<R> sum[8];
