@@ -20,9 +20,11 @@ static_assert(kPartialsCount >= kRedBlocksMax * kPartialsPerBlock, "partials buf
 // Independent systems of a batched solve (the CN solves of i, o and l).
 constexpr int kMaxSys = 3;
 
-// Device scalars of one PCG solve.  Written by a one-block totalling kernel
-// (k_fin_*) from the reduction kernels' per-block partials, read by the
-// following kernels and by the host.
+// Device scalars of one PCG solve.  Written by one-block totalling kernels
+// (k_fin_*) from the reduction kernels' per-block partials, except pq and
+// alpha: every block of the PCG update totals the inner-product partials of
+// the pass before it itself, and block 0 stores them.  Read by the following
+// kernels and by the host.
 struct SolveScalars {
   double bb;      // ||b||^2 (spectral, Parseval-weighted)
   double rr;      // ||r||^2 of the current residual
