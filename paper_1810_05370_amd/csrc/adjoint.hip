@@ -754,29 +754,45 @@ __global__ void __launch_bounds__(kSlAdjThreads) k_sl_adj(SLAdjArgs a, const Gra
 }
 
 // ------------------------------------------------------ initial condition
-// part[k * nb + block] = sum over the block's voxels of phi_k * lam_p.
+// part[k * nb + block] = sum over the block's voxels of phi_k * lam_p, for
+// the kIcGroup seeds k of grid row blockIdx.y: lam_p is read once per group
+// of seeds, and each seed's sum runs in the same order as alone.
+constexpr int kIcGroup = 16;
 __global__ void __launch_bounds__(256) k_ic_adj(int n, const double* ic, int n_ic, const double* lam_p,
                                                 double* part) {
   const long long V = (long long)n * n * n;
-  const int k = blockIdx.y;
+  const int k0 = blockIdx.y * kIcGroup;
+  const int ng = min(kIcGroup, n_ic - k0);  // block-uniform
   const double h = 2.0 * M_PI / n, twopi = 2.0 * M_PI;
-  const double* c = ic + 5 * k;
-  double acc = 0.0;
+  double acc[kIcGroup];
+#pragma unroll
+  for (int g = 0; g < kIcGroup; ++g) acc[g] = 0.0;
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < V;
        v += (long long)gridDim.x * blockDim.x) {
     const int jx = (int)(v % n), jy = (int)((v / n) % n), jz = (int)(v / ((long long)n * n));
-    double dx = h * jx - c[0], dy = h * jy - c[1], dz = h * jz - c[2];
-    dx -= twopi * rint(dx / twopi);
-    dy -= twopi * rint(dy / twopi);
-    dz -= twopi * rint(dz / twopi);
-    const double d2 = dz * dz + dy * dy + dx * dx;
-    acc += exp(-d2 / (2.0 * c[3] * c[3])) * lam_p[v];
+    const double lp = lam_p[v];
+#pragma unroll
+    for (int g = 0; g < kIcGroup; ++g) {
+      if (g < ng) {
+        const double* c = ic + 5 * (k0 + g);
+        double dx = h * jx - c[0], dy = h * jy - c[1], dz = h * jz - c[2];
+        dx -= twopi * rint(dx / twopi);
+        dy -= twopi * rint(dy / twopi);
+        dz -= twopi * rint(dz / twopi);
+        const double d2 = dz * dz + dy * dy + dx * dx;
+        acc[g] += exp(-d2 / (2.0 * c[3] * c[3])) * lp;
+      }
+    }
   }
-  __shared__ double sh[4];
-  const double s = wave_sum_d(acc);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __shared__ double sh[kIcGroup][4];
+#pragma unroll
+  for (int g = 0; g < kIcGroup; ++g) {
+    const double s = wave_sum_d(acc[g]);
+    if ((threadIdx.x & 63) == 0) sh[g][threadIdx.x >> 6] = s;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) part[(long long)k * gridDim.x + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+  const int g = threadIdx.x;
+  if (g < ng) part[(long long)(k0 + g) * gridDim.x + blockIdx.x] = sh[g][0] + sh[g][1] + sh[g][2] + sh[g][3];
 }
 
 __global__ void k_ic_adj_sum(const double* part, int nb, int n_ic, double* out) {
@@ -830,7 +846,8 @@ void launch_ic_adj(int n, const double* ic, int n_ic, const double* lam_p, doubl
                    hipStream_t st) {
   if (n_ic <= 0) return;
   const int nb = ic_adj_blocks(n);
-  hipLaunchKernelGGL(k_ic_adj, dim3(nb, n_ic), dim3(256), 0, st, n, ic, n_ic, lam_p, part);
+  hipLaunchKernelGGL(k_ic_adj, dim3(nb, (n_ic + kIcGroup - 1) / kIcGroup), dim3(256), 0, st, n, ic, n_ic, lam_p,
+                     part);
   hipLaunchKernelGGL(k_ic_adj_sum, dim3((n_ic + 63) / 64), dim3(64), 0, st, part, nb, n_ic, out);
 }
 
