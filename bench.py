@@ -125,6 +125,15 @@ def run_form(tm, torch, inp, P, precision, steps, warmup, window, keep_fields=Fa
     nsub, sub = sim.substep_timer_read()
     sim.substep_timer(False)
     substeps = {k: round(v / max(nsub, 1), 3) for k, v in sub.items()}
+    # algorithmic bytes of the timed steps: the same runs again (bit-exact from
+    # the snapshot, so the same iterations) with every kernel class counting;
+    # the timed region above ran with one class only
+    for c in CLASSES:
+        sim.kernel_timer(c, True)
+    timed_cycles(torch, sim, snap, steps, span)
+    step_bytes = sum(sim.kernel_timer_read(c)["bytes"] for c in CLASSES) / max(steps, 1)
+    for c in CLASSES:
+        sim.kernel_timer(c, False)
     log(f"[{precision}] {steps} steps in runs {cycle_plan(steps, span)}: events {gpu_ms / 1e3:.3f} s, wall {wall:.3f} s;"
         f" dominant {dominant}: {dom['launches']} launches, {dom['ms']:.1f} ms")
     # mass-effect diagnostics (scalars) of the displacement the timed runs ended with
@@ -139,7 +148,18 @@ def run_form(tm, torch, inp, P, precision, steps, warmup, window, keep_fields=Fa
     fields = window_end_fields(sim, snap, span) if keep_fields else None
     sim.close()
     return dict(wall=wall, gpu_ms=gpu_ms, stats=stats, warm_profile=prof, dominant=dominant, dom=dom,
-                diag=diag, diag_ms=diag_ms, fields=fields, substeps=substeps)
+                diag=diag, diag_ms=diag_ms, fields=fields, substeps=substeps, step_bytes=step_bytes)
+
+
+def step_roofline(run, steps):
+    """Per-step roofline: the algorithmic bytes of the timed steps (every
+    kernel class) over their event-timed duration, against the 8 TB/s peak."""
+    ms = run["gpu_ms"] / steps
+    gbs = run["step_bytes"] / (ms / 1e3) / 1e9
+    return dict(bytes_per_step=round(run["step_bytes"]), ms_per_step=round(ms, 3), achieved=round(gbs, 1),
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+                note="bytes: each kernel's input and output arrays once per launch, summed over every kernel "
+                     "class; device-to-device state copies and fills are not counted")
 
 
 def run_single(tm, torch, inp, P, precision, steps, warmup, window, model="single", flags=None):
@@ -532,8 +552,12 @@ def main():
         extra["fp64_steps_per_s"] = round(v64, 4)
         extra["mixed_speedup_over_fp64"] = round(value / v64, 3)
         extra["fp64_roofline"] = roofline(fp64_run["dom"], fp64_run["dominant"], n)
+        extra["fp64_step_roofline"] = step_roofline(fp64_run, args.steps)
         extra["fp64_substep_ms_per_step"] = fp64_run["substeps"]
     extra["substep_ms_per_step"] = main_run["substeps"]
+    extra["step_roofline"] = step_roofline(main_run, args.steps)
+    extra["step_roofline"]["frac_of_copy_ceiling"] = round(
+        extra["step_roofline"]["achieved"] / extra["copy_ceiling"]["gbs"], 4)
     if compare:
         # error of the mixed form against the FP64 form (itself held to the FP64
         # oracle at 1e-10 by the parity tests), after every step from t = 0 to the

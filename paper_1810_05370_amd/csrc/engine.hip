@@ -858,7 +858,8 @@ SolveOut solve_system(Ctx& c, int ncomp, int kind, double h, cplx<double>* x, cp
       so.conv = false;
       break;
     }
-    tumor::launch_add32to64(x, P.x, 1.0 / sc, cnt, c.st);
+    // x64 += x32 / sc: read x64 and x32, write x64
+    timed(c, TUMOR_K_KRYLOV64, 20.0 * cnt, [&] { tumor::launch_add32to64(x, P.x, 1.0 / sc, cnt, c.st); });
     // r64 = b - A64 x64
     A64(x, c.p64.q, nullptr);
     tumor::KrylovArgs ar = a;
@@ -1246,7 +1247,8 @@ void cn_solve_b(Ctx& c, int ns, const double* const* src, double* const* dst, co
       int add = 0;
       for (int k = 0; k < ns; ++k)
         if ((active & (1 << k)) && !so[k].bad) add |= 1 << k;
-      tumor::launch_badd32to64(x, Q.x, inv_sc, ns, add, cnt, c.st);
+      timed_b(c, TUMOR_K_KRYLOV64, 20.0 * cnt * __builtin_popcount((unsigned)add), 0.0,
+              [&] { tumor::launch_badd32to64(x, Q.x, inv_sc, ns, add, cnt, c.st); });
       // r64 = b - A64 x64 for the systems that added a correction
       if (add) {
         apply64(add, x, P.q, 1.0, -h);
