@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) k_react_adj(ReactAdjArgs a) {
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.V;
        v += (long long)gridDim.x * blockDim.x) {
     const double dt = rc.dt, eps = rc.eps;
-    const double p = a.p_dag[v], idag = a.i_dag[v], i = a.i_dd[v], n = a.n_dag[v], g = a.g_dag[v],
+    const double p = a.p_dag[v], idag = a.i_dag[v], i = a.i_dd[v], g = a.g_dag[v],
                  w = a.w_dag[v], o = a.o_dag[v];
     const double i1 = a.i1[v], g1 = a.g1[v], w1 = a.w1[v];
     const double rho_p = a.rho_w * a.w0[v] + a.rho_g * a.g0[v];

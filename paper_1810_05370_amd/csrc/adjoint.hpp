@@ -20,7 +20,7 @@ struct GradScalars {
 
 struct ReactAdjArgs {
   // forward values of the step
-  const double *p_dag, *i_dag, *i_dd, *n_dag, *g_dag, *w_dag, *o_dag;  // reaction inputs
+  const double *p_dag, *i_dag, *i_dd, *g_dag, *w_dag, *o_dag;  // reaction inputs (no derivative of the reaction needs n)
   const double *i1, *g1, *w1;                                         // reaction outputs used by O2/edema
   const double *w0, *g0;                                              // step-start tissue (rho_p)
   double rho_w, rho_g;

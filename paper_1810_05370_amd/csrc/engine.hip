@@ -1910,7 +1910,6 @@ void adjoint_core(Ctx& c, const double* x0, double* adj, int m, double* grad) {
     ra.p_dag = c.G[P];
     ra.i_dag = c.G[I];
     ra.i_dd = c.Rdd[0];
-    ra.n_dag = c.G[N];
     ra.g_dag = c.G[G];
     ra.w_dag = c.G[W];
     ra.o_dag = c.Rdd[1];
